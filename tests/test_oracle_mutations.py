@@ -1,0 +1,69 @@
+"""Sensitivity of the oracle's pins: plant a plausible mistake in a copy of the oracle (on the CPU), build
+it, and check that the fast pin suite fails.  About 90 s; opt in with LBM_MUTATION_CHECK=1.
+
+One reading is known to be unpinned: whether B(c) in the bracket of Eq. (18) takes c at time n or at
+n + 1/2 (the paper prints n + 1/2, which the oracle follows).  The difference is second order in the
+departure from equilibrium and vanishes at equilibrium, so no closed form or printed value separates
+the two.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
+PINS = ["tests/test_oracle_thermo.py", "tests/test_oracle_stencils.py", "tests/test_oracle_lb.py",
+        "tests/test_oracle_fd.py", "tests/test_oracle_equilibrium.py"]
+
+MUTATIONS = [
+    ("equilibrium without the 1/2", "4.5 * eu * eu", "9.0 * eu * eu"),
+    ("forcing sign", "(exd - ux[k])", "(exd + ux[k])"),
+    ("velocity without half force", "(mx + 0.5 * Fx[k])", "(mx + Fx[k])"),
+    ("force: sign of grad c", "-(phi[k] * gmx[k]) - gcx[k]", "-(phi[k] * gmx[k]) + gcx[k]"),
+    ("force: sign of c grad X", "- c[k] * gXx[k]", "+ c[k] * gXx[k]"),
+    ("force: sign of phi grad mu", "(-(phi[k] * gmy[k])", "((phi[k] * gmy[k])"),
+    ("upwind side reversed", "ux[k] > 0.0 ? gc - g[kW] : g[kE] - gc", "ux[k] > 0.0 ? g[kE] - gc : gc - g[kW]"),
+    ("centred divergence sign", "0.5 * (ux[kE] - ux[kW])", "0.5 * (ux[kW] - ux[kE])"),
+    ("cubic term at the half step", "p->b * (pn * pn * pn)", "p->b * (ph[k] * ph[k] * ph[k])"),
+    ("gradient axes mixed", "gy[k] = (4.0 * (N - S)", "gy[k] = (4.0 * (E - Wv)"),
+    ("Laplacian centre weight", "- 20.0 * g[k]", "- 16.0 * g[k]"),
+    ("streaming reversed", "idx(p, x + EX[i], y + EY[i])] = fstar", "idx(p, x - EX[i], y - EY[i])] = fstar"),
+    ("source disk radius", "<= d->Rs * d->Rs", "< d->Rs * d->Rs * 0.5"),
+    ("consumption sign", "- p->gamma * (ch[k] - p->c0)", "+ p->gamma * (ch[k] - p->c0)"),
+    ("link mobility from one end", "(kc + kf[ki])", "(2.0 * kc)"),
+    ("sign of X in mu_c", "    X[k] = halfB1 *", "    X[k] = -halfB1 *"),
+    ("B1 dropped from B(c) in mu", "double B = p->B0 + p->B1 * c[k];", "double B = p->B0;"),
+    ("B1 dropped from B(c) in M", "double Bh = p->B0 + p->B1 * ch[k];", "double Bh = p->B0;"),
+    ("mu: sign of grad phi . grad c", "- p->B1 * (gpx[k] * gcx[k] + gpy[k] * gcy[k])",
+     "+ p->B1 * (gpx[k] * gcx[k] + gpy[k] * gcy[k])"),
+    ("M: sign of grad c . grad phi", "- p->B1 * (gchx[k] * gphx[k] + gchy[k] * gphy[k])",
+     "+ p->B1 * (gchx[k] * gphx[k] + gchy[k] * gphy[k])"),
+    ("mobility Gamma ignored", "ph[k] + p->Gamma * lM[k]", "ph[k] + lM[k]"),
+    ("surfactant diffusion dropped", "(ch[k] + p->D * lch[k])", "(ch[k])"),
+    ("ramp not clipped at t*", "(tn < p->t_star ? tn : p->t_star)", "(tn)"),
+    ("momentum from the wrong diagonals", "double my = (fi[2] + (fi[5] + fi[6])) - (fi[4] + (fi[7] + fi[8]));",
+     "double my = (fi[2] + (fi[5] + fi[8])) - (fi[4] + (fi[7] + fi[6]));"),
+    ("centre of mass unweighted", "sx[k] += v * dx;", "sx[k] += dx;"),
+    ("relaxation rate", "double omega = 1.0 / p->tau;", "double omega = 1.0 / (p->tau + 0.1);"),
+]
+
+
+@pytest.mark.skipif(os.environ.get("LBM_MUTATION_CHECK") != "1", reason="set LBM_MUTATION_CHECK=1 (about 90 s)")
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site not found: {name}"
+    with tempfile.TemporaryDirectory() as d:
+        c_file = os.path.join(d, "mutant.c")
+        lib = os.path.join(d, "libmutant.so")
+        with open(c_file, "w") as fh:
+            fh.write(src.replace(old, new))
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-o", lib,
+                        c_file, "-lm"], check=True)
+        env = dict(os.environ, LBM_ORACLE_LIB=lib, LBM_MUTATION_CHECK="0")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-m", "not slow", "-p", "no:cacheprovider"]
+                           + PINS, cwd=ROOT, env=env, capture_output=True, text=True)
+        assert r.returncode != 0, f"the pins did not notice: {name}"
