@@ -1,0 +1,176 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) hybrid lattice-Boltzmann / finite-difference
+ * solver for chemically driven self-propelled droplets.
+ *
+ * Model: Fadda, Gonnella, Lamura, Tiribocchi, "Lattice Boltzmann study of
+ * chemically-driven self-propelled droplets", EPJ E (2017), arXiv:1711.10984.
+ *   - order parameter phi and surfactant c obey convection-diffusion equations
+ *     with chemical potentials from the free energy            (Sec. 2.1, Eqs. 1-5)
+ *   - the fluid obeys Navier-Stokes + continuity through a D2Q9 BGK lattice
+ *     Boltzmann scheme with a forcing term                     (Sec. 2.2, Eqs. 10-15)
+ *   - phi and c are advanced by a two-step explicit finite-difference scheme
+ *                                                              (Sec. 2.3, Eqs. 16-19)
+ *   - surfactant production A(t) Theta(R_s - |r - r_P|) inside each active
+ *     droplet and consumption -gamma (c - c0)                  (Sec. 2.1, Sec. 4)
+ *   - droplet centres of mass over phi >= 0                    (Sec. 4)
+ * All quantities are in lattice units (Delta x = Delta t = 1).  The lattice is periodic.
+ *
+ * Conventions shared by every entry point
+ *   Host field arrays are row-major [ny][nx] doubles, x fastest.  Populations are
+ *   [9][ny][nx] in the D2Q9 order rest, E(+x), N(+y), W(-x), S(-y), NE, NW, SW, SE.
+ *   Batched contexts hold several independent lattices ("instances"); host arrays for
+ *   a batch are the instances' arrays concatenated in instance order.
+ *   Device memory belongs to the caller: the library carves all its buffers out of one
+ *   caller-allocated workspace and never allocates or frees device memory itself
+ *   (hipGraph objects and hipEvents are the only HIP objects it creates).  The HIP
+ *   stream also belongs to the caller; all work is enqueued on it.  Host arrays belong
+ *   to the caller and are only read or written during the call.
+ *   Every function returns LBM_OK (0) or a negative error code; nothing is thrown across
+ *   the ABI.  lbm_last_error() returns a thread-local description of the last failure.
+ *   lbm_step() does not synchronise; device-side problems (non-finite values, B(c) <= 0)
+ *   are reported by the next lbm_observables() call.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_E_INVAL -1    /* invalid argument or configuration */
+#define LBM_E_NOMEM -2    /* workspace too small */
+#define LBM_E_HIP -3      /* a HIP runtime call failed */
+#define LBM_E_UNSTABLE -4 /* non-finite state or B(c) <= 0 somewhere (Sec. 4: B(c) > 0 is required) */
+#define LBM_E_STATE -5    /* call not valid in the current state */
+
+#define LBM_FP64 0 /* populations, fields and arithmetic in FP64 */
+#define LBM_FP32 1 /* populations, fields and arithmetic in FP32; droplet sums in FP64 */
+
+#define LBM_ADV_PAPER 0 /* advection half-step of Eqs. (16)-(17) as printed */
+#define LBM_ADV_FLUX 1  /* conservative face-upwind flux form of the same half-step */
+
+#define LBM_MAXDROP 256 /* droplets per instance */
+#define LBM_NSTAGE 22   /* planes written by lbm_debug_stage */
+
+/* Per-instance model parameters (lattice units). */
+typedef struct lbm_config {
+  int32_t nx, ny;     /* periodic lattice, nx, ny >= 3 */
+  int32_t precision;  /* LBM_FP64 or LBM_FP32; equal for every instance of a batch */
+  int32_t advection;  /* LBM_ADV_PAPER or LBM_ADV_FLUX */
+  double tau;         /* BGK relaxation time, > 1/2; viscosity (tau - 1/2)/3 (Eq. 15) */
+  double n0;          /* initial fluid density (populations w_i n0 when none are given) */
+  double a, b;        /* bulk free energy a phi^2/2 + b phi^4/4, b > 0 (Eq. 1) */
+  double B0, B1;      /* gradient coupling B(c) = B0 + B1 c (Eq. 1) */
+  double D;           /* surfactant mobility L(c) = D c (Eq. 4) */
+  double Gamma;       /* mobility of phi multiplying the Laplacian in Eq. (18) (1 in the paper) */
+  double gamma;       /* consumption rate (Sec. 2.1) */
+  double A0;          /* production ramp A(n) = A0 min(n, t_star) (Sec. 4) */
+  double t_star;
+  double c0;          /* consumption floor c0 (Sec. 2.1) */
+} lbm_config;
+
+/* One droplet: tracked centre of mass, radius, production disk (Sec. 2.1, Sec. 4). */
+typedef struct lbm_droplet {
+  double x, y;   /* centre of mass r_CM; at init the centre the first CM pass starts from */
+  double R, Rs;  /* droplet radius and production-disk radius */
+  double ex, ey; /* unit vector: production disk centred at r_P = r_CM + (R - Rs) e */
+  int32_t active; /* 1: produces surfactant; 0: passive (tracked only) */
+  int32_t reserved;
+} lbm_droplet;
+
+/* Conserved sums and stability diagnostics of one instance at the current step. */
+typedef struct lbm_obs {
+  int64_t step;      /* n */
+  double mass;       /* sum_r sum_i f_i (Eq. 11) */
+  double sum_phi;    /* sum_r phi */
+  double sum_c;      /* sum_r c */
+  double min_B;      /* min_r B0 + B1 c (must stay > 0, Sec. 4) */
+  double max_u;      /* max_r |u| */
+  int32_t nonfinite; /* 1 if any population, phi or c is not finite */
+  int32_t ndrop;
+} lbm_obs;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of device workspace a batch of `ninst` instances needs.  cfgs[ninst], ndrop[ninst]. */
+int lbm_workspace_bytes(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, size_t* bytes);
+
+/* Create a batch and set its state at step `step` (Sec. 2).
+ *   workspace: device pointer, >= lbm_workspace_bytes(), 256-byte aligned, owned by the caller and
+ *              used exclusively by this context until lbm_destroy().
+ *   stream:    hipStream_t owned by the caller (a non-default stream enables graph replay).
+ *   phi0, c0:  host, concatenated [ny][nx] per instance.
+ *   f_pre:     host, concatenated [9][ny][nx] pre-collision populations, or NULL for w_i n0.
+ *   drops:     host, concatenated droplet tables (ndrop[i] each).  Initial centres of mass are one
+ *              centre-of-mass pass over phi0 started from the given (x, y).
+ * Errors: LBM_E_INVAL (nx, ny < 3, tau <= 1/2, b <= 0, mixed precision, too many droplets,
+ * misaligned workspace), LBM_E_NOMEM (workspace too small), LBM_E_HIP. */
+int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_t workspace_bytes,
+                   void* stream, const double* phi0, const double* c0, const double* f_pre,
+                   const int32_t* ndrop, const lbm_droplet* drops, int64_t step, lbm_ctx** out);
+
+/* Single-instance form of lbm_init_batch. */
+int lbm_init(const lbm_config* cfg, void* workspace, size_t workspace_bytes, void* stream,
+             const double* phi0, const double* c0, const double* f_pre, int32_t ndrop,
+             const lbm_droplet* drops, int64_t step, lbm_ctx** out);
+
+/* Advance every instance by n >= 0 timesteps n -> n+1 (Sec. 2.2-2.3, Eqs. 10-19, then the
+ * centre-of-mass update of Sec. 4).  Asynchronous on the context's stream. */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Replay the timestep through hipGraphs of `steps_per_graph` steps (even, >= 2), or launch kernels
+ * one by one when 0.  Default: 20 on a non-default stream, 0 on the null stream. */
+int lbm_set_graph(lbm_ctx* ctx, int32_t steps_per_graph);
+
+/* Wait for the context's stream. */
+int lbm_sync(lbm_ctx* ctx);
+
+/* Current step counter n. */
+int64_t lbm_get_step(const lbm_ctx* ctx);
+
+/* Copy instance `inst` to host arrays (any may be NULL): pre-collision populations f_pre
+ * [9][ny][nx] at time n, phi, c, and the density and velocity of Eq. (11) at time n (with half
+ * the force of Eq. 14 computed from the current phi, c).  Synchronous. */
+int lbm_fields(lbm_ctx* ctx, int32_t inst, double* f_pre, double* phi, double* c, double* n, double* ux,
+               double* uy);
+
+/* Observables of instance `inst` at the current step.  drop_out (may be NULL): per droplet
+ * {x_cm, y_cm, vx, vy, sum_phi}, the velocity being the phi-weighted mean of u over the
+ * droplet's nodes (phi >= 0, nearest centre).  Synchronous.  Returns LBM_E_UNSTABLE (after
+ * filling *obs) if a value is non-finite or B(c) <= 0. */
+int lbm_observables(lbm_ctx* ctx, int32_t inst, lbm_obs* obs, double* drop_out);
+
+/* Current droplet table of instance `inst` (ndrop entries).  Synchronous. */
+int lbm_droplets(lbm_ctx* ctx, int32_t inst, lbm_droplet* out);
+
+/* Test hook: the intermediate planes of the next step of instance `inst` as computed by the
+ * production kernels, without advancing the state.  out: host [LBM_NSTAGE][ny][nx] doubles in
+ * the order mu_phi, X = (B1/2)|grad phi|^2, Fx, Fy, n, ux, uy, phi^{n+1/2}, c^{n+1/2}, M
+ * (bracket of Eq. 18), X^{n+1/2}, phi^{n+1}, c^{n+1}, f*_0..8 (post-collision, before
+ * streaming).  Instances of at most 512 x 512 nodes (LBM_E_INVAL otherwise).  Synchronous. */
+int lbm_debug_stage(lbm_ctx* ctx, int32_t inst, double* out);
+
+/* Average device time per launch (ms) of each kernel of the timestep over n eagerly launched
+ * steps, measured with hipEvents on the context's stream.  ms_out[0] = lattice-Boltzmann kernel,
+ * ms_out[1] = finite-difference kernel, ms_out[2] = centre-of-mass reduction.  Advances the state
+ * by n steps.  Synchronous. */
+int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
+
+/* Kernel names for ms_out entries of lbm_time_kernels (static strings). */
+const char* lbm_kernel_name(int32_t which);
+
+/* Release the context (graphs, events, host bookkeeping).  The workspace is not freed. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Description of the last error on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,666 @@
+// Host side of the C ABI declared in include/lbm.h: workspace layout, validation, state transfer,
+// launch sequencing (eager or hipGraph replay), observables and the stage-export test hook.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(LBM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+// lbm_debug_stage exports planes only for instances up to this many nodes (its scratch is sized by it).
+constexpr int64_t DEBUG_MAX_NODES = 512 * 512;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// D2Q9 directions in the public order rest, E, N, W, S, NE, NW, SW, SE.
+constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr double WGT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// Workspace layout of a batch: one typed pool for all fields, then bookkeeping arrays.
+struct Layout {
+  int prec = 0;
+  size_t elem = 8;
+  std::vector<InstDev> inst;
+  std::vector<TileDev> tiles;  // launch order (XCD-aware), padded with inst = -1
+  int ntiles = 0, ndrop_total = 0, max_nd = 0, obs_stride = 0;
+  int64_t max_nodes = 0;
+  size_t off_pool = 0, off_inst = 0, off_tiles = 0, off_drops = 0, off_part = 0, off_mask = 0,
+         off_step = 0, off_obs = 0, off_dbg = 0, total = 0;
+};
+
+int validate(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop) {
+  if (ninst <= 0 || !cfgs || !ndrop) return fail(LBM_E_INVAL, "ninst must be > 0 with configs and droplet counts");
+  for (int i = 0; i < ninst; ++i) {
+    const lbm_config& c = cfgs[i];
+    char where[64];
+    snprintf(where, sizeof where, "instance %d: ", i);
+    if (c.nx < 3 || c.ny < 3) return fail(LBM_E_INVAL, std::string(where) + "nx and ny must be >= 3");
+    if ((int64_t)c.nx * c.ny > (int64_t)1 << 30) return fail(LBM_E_INVAL, std::string(where) + "lattice too large");
+    if (c.precision != LBM_FP64 && c.precision != LBM_FP32)
+      return fail(LBM_E_INVAL, std::string(where) + "precision must be LBM_FP64 or LBM_FP32");
+    if (c.precision != cfgs[0].precision) return fail(LBM_E_INVAL, "all instances of a batch need the same precision");
+    if (c.advection != LBM_ADV_PAPER && c.advection != LBM_ADV_FLUX)
+      return fail(LBM_E_INVAL, std::string(where) + "unknown advection scheme");
+    if (!(c.tau > 0.5)) return fail(LBM_E_INVAL, std::string(where) + "tau must exceed 1/2");
+    if (!(c.b > 0.0)) return fail(LBM_E_INVAL, std::string(where) + "b must be positive");
+    if (!(c.n0 > 0.0)) return fail(LBM_E_INVAL, std::string(where) + "n0 must be positive");
+    const double vals[] = {c.a, c.B0, c.B1, c.D, c.Gamma, c.gamma, c.A0, c.t_star, c.c0};
+    for (double v : vals)
+      if (!std::isfinite(v)) return fail(LBM_E_INVAL, std::string(where) + "parameters must be finite");
+    if (ndrop[i] < 0 || ndrop[i] > LBM_MAXDROP)
+      return fail(LBM_E_INVAL, std::string(where) + "droplet count out of range [0, LBM_MAXDROP]");
+  }
+  return LBM_OK;
+}
+
+void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, Layout& L) {
+  L.prec = cfgs[0].precision;
+  L.elem = L.prec == LBM_FP64 ? 8 : 4;
+  const size_t row_align = ALIGN / L.elem;
+  int64_t pool_elems = 0;
+  int tile_base = 0, drop_base = 0;
+  int64_t part_elems = 0;
+  L.inst.resize(ninst);
+  for (int i = 0; i < ninst; ++i) {
+    const lbm_config& c = cfgs[i];
+    InstDev& d = L.inst[i];
+    memset(&d, 0, sizeof d);
+    d.nx = c.nx;
+    d.ny = c.ny;
+    d.pitch = (int32_t)align_up((size_t)c.nx, row_align);
+    d.ndrop = ndrop[i];
+    d.tiles_x = (c.nx + TILE_X - 1) / TILE_X;
+    d.tiles_y = (c.ny + TILE_Y - 1) / TILE_Y;
+    d.tile_base = tile_base;
+    d.drop_base = drop_base;
+    const int64_t plane = (int64_t)c.ny * d.pitch;
+    int64_t o = pool_elems;
+    d.off_f[0] = o;  o += 9 * plane;
+    d.off_f[1] = o;  o += 9 * plane;
+    d.off_phi[0] = o; o += plane;
+    d.off_phi[1] = o; o += plane;
+    d.off_c[0] = o;  o += plane;
+    d.off_c[1] = o;  o += plane;
+    d.off_ux = o;    o += plane;
+    d.off_uy = o;    o += plane;
+    d.off_n = o;     o += plane;
+    pool_elems = o;
+    d.part_base = part_elems;
+    part_elems += (int64_t)d.tiles_x * d.tiles_y * d.ndrop * 3;
+    d.advection = c.advection;
+    d.a = c.a;
+    d.b = c.b;
+    d.B0 = c.B0;
+    d.B1 = c.B1;
+    d.halfB1 = 0.5 * c.B1;
+    d.D = c.D;
+    d.Gamma = c.Gamma;
+    d.gamma = c.gamma;
+    d.c0 = c.c0;
+    d.omega = 1.0 / c.tau;
+    d.coef = 1.0 - 1.0 / (2.0 * c.tau);
+    d.A0 = c.A0;
+    d.t_star = c.t_star;
+    tile_base += d.tiles_x * d.tiles_y;
+    drop_base += d.ndrop;
+    L.max_nd = std::max(L.max_nd, (int)d.ndrop);
+    L.max_nodes = std::max(L.max_nodes, (int64_t)c.nx * c.ny);
+  }
+  L.ntiles = tile_base;
+  L.ndrop_total = drop_base;
+  L.obs_stride = 6 + 3 * L.max_nd;
+  // Tile list in launch order: workgroup b runs on XCD (b mod 8); give each XCD a contiguous run of
+  // tiles (raster order within an instance) so that neighbouring tiles share that XCD's L2.
+  std::vector<TileDev> natural;
+  natural.reserve(L.ntiles);
+  for (int i = 0; i < ninst; ++i) {
+    const InstDev& d = L.inst[i];
+    for (int ty = 0; ty < d.tiles_y; ++ty)
+      for (int tx = 0; tx < d.tiles_x; ++tx)
+        natural.push_back(TileDev{i, tx * TILE_X, ty * TILE_Y, (int32_t)natural.size()});
+  }
+  const int nx8 = 8;
+  const int chunk = (L.ntiles + nx8 - 1) / nx8;
+  L.tiles.assign((size_t)chunk * nx8, TileDev{-1, 0, 0, -1});
+  for (int t = 0; t < L.ntiles; ++t) {
+    const int xcd = t / chunk, m = t % chunk;
+    L.tiles[(size_t)m * nx8 + xcd] = natural[t];
+  }
+  size_t off = 0;
+  L.off_pool = off;  off = align_up(off + (size_t)pool_elems * L.elem, ALIGN);
+  L.off_inst = off;  off = align_up(off + sizeof(InstDev) * ninst, ALIGN);
+  L.off_tiles = off; off = align_up(off + sizeof(TileDev) * L.tiles.size(), ALIGN);
+  L.off_drops = off; off = align_up(off + sizeof(DropDev) * std::max(1, L.ndrop_total), ALIGN);
+  L.off_part = off;  off = align_up(off + sizeof(double) * std::max<int64_t>(1, part_elems), ALIGN);
+  L.off_mask = off;  off = align_up(off + sizeof(uint64_t) * MASK_WORDS * (size_t)L.ntiles, ALIGN);
+  L.off_step = off;  off = align_up(off + sizeof(int64_t), ALIGN);
+  L.off_obs = off;   off = align_up(off + sizeof(double) * (size_t)L.obs_stride * L.ntiles, ALIGN);
+  L.off_dbg = off;
+  off = align_up(off + sizeof(double) * (size_t)LBM_NSTAGE * std::min(L.max_nodes, DEBUG_MAX_NODES), ALIGN);
+  L.total = off;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  Layout L;
+  std::vector<lbm_config> cfg;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int parity = 0;
+  int64_t step = 0;
+  int graph_steps = 0;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+
+  void* pool() const { return ws + L.off_pool; }
+  InstDev* d_inst() const { return reinterpret_cast<InstDev*>(ws + L.off_inst); }
+  TileDev* d_tiles() const { return reinterpret_cast<TileDev*>(ws + L.off_tiles); }
+  DropDev* d_drops() const { return reinterpret_cast<DropDev*>(ws + L.off_drops); }
+  double* d_part() const { return reinterpret_cast<double*>(ws + L.off_part); }
+  uint64_t* d_mask() const { return reinterpret_cast<uint64_t*>(ws + L.off_mask); }
+  int64_t* d_step() const { return reinterpret_cast<int64_t*>(ws + L.off_step); }
+  double* d_obs() const { return reinterpret_cast<double*>(ws + L.off_obs); }
+  double* d_dbg() const { return reinterpret_cast<double*>(ws + L.off_dbg); }
+  int nlaunch() const { return (int)L.tiles.size(); }
+};
+
+namespace {
+
+template <typename T>
+hipError_t enqueue_step(lbm_ctx* c, int parity) {
+  T* buf = reinterpret_cast<T*>(c->pool());
+  hipError_t e = launch_lb<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+  if (e != hipSuccess) return e;
+  e = launch_fd<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
+                   c->d_part(), c->d_mask(), c->d_step(), nullptr, -1);
+  if (e != hipSuccess) return e;
+  return launch_reduce(c->stream, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
+                       c->d_step(), 1);
+}
+
+hipError_t enqueue_step_any(lbm_ctx* c, int parity) {
+  return c->L.prec == LBM_FP64 ? enqueue_step<double>(c, parity) : enqueue_step<float>(c, parity);
+}
+
+void destroy_graphs(lbm_ctx* c) {
+  for (int p = 0; p < 2; ++p) {
+    if (c->exec[p]) (void)hipGraphExecDestroy(c->exec[p]);
+    if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+    c->exec[p] = nullptr;
+    c->graph[p] = nullptr;
+  }
+}
+
+int build_graph(lbm_ctx* c, int parity) {
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+  hipError_t err = hipSuccess;
+  for (int s = 0; s < c->graph_steps && err == hipSuccess; ++s) err = enqueue_step_any(c, (parity + s) & 1);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+  if (err != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LBM_E_HIP, std::string("kernel launch during capture: ") + hipGetErrorString(err));
+  }
+  if (e2 != hipSuccess) return fail(LBM_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+  c->graph[parity] = g;
+  HIPCHK(hipGraphInstantiate(&c->exec[parity], g, nullptr, nullptr, 0));
+  return LBM_OK;
+}
+
+template <typename T>
+void to_device_layout(const double* src, T* dst, int nx, int ny, int pitch) {
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < pitch; ++x) dst[(size_t)y * pitch + x] = x < nx ? (T)src[(size_t)y * nx + x] : T(0);
+}
+
+template <typename T>
+int upload_instance(lbm_ctx* c, int i, const double* phi0, const double* c0, const double* f_pre) {
+  const InstDev& d = c->L.inst[i];
+  const int nx = d.nx, ny = d.ny, pitch = d.pitch;
+  const size_t plane = (size_t)ny * pitch;
+  std::vector<T> h(plane * 9);
+  T* base = reinterpret_cast<T*>(c->pool());
+  to_device_layout(phi0, h.data(), nx, ny, pitch);
+  HIPCHK(hipMemcpyAsync(base + d.off_phi[0], h.data(), plane * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  to_device_layout(c0, h.data(), nx, ny, pitch);
+  HIPCHK(hipMemcpyAsync(base + d.off_c[0], h.data(), plane * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  // Stored populations are post-collision values at the emitting node: f*_i(r) = f_i(r + e_i).
+  std::fill(h.begin(), h.end(), T(0));
+  for (int k = 0; k < 9; ++k)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        double v;
+        if (f_pre) {
+          const int xs = (x + EX[k] + nx) % nx, ys = (y + EY[k] + ny) % ny;
+          v = f_pre[(size_t)k * nx * ny + (size_t)ys * nx + xs];
+        } else {
+          v = WGT[k] * c->cfg[i].n0;
+        }
+        h[(size_t)k * plane + (size_t)y * pitch + x] = (T)v;
+      }
+  HIPCHK(hipMemcpyAsync(base + d.off_f[0], h.data(), 9 * plane * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  // velocity / density planes start at zero; the second buffers are fully rewritten by the first step
+  HIPCHK(hipMemsetAsync(base + d.off_ux, 0, 3 * plane * sizeof(T), c->stream));
+  HIPCHK(hipMemsetAsync(base + d.off_f[1], 0, 9 * plane * sizeof(T), c->stream));
+  HIPCHK(hipMemsetAsync(base + d.off_phi[1], 0, plane * sizeof(T), c->stream));
+  HIPCHK(hipMemsetAsync(base + d.off_c[1], 0, plane * sizeof(T), c->stream));
+  return LBM_OK;
+}
+
+int check_inst(lbm_ctx* c, int32_t inst) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  if (inst < 0 || inst >= (int)c->L.inst.size()) return fail(LBM_E_INVAL, "instance index out of range");
+  return LBM_OK;
+}
+
+// n, u planes of every instance from the current state (Eq. 11 with the force of Eq. 14).
+int run_diag(lbm_ctx* c) {
+  hipError_t e;
+  if (c->L.prec == LBM_FP64)
+    e = launch_lb<double>(c->stream, 2, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
+                          reinterpret_cast<double*>(c->pool()), nullptr, -1);
+  else
+    e = launch_lb<float>(c->stream, 2, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
+                         reinterpret_cast<float*>(c->pool()), nullptr, -1);
+  if (e != hipSuccess) return fail(LBM_E_HIP, std::string("diagnostic launch: ") + hipGetErrorString(e));
+  return LBM_OK;
+}
+
+template <typename T>
+int download_plane(lbm_ctx* c, int64_t off, const InstDev& d, double* out) {
+  const size_t plane = (size_t)d.ny * d.pitch;
+  std::vector<T> h(plane);
+  HIPCHK(hipMemcpyAsync(h.data(), reinterpret_cast<T*>(c->pool()) + off, plane * sizeof(T), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int y = 0; y < d.ny; ++y)
+    for (int x = 0; x < d.nx; ++x) out[(size_t)y * d.nx + x] = (double)h[(size_t)y * d.pitch + x];
+  return LBM_OK;
+}
+
+template <typename T>
+int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, double* n, double* ux,
+                double* uy) {
+  const InstDev& d = c->L.inst[inst];
+  int rc;
+  if (n || ux || uy) {
+    if ((rc = run_diag(c)) != LBM_OK) return rc;
+  }
+  if (phi && (rc = download_plane<T>(c, d.off_phi[c->parity], d, phi)) != LBM_OK) return rc;
+  if (cc && (rc = download_plane<T>(c, d.off_c[c->parity], d, cc)) != LBM_OK) return rc;
+  if (n && (rc = download_plane<T>(c, d.off_n, d, n)) != LBM_OK) return rc;
+  if (ux && (rc = download_plane<T>(c, d.off_ux, d, ux)) != LBM_OK) return rc;
+  if (uy && (rc = download_plane<T>(c, d.off_uy, d, uy)) != LBM_OK) return rc;
+  if (f_pre) {
+    const size_t plane = (size_t)d.ny * d.pitch;
+    std::vector<T> h(9 * plane);
+    HIPCHK(hipMemcpyAsync(h.data(), reinterpret_cast<T*>(c->pool()) + d.off_f[c->parity], 9 * plane * sizeof(T),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int nx = d.nx, ny = d.ny;
+    for (int k = 0; k < 9; ++k)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          // pre-collision f_k(r) = f*_k(r - e_k)
+          const int xs = (x - EX[k] + nx) % nx, ys = (y - EY[k] + ny) % ny;
+          f_pre[(size_t)k * nx * ny + (size_t)y * nx + x] = (double)h[(size_t)k * plane + (size_t)ys * d.pitch + xs];
+        }
+  }
+  return LBM_OK;
+}
+
+int read_drops(lbm_ctx* c, int inst, std::vector<DropDev>& out) {
+  const InstDev& d = c->L.inst[inst];
+  out.resize(d.ndrop);
+  if (d.ndrop == 0) return LBM_OK;
+  HIPCHK(hipMemcpyAsync(out.data(), c->d_drops() + d.drop_base, sizeof(DropDev) * d.ndrop, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_workspace_bytes(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, size_t* bytes) {
+  if (!bytes) return fail(LBM_E_INVAL, "bytes must not be NULL");
+  int rc = validate(ninst, cfgs, ndrop);
+  if (rc != LBM_OK) return rc;
+  Layout L;
+  make_layout(ninst, cfgs, ndrop, L);
+  *bytes = L.total;
+  return LBM_OK;
+}
+
+int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_t workspace_bytes, void* stream,
+                   const double* phi0, const double* c0, const double* f_pre, const int32_t* ndrop,
+                   const lbm_droplet* drops, int64_t step, lbm_ctx** out) {
+  if (!out) return fail(LBM_E_INVAL, "out must not be NULL");
+  *out = nullptr;
+  int rc = validate(ninst, cfgs, ndrop);
+  if (rc != LBM_OK) return rc;
+  if (!workspace) return fail(LBM_E_INVAL, "workspace must not be NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(LBM_E_INVAL, "workspace must be 256-byte aligned");
+  if (!phi0 || !c0) return fail(LBM_E_INVAL, "phi0 and c0 must not be NULL");
+  if (step < 0) return fail(LBM_E_INVAL, "step must be >= 0");
+  int nd_total = 0;
+  for (int i = 0; i < ninst; ++i) nd_total += ndrop[i];
+  if (nd_total > 0 && !drops) return fail(LBM_E_INVAL, "drops must not be NULL when droplets are requested");
+  for (int k = 0; k < nd_total; ++k) {
+    const lbm_droplet& d = drops[k];
+    if (!std::isfinite(d.x) || !std::isfinite(d.y) || !std::isfinite(d.ex) || !std::isfinite(d.ey) ||
+        !(d.R >= 0.0) || !(d.Rs >= 0.0))
+      return fail(LBM_E_INVAL, "droplet table entries must be finite with R, Rs >= 0");
+  }
+  lbm_ctx* c = new lbm_ctx();
+  make_layout(ninst, cfgs, ndrop, c->L);
+  if (workspace_bytes < c->L.total) {
+    delete c;
+    return fail(LBM_E_NOMEM, "workspace smaller than lbm_workspace_bytes()");
+  }
+  c->cfg.assign(cfgs, cfgs + ninst);
+  c->ws = static_cast<char*>(workspace);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->step = step;
+  c->graph_steps = stream ? 20 : 0;
+
+  auto bail = [&](int code) {
+    destroy_graphs(c);
+    delete c;
+    return code;
+  };
+  size_t off_field = 0;
+  for (int i = 0; i < ninst; ++i) {
+    const size_t n = (size_t)cfgs[i].nx * cfgs[i].ny;
+    rc = c->L.prec == LBM_FP64
+             ? upload_instance<double>(c, i, phi0 + off_field, c0 + off_field, f_pre ? f_pre + 9 * off_field : nullptr)
+             : upload_instance<float>(c, i, phi0 + off_field, c0 + off_field, f_pre ? f_pre + 9 * off_field : nullptr);
+    if (rc != LBM_OK) return bail(rc);
+    off_field += n;
+  }
+  std::vector<DropDev> dd(std::max(1, nd_total));
+  int k = 0;
+  for (int i = 0; i < ninst; ++i)
+    for (int j = 0; j < ndrop[i]; ++j, ++k) {
+      const lbm_droplet& s = drops[k];
+      dd[k] = DropDev{s.x, s.y, s.R, s.Rs, s.ex, s.ey, s.active ? 1 : 0, i};
+    }
+  hipError_t e;
+#define INIT_CHK(call)                                                                               \
+  do {                                                                                               \
+    e = (call);                                                                                      \
+    if (e != hipSuccess) return bail(fail(LBM_E_HIP, std::string(#call) + ": " + hipGetErrorString(e))); \
+  } while (0)
+  INIT_CHK(hipMemcpyAsync(c->d_inst(), c->L.inst.data(), sizeof(InstDev) * ninst, hipMemcpyHostToDevice, c->stream));
+  INIT_CHK(hipMemcpyAsync(c->d_tiles(), c->L.tiles.data(), sizeof(TileDev) * c->L.tiles.size(), hipMemcpyHostToDevice,
+                          c->stream));
+  INIT_CHK(hipMemcpyAsync(c->d_drops(), dd.data(), sizeof(DropDev) * dd.size(), hipMemcpyHostToDevice, c->stream));
+  INIT_CHK(hipMemcpyAsync(c->d_step(), &c->step, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  INIT_CHK(hipMemsetAsync(c->d_mask(), 0, sizeof(uint64_t) * MASK_WORDS * c->L.ntiles, c->stream));
+  // first centre-of-mass pass on phi0, started from the given centres
+  if (c->L.prec == LBM_FP64)
+    INIT_CHK(launch_cm_partials<double>(c->stream, 0, c->nlaunch(), c->d_tiles(), c->d_inst(),
+                                        reinterpret_cast<double*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask()));
+  else
+    INIT_CHK(launch_cm_partials<float>(c->stream, 0, c->nlaunch(), c->d_tiles(), c->d_inst(),
+                                       reinterpret_cast<float*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask()));
+  INIT_CHK(launch_reduce(c->stream, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
+                         c->d_step(), 0));
+  INIT_CHK(hipStreamSynchronize(c->stream));
+#undef INIT_CHK
+  *out = c;
+  g_err.clear();
+  return LBM_OK;
+}
+
+int lbm_init(const lbm_config* cfg, void* workspace, size_t workspace_bytes, void* stream, const double* phi0,
+             const double* c0, const double* f_pre, int32_t ndrop, const lbm_droplet* drops, int64_t step,
+             lbm_ctx** out) {
+  return lbm_init_batch(1, cfg, workspace, workspace_bytes, stream, phi0, c0, f_pre, &ndrop, drops, step, out);
+}
+
+int lbm_set_graph(lbm_ctx* c, int32_t steps_per_graph) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  if (steps_per_graph < 0 || (steps_per_graph > 0 && (steps_per_graph % 2 != 0 || steps_per_graph < 2)))
+    return fail(LBM_E_INVAL, "steps_per_graph must be 0 or an even number >= 2");
+  if (steps_per_graph > 0 && !c->stream) return fail(LBM_E_STATE, "graph replay needs a non-default stream");
+  destroy_graphs(c);
+  c->graph_steps = steps_per_graph;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  if (n < 0) return fail(LBM_E_INVAL, "n must be >= 0");
+  int64_t left = n;
+  if (c->graph_steps > 0) {
+    while (left >= c->graph_steps) {
+      if (!c->exec[c->parity]) {
+        int rc = build_graph(c, c->parity);
+        if (rc != LBM_OK) return rc;
+      }
+      HIPCHK(hipGraphLaunch(c->exec[c->parity], c->stream));
+      left -= c->graph_steps;
+      c->step += c->graph_steps;
+    }
+  }
+  for (; left > 0; --left) {
+    hipError_t e = enqueue_step_any(c, c->parity);
+    if (e != hipSuccess) return fail(LBM_E_HIP, std::string("timestep launch: ") + hipGetErrorString(e));
+    c->parity ^= 1;
+    c->step += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_sync(lbm_ctx* c) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int64_t lbm_get_step(const lbm_ctx* c) { return c ? c->step : -1; }
+
+int lbm_fields(lbm_ctx* c, int32_t inst, double* f_pre, double* phi, double* cc, double* n, double* ux, double* uy) {
+  int rc = check_inst(c, inst);
+  if (rc != LBM_OK) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return c->L.prec == LBM_FP64 ? fields_impl<double>(c, inst, f_pre, phi, cc, n, ux, uy)
+                               : fields_impl<float>(c, inst, f_pre, phi, cc, n, ux, uy);
+}
+
+int lbm_droplets(lbm_ctx* c, int32_t inst, lbm_droplet* out) {
+  int rc = check_inst(c, inst);
+  if (rc != LBM_OK) return rc;
+  if (!out && c->L.inst[inst].ndrop > 0) return fail(LBM_E_INVAL, "out must not be NULL");
+  std::vector<DropDev> dd;
+  if ((rc = read_drops(c, inst, dd)) != LBM_OK) return rc;
+  for (size_t k = 0; k < dd.size(); ++k)
+    out[k] = lbm_droplet{dd[k].x, dd[k].y, dd[k].R, dd[k].Rs, dd[k].ex, dd[k].ey, dd[k].active, 0};
+  return LBM_OK;
+}
+
+int lbm_observables(lbm_ctx* c, int32_t inst, lbm_obs* obs, double* drop_out) {
+  int rc = check_inst(c, inst);
+  if (rc != LBM_OK) return rc;
+  if (!obs) return fail(LBM_E_INVAL, "obs must not be NULL");
+  if ((rc = run_diag(c)) != LBM_OK) return rc;
+  hipError_t e = c->L.prec == LBM_FP64
+                     ? launch_obs<double>(c->stream, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
+                                          reinterpret_cast<double*>(c->pool()), c->d_drops(), c->d_obs(),
+                                          c->L.obs_stride)
+                     : launch_obs<float>(c->stream, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
+                                         reinterpret_cast<float*>(c->pool()), c->d_drops(), c->d_obs(),
+                                         c->L.obs_stride);
+  if (e != hipSuccess) return fail(LBM_E_HIP, std::string("observables launch: ") + hipGetErrorString(e));
+  const InstDev& d = c->L.inst[inst];
+  const int nt = d.tiles_x * d.tiles_y, S = c->L.obs_stride;
+  std::vector<double> h((size_t)nt * S);
+  HIPCHK(hipMemcpyAsync(h.data(), c->d_obs() + (size_t)d.tile_base * S, h.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<DropDev> dd;
+  if ((rc = read_drops(c, inst, dd)) != LBM_OK) return rc;
+  double m = 0, sp = 0, sc = 0, mb = INFINITY, mu = 0, nf = 0;
+  std::vector<double> sw(d.ndrop, 0.0), su(d.ndrop, 0.0), sv(d.ndrop, 0.0);
+  for (int t = 0; t < nt; ++t) {
+    const double* o = &h[(size_t)t * S];
+    m += o[0];
+    sp += o[1];
+    sc += o[2];
+    mb = std::min(mb, o[3]);
+    mu = std::max(mu, o[4]);
+    nf = std::max(nf, o[5]);
+    for (int k = 0; k < d.ndrop; ++k) {
+      sw[k] += o[6 + 3 * k];
+      su[k] += o[7 + 3 * k];
+      sv[k] += o[8 + 3 * k];
+    }
+  }
+  obs->step = c->step;
+  obs->mass = m;
+  obs->sum_phi = sp;
+  obs->sum_c = sc;
+  obs->min_B = mb;
+  obs->max_u = mu;
+  obs->nonfinite = (nf != 0.0 || !std::isfinite(m) || !std::isfinite(sp) || !std::isfinite(sc)) ? 1 : 0;
+  obs->ndrop = d.ndrop;
+  if (drop_out) {
+    for (int k = 0; k < d.ndrop; ++k) {
+      drop_out[5 * k + 0] = dd[k].x;
+      drop_out[5 * k + 1] = dd[k].y;
+      drop_out[5 * k + 2] = sw[k] > 0.0 ? su[k] / sw[k] : 0.0;
+      drop_out[5 * k + 3] = sw[k] > 0.0 ? sv[k] / sw[k] : 0.0;
+      drop_out[5 * k + 4] = sw[k];
+    }
+  }
+  if (obs->nonfinite) return fail(LBM_E_UNSTABLE, "non-finite values in the state");
+  if (!(obs->min_B > 0.0)) return fail(LBM_E_UNSTABLE, "B(c) = B0 + B1 c <= 0 somewhere (interfaces unstable)");
+  return LBM_OK;
+}
+
+int lbm_debug_stage(lbm_ctx* c, int32_t inst, double* out) {
+  int rc = check_inst(c, inst);
+  if (rc != LBM_OK) return rc;
+  if (!out) return fail(LBM_E_INVAL, "out must not be NULL");
+  const InstDev& d = c->L.inst[inst];
+  if ((int64_t)d.nx * d.ny > DEBUG_MAX_NODES) return fail(LBM_E_INVAL, "stage export is limited to 512 x 512 nodes");
+  hipError_t e;
+  if (c->L.prec == LBM_FP64) {
+    double* buf = reinterpret_cast<double*>(c->pool());
+    e = launch_lb<double>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
+    if (e == hipSuccess)
+      e = launch_fd<double>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
+                            c->d_part(), c->d_mask(), c->d_step(), c->d_dbg(), inst);
+  } else {
+    float* buf = reinterpret_cast<float*>(c->pool());
+    e = launch_lb<float>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
+    if (e == hipSuccess)
+      e = launch_fd<float>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
+                           c->d_part(), c->d_mask(), c->d_step(), c->d_dbg(), inst);
+  }
+  if (e != hipSuccess) return fail(LBM_E_HIP, std::string("stage launch: ") + hipGetErrorString(e));
+  const size_t n = (size_t)d.nx * d.ny;
+  HIPCHK(hipMemcpyAsync(out, c->d_dbg(), sizeof(double) * LBM_NSTAGE * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
+  if (!c || !ms_out) return fail(LBM_E_INVAL, "null argument");
+  if (n <= 0) return fail(LBM_E_INVAL, "n must be > 0");
+  std::vector<hipEvent_t> ev((size_t)n * 4);
+  for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+  hipError_t e = hipSuccess;
+  for (int64_t s = 0; s < n && e == hipSuccess; ++s) {
+    hipEvent_t* E = &ev[(size_t)s * 4];
+    const int p = c->parity;
+    if (c->L.prec == LBM_FP64) {
+      double* buf = reinterpret_cast<double*>(c->pool());
+      (void)hipEventRecord(E[0], c->stream);
+      e = launch_lb<double>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+      (void)hipEventRecord(E[1], c->stream);
+      if (e == hipSuccess)
+        e = launch_fd<double>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
+                              c->d_mask(), c->d_step(), nullptr, -1);
+    } else {
+      float* buf = reinterpret_cast<float*>(c->pool());
+      (void)hipEventRecord(E[0], c->stream);
+      e = launch_lb<float>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+      (void)hipEventRecord(E[1], c->stream);
+      if (e == hipSuccess)
+        e = launch_fd<float>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
+                             c->d_mask(), c->d_step(), nullptr, -1);
+    }
+    (void)hipEventRecord(E[2], c->stream);
+    if (e == hipSuccess)
+      e = launch_reduce(c->stream, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(), c->d_step(), 1);
+    (void)hipEventRecord(E[3], c->stream);
+    c->parity ^= 1;
+    c->step += 1;
+  }
+  hipError_t es = hipStreamSynchronize(c->stream);
+  double acc[3] = {0, 0, 0};
+  if (e == hipSuccess && es == hipSuccess) {
+    for (int64_t s = 0; s < n; ++s) {
+      for (int j = 0; j < 3; ++j) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[(size_t)s * 4 + j], ev[(size_t)s * 4 + j + 1]);
+        acc[j] += ms;
+      }
+    }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return fail(LBM_E_HIP, std::string("timed launch: ") + hipGetErrorString(e));
+  if (es != hipSuccess) return fail(LBM_E_HIP, std::string("timed sync: ") + hipGetErrorString(es));
+  for (int j = 0; j < 3; ++j) ms_out[j] = acc[j] / (double)n;
+  return LBM_OK;
+}
+
+const char* lbm_kernel_name(int32_t which) {
+  switch (which) {
+    case 0: return "k_lb";
+    case 1: return "k_fd";
+    case 2: return "k_reduce";
+    default: return "";
+  }
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  destroy_graphs(c);
+  delete c;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

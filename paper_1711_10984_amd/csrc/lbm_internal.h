@@ -1,0 +1,62 @@
+// Internal declarations shared by the kernels and the host side of the library.
+// Not part of the public ABI (include/lbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Tile of interior nodes processed by one workgroup of the timestep kernels.
+constexpr int TILE_X = 64;
+constexpr int TILE_Y = 8;
+constexpr int NTHREADS = 256;
+constexpr int MAXDROP = 256;   // droplets per instance
+constexpr int MASK_WORDS = MAXDROP / 64;  // one presence bit per droplet and tile
+
+// Per-instance description read by every kernel (device copy in the workspace).
+struct InstDev {
+  int32_t nx, ny, pitch, ndrop;
+  int32_t tiles_x, tiles_y, tile_base, drop_base;
+  int64_t off_f[2];    // element offsets of the two population buffers [9][ny][pitch]
+  int64_t off_phi[2];  // the two phi buffers [ny][pitch]
+  int64_t off_c[2];    // the two c buffers
+  int64_t off_ux, off_uy, off_n;  // velocity planes written by the LB kernel; density (diagnostics)
+  int64_t part_base;   // offset (doubles) of this instance's centre-of-mass partials [tiles][ndrop][3]
+  int32_t advection, pad0;
+  // model parameters, derived on the host in double precision
+  double a, b, B0, B1, halfB1, D, Gamma, gamma, c0, omega, coef, A0, t_star;
+};
+
+// Droplet table entry on the device.
+struct DropDev {
+  double x, y, R, Rs, ex, ey;
+  int32_t active, inst;
+};
+
+// One entry of the tile list (natural order: instance, tile row, tile column).
+struct TileDev {
+  int32_t inst, x0, y0, t;  // t: natural tile index (partials are stored by it)
+};
+
+// Launch helpers implemented in lbm_kernels.hip.  `buf` is the typed base pointer of the field pool,
+// `parity` selects the current buffers.  Modes: 0 step, 1 step + stage export, 2 diagnostics only.
+template <typename T>
+hipError_t launch_lb(hipStream_t s, int mode, int parity, int ntiles_launch, const TileDev* tiles,
+                     const InstDev* inst, T* buf, double* dbg, int dbg_inst);
+template <typename T>
+hipError_t launch_fd(hipStream_t s, int mode, int parity, int ntiles_launch, const TileDev* tiles,
+                     const InstDev* inst, T* buf, const DropDev* drops, double* part, uint64_t* mask,
+                     const int64_t* step, double* dbg, int dbg_inst);
+template <typename T>
+hipError_t launch_cm_partials(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
+                              const InstDev* inst, T* buf, const DropDev* drops, double* part,
+                              uint64_t* mask);
+hipError_t launch_reduce(hipStream_t s, int ndrop_total, const InstDev* inst, DropDev* drops,
+                         const double* part, const uint64_t* mask, int64_t* step, int increment);
+template <typename T>
+hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
+                      const InstDev* inst, T* buf, const DropDev* drops, double* obs_part,
+                      int obs_stride);
+
+}  // namespace lbm

@@ -1,0 +1,756 @@
+// HIP kernels (gfx950) of the hybrid lattice-Boltzmann / finite-difference timestep of
+// Fadda et al., "Lattice Boltzmann study of chemically-driven self-propelled droplets"
+// (EPJ E 2017, arXiv:1711.10984), Sec. 2.
+//
+// One timestep n -> n+1 is three launches over a list of TILE_X x TILE_Y tiles that may span
+// several independent lattices (instances) of different sizes:
+//   k_lb     chemical potential mu_phi (Eq. 3), X = (B1/2)|grad phi|^2 (Eq. 5), force F (Eq. 14),
+//            pull streaming + moments with half the force (Eqs. 10-11), BGK collision with the
+//            equilibrium of Eq. (12) and the forcing of Eq. (13); writes f* and u^n.
+//   k_fd     advection half-step (Eqs. 16-17), diffusion of phi (Eq. 18), diffusion, consumption and
+//            production of c (Eq. 19); writes phi^{n+1}, c^{n+1} and per-tile centre-of-mass partials.
+//   k_reduce fixed-order sum of the partials, new centres of mass (Sec. 4), step counter.
+// Populations are stored post-collision (f*_i at the node that emitted them) in structure-of-arrays
+// planes [9][ny][pitch]; the next step pulls f_i(r) = f*_i(r - e_i).  Every field has two buffers
+// that alternate with the step parity.
+//
+// Floating-point expressions keep the grouping of the plain definitions (x- and y-reflection
+// symmetric sums); the library is compiled without FMA contraction, so the FP64 path is IEEE
+// arithmetic in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ constexpr T cst(double x) {
+  return static_cast<T>(x);
+}
+
+__device__ __forceinline__ int wrap_idx(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double minimg(double d, double L) {
+  if (d >= 0.5 * L) return d - L;
+  if (d < -0.5 * L) return d + L;
+  return d;
+}
+
+__device__ __forceinline__ double wrapd(double v, double L) {
+  double r = fmod(v, L);
+  if (r < 0.0) r += L;
+  if (r >= L) r -= L;
+  return r;
+}
+
+// Isotropic 9-point gradient sum_i (w_i / cs^2) e_i g(r + e_i) on an LDS tile of row stride W.
+template <typename T>
+__device__ __forceinline__ void grad9(const T* s, int i, int W, T& gx, T& gy) {
+  const T E = s[i + 1], Wv = s[i - 1], N = s[i + W], S = s[i - W];
+  const T NE = s[i + W + 1], NW = s[i + W - 1], SW = s[i - W - 1], SE = s[i - W + 1];
+  gx = (T(4) * (E - Wv) + ((NE - NW) + (SE - SW))) * cst<T>(1.0 / 12.0);
+  gy = (T(4) * (N - S) + ((NE - SE) + (NW - SW))) * cst<T>(1.0 / 12.0);
+}
+
+// Isotropic 9-point Laplacian sum_{i>0} (2 w_i / cs^2)(g(r + e_i) - g(r)).
+template <typename T>
+__device__ __forceinline__ T lap9(const T* s, int i, int W) {
+  const T E = s[i + 1], Wv = s[i - 1], N = s[i + W], S = s[i - W];
+  const T NE = s[i + W + 1], NW = s[i + W - 1], SW = s[i - W - 1], SE = s[i - W + 1];
+  return (T(4) * ((E + Wv) + (N + S)) + ((NE + NW) + (SE + SW)) - T(20) * s[i]) * cst<T>(1.0 / 6.0);
+}
+
+// Conservative link divergence of k grad X, sum_{i>0} (2 w_i/cs^2) (k + k_i)/2 (X_i - X), with
+// k = D c read from the LDS tile `cs` (stride Wc) and X from the tile `X` (stride WX).
+template <typename T>
+__device__ __forceinline__ T div9(const T* cs, int ic, int Wc, T D, const T* X, int iX, int WX) {
+  const T k0 = D * cs[ic], X0 = X[iX];
+  const T t1 = (k0 + D * cs[ic + 1]) * (X[iX + 1] - X0);
+  const T t2 = (k0 + D * cs[ic + Wc]) * (X[iX + WX] - X0);
+  const T t3 = (k0 + D * cs[ic - 1]) * (X[iX - 1] - X0);
+  const T t4 = (k0 + D * cs[ic - Wc]) * (X[iX - WX] - X0);
+  const T t5 = (k0 + D * cs[ic + Wc + 1]) * (X[iX + WX + 1] - X0);
+  const T t6 = (k0 + D * cs[ic + Wc - 1]) * (X[iX + WX - 1] - X0);
+  const T t7 = (k0 + D * cs[ic - Wc - 1]) * (X[iX - WX - 1] - X0);
+  const T t8 = (k0 + D * cs[ic - Wc + 1]) * (X[iX - WX + 1] - X0);
+  return (T(4) * ((t1 + t3) + (t2 + t4)) + ((t5 + t6) + (t7 + t8))) * cst<T>(1.0 / 12.0);
+}
+
+// Advection half-step of Eqs. (16)-(17) for the scalar tile g at index i (stride W), velocity
+// tiles ux, uy of the same geometry.  mode 0: centred velocity divergence and first-order upwind
+// concentration gradient; mode 1: conservative face-upwind fluxes.
+template <typename T>
+__device__ __forceinline__ T advect(const T* g, const T* ux, const T* uy, int i, int W, int mode) {
+  const T gc = g[i];
+  if (mode == 0) {
+    const T divu = T(0.5) * (ux[i + 1] - ux[i - 1]) + T(0.5) * (uy[i + W] - uy[i - W]);
+    const T u = ux[i], v = uy[i];
+    const T dgx = u > T(0) ? gc - g[i - 1] : g[i + 1] - gc;
+    const T dgy = v > T(0) ? gc - g[i - W] : g[i + W] - gc;
+    return gc - ((gc * divu + u * dgx) + v * dgy);
+  }
+  const T uxr = T(0.5) * (ux[i] + ux[i + 1]), uxl = T(0.5) * (ux[i - 1] + ux[i]);
+  const T uyt = T(0.5) * (uy[i] + uy[i + W]), uyb = T(0.5) * (uy[i - W] + uy[i]);
+  const T Fr = uxr * (uxr >= T(0) ? gc : g[i + 1]);
+  const T Fl = uxl * (uxl >= T(0) ? g[i - 1] : gc);
+  const T Ft = uyt * (uyt >= T(0) ? gc : g[i + W]);
+  const T Fb = uyb * (uyb >= T(0) ? g[i - W] : gc);
+  return gc - ((Fr - Fl) + (Ft - Fb));
+}
+
+// BGK collision of Eq. (10) with the equilibrium of Eq. (12) and the forcing of Eq. (13) for one
+// direction e: f* = f - omega (f - feq) + (1 - 1/(2 tau)) w [3 (e - u) + 9 (e.u) e] . F.
+// wn = w n, cw = (1 - 1/(2 tau)) w, eu = e.u, eF = e.F, exu = e_x - u_x, eyu = e_y - u_y.
+template <typename T>
+__device__ __forceinline__ T collide1(T f, T wn, T cw, T eu, T eF, T exu, T eyu, T Fx, T Fy, T usq,
+                                      T omega) {
+  const T feq = wn * (((T(1) + T(3) * eu) + (T(4.5) * eu) * eu) - T(1.5) * usq);
+  const T Fi = cw * (T(3) * (exu * Fx + eyu * Fy) + (T(9) * eu) * eF);
+  return (f - omega * (f - feq)) + Fi;
+}
+
+// Sum (or min/max) over the workgroup in a fixed order; every thread receives lane 0's result.
+struct OpAdd {
+  __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpMin {
+  __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+struct OpMax {
+  __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+
+template <class Op>
+__device__ double block_reduce(double v, double* sh, Op op) {
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int w = 1; w < NTHREADS / 64; ++w) r = op(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+// Droplet bookkeeping of one tile: candidate lists for the nearest-centre assignment and for the
+// production disks, and the deterministic per-tile sums over nodes with phi >= 0 (Sec. 4).
+struct DropShared {
+  int n_near, n_src;
+  int near_list[MAXDROP];
+  int src_list[MAXDROP];
+  double mind2[MAXDROP];
+  unsigned char src_flag[MAXDROP];
+  double red[NTHREADS / 64];
+  unsigned long long mask[MASK_WORDS];
+};
+
+// Conservative culling for the box [bx0, bx1] x [by0, by1]: a droplet is a nearest-centre candidate
+// unless its distance to every node of the box exceeds the largest distance of some other droplet's
+// centre to the box; a production disk is a candidate if it may reach the box.  Exact decisions are
+// taken per node among the candidates, in increasing droplet index.
+__device__ void cull_droplets(const InstDev& I, const DropDev* __restrict__ drops, int bx0, int bx1,
+                              int by0, int by1, DropShared& sh) {
+  const int tid = threadIdx.x;
+  const int nd = I.ndrop;
+  const double Lx = I.nx, Ly = I.ny;
+  const double xm = 0.5 * (bx0 + bx1), ym = 0.5 * (by0 + by1);
+  const double hx = 0.5 * (bx1 - bx0), hy = 0.5 * (by1 - by0);
+  double my_min_max = 1e300;
+  for (int k = tid; k < nd; k += NTHREADS) {
+    const DropDev d = drops[I.drop_base + k];
+    const double ddx = fabs(minimg(xm - d.x, Lx)), ddy = fabs(minimg(ym - d.y, Ly));
+    const double ux = ddx + hx, uy = ddy + hy;
+    my_min_max = fmin(my_min_max, ux * ux + uy * uy);
+    const double lx = fmax(0.0, ddx - hx), ly = fmax(0.0, ddy - hy);
+    sh.mind2[k] = lx * lx + ly * ly;
+    unsigned char sf = 0;
+    if (d.active) {
+      const double px = d.x + (d.R - d.Rs) * d.ex, py = d.y + (d.R - d.Rs) * d.ey;
+      const double sdx = fmax(0.0, fabs(minimg(xm - px, Lx)) - hx);
+      const double sdy = fmax(0.0, fabs(minimg(ym - py, Ly)) - hy);
+      const double rr = d.Rs + 1e-6;
+      sf = (sdx * sdx + sdy * sdy <= rr * rr) ? 1 : 0;
+    }
+    sh.src_flag[k] = sf;
+  }
+  const double thr = block_reduce(my_min_max, sh.red, OpMin());
+  if (tid == 0) {
+    int nn = 0, ns = 0;
+    const double lim = thr * (1.0 + 1e-12) + 1e-6;
+    for (int k = 0; k < nd; ++k) {
+      if (sh.mind2[k] <= lim) sh.near_list[nn++] = k;
+      if (sh.src_flag[k]) sh.src_list[ns++] = k;
+    }
+    sh.n_near = nn;
+    sh.n_src = ns;
+  }
+  __syncthreads();
+}
+
+// Index of the droplet whose centre is nearest (minimum image) to node (x, y); lowest index on ties.
+__device__ __forceinline__ int nearest_drop(const InstDev& I, const DropDev* __restrict__ drops,
+                                            const DropShared& sh, double x, double y) {
+  int best = -1;
+  double bd = 0.0;
+  for (int j = 0; j < sh.n_near; ++j) {
+    const int k = sh.near_list[j];
+    const DropDev d = drops[I.drop_base + k];
+    const double dx = minimg(x - d.x, (double)I.nx);
+    const double dy = minimg(y - d.y, (double)I.ny);
+    const double d2 = dx * dx + dy * dy;
+    if (best < 0 || d2 < bd) {
+      best = k;
+      bd = d2;
+    }
+  }
+  return best;
+}
+
+// Number of active production disks |r - r_P| <= Rs containing node (x, y) (Sec. 2.1).
+__device__ __forceinline__ int source_count(const InstDev& I, const DropDev* __restrict__ drops,
+                                            const DropShared& sh, double x, double y) {
+  int cnt = 0;
+  for (int j = 0; j < sh.n_src; ++j) {
+    const DropDev d = drops[I.drop_base + sh.src_list[j]];
+    const double px = d.x + (d.R - d.Rs) * d.ex;
+    const double py = d.y + (d.R - d.Rs) * d.ey;
+    const double dx = minimg(x - px, (double)I.nx);
+    const double dy = minimg(y - py, (double)I.ny);
+    if (dx * dx + dy * dy <= d.Rs * d.Rs) ++cnt;
+  }
+  return cnt;
+}
+
+constexpr int NPT = TILE_X * TILE_Y / NTHREADS;  // interior nodes per thread
+static_assert(TILE_X * TILE_Y % NTHREADS == 0, "tile must be a multiple of the workgroup");
+
+// Per-tile centre-of-mass sums {phi, phi dx, phi dy} for every droplet present in the tile, written
+// as partials[t][k][3] plus a presence mask; kd[j] < 0 marks nodes that contribute nothing.
+__device__ void tile_cm_sums(const InstDev& I, int t_local, int t_global, const int* kd, const double* v,
+                             const double* vx, const double* vy, DropShared& sh, double* part,
+                             uint64_t* mask) {
+  const int tid = threadIdx.x;
+  if (tid < MASK_WORDS) sh.mask[tid] = 0ull;
+  __syncthreads();
+  for (int j = 0; j < NPT; ++j)
+    if (kd[j] >= 0) atomicOr(&sh.mask[kd[j] >> 6], 1ull << (kd[j] & 63));
+  __syncthreads();
+  for (int w = 0; w < MASK_WORDS; ++w) {
+    unsigned long long m = sh.mask[w];
+    while (m) {
+      const int bit = __ffsll(m) - 1;
+      m &= m - 1;
+      const int k = w * 64 + bit;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      for (int j = 0; j < NPT; ++j)
+        if (kd[j] == k) {
+          a0 += v[j];
+          a1 += vx[j];
+          a2 += vy[j];
+        }
+      const double s0 = block_reduce(a0, sh.red, OpAdd());
+      const double s1 = block_reduce(a1, sh.red, OpAdd());
+      const double s2 = block_reduce(a2, sh.red, OpAdd());
+      if (tid == 0) {
+        double* p = part + I.part_base + ((int64_t)t_local * I.ndrop + k) * 3;
+        p[0] = s0;
+        p[1] = s1;
+        p[2] = s2;
+      }
+    }
+  }
+  if (tid < MASK_WORDS) mask[(int64_t)t_global * MASK_WORDS + tid] = sh.mask[tid];
+}
+
+// ------------------------------------------------------------------------------------------------
+// k_lb: mu, X, F; pull + moments; collision.  MODE 0: step, 1: step + stage planes, 2: n and u only.
+template <typename T, int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __restrict__ tiles,
+                                                 const InstDev* __restrict__ insts, T* __restrict__ buf,
+                                                 double* __restrict__ dbg, int dbg_inst) {
+  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  __shared__ T s_phi[W2 * H2], s_c[W2 * H2], s_mu[W1 * H1], s_X[W1 * H1];
+  __shared__ int s_col[W2], s_row[H2];
+
+  const TileDev td = tiles[blockIdx.x];
+  if (td.inst < 0) return;
+  if (MODE == 1 && td.inst != dbg_inst) return;
+  const InstDev& I = insts[td.inst];
+  const int nx = I.nx, ny = I.ny, pitch = I.pitch;
+  const int tid = threadIdx.x;
+  const int64_t plane = (int64_t)ny * pitch;
+  const T* __restrict__ phi = buf + I.off_phi[parity];
+  const T* __restrict__ cc = buf + I.off_c[parity];
+  const T* __restrict__ fin = buf + I.off_f[parity];
+  T* __restrict__ fout = buf + I.off_f[parity ^ 1];
+
+  for (int i = tid; i < W2; i += NTHREADS) s_col[i] = wrap_idx(td.x0 + i - 2, nx);
+  for (int i = tid; i < H2; i += NTHREADS) s_row[i] = wrap_idx(td.y0 + i - 2, ny);
+  __syncthreads();
+  for (int idx = tid; idx < W2 * H2; idx += NTHREADS) {
+    const int ly = idx / W2, lx = idx - ly * W2;
+    const int64_t g = (int64_t)s_row[ly] * pitch + s_col[lx];
+    s_phi[idx] = phi[g];
+    s_c[idx] = cc[g];
+  }
+  __syncthreads();
+
+  // S1-S2: mu_phi (Eq. 3) and X (Eq. 5) on the tile plus a one-node ring
+  const T a = T(I.a), b = T(I.b), B0 = T(I.B0), B1 = T(I.B1), halfB1 = T(I.halfB1);
+  for (int idx = tid; idx < W1 * H1; idx += NTHREADS) {
+    const int ly = idx / W1, lx = idx - ly * W1;
+    const int i2 = (ly + 1) * W2 + (lx + 1);
+    T gpx, gpy, gcx, gcy;
+    grad9(s_phi, i2, W2, gpx, gpy);
+    grad9(s_c, i2, W2, gcx, gcy);
+    const T lp = lap9(s_phi, i2, W2);
+    const T ph = s_phi[i2];
+    const T B = B0 + B1 * s_c[i2];
+    s_mu[idx] = ((a * ph + b * (ph * ph * ph)) - B * lp) - B1 * (gpx * gcx + gpy * gcy);
+    s_X[idx] = halfB1 * (gpx * gpx + gpy * gpy);
+  }
+  __syncthreads();
+
+  const T omega = T(I.omega), coef = T(I.coef);
+  const T w0 = cst<T>(4.0 / 9.0), w1 = cst<T>(1.0 / 9.0), w5 = cst<T>(1.0 / 36.0);
+  const T cw0 = coef * w0, cw1 = coef * w1, cw5 = coef * w5;
+  const int64_t nplane = (int64_t)nx * ny;
+
+  for (int idx = tid; idx < TX * TY; idx += NTHREADS) {
+    const int ly = idx / TX, lx = idx - ly * TX;
+    const int x = td.x0 + lx, y = td.y0 + ly;
+    if (x >= nx || y >= ny) continue;
+    const int i1 = (ly + 1) * W1 + (lx + 1), i2 = (ly + 2) * W2 + (lx + 2);
+    // S3: F = -phi grad mu - grad c - c grad X (Eq. 14)
+    T gmx, gmy, gXx, gXy, gcx, gcy;
+    grad9(s_mu, i1, W1, gmx, gmy);
+    grad9(s_X, i1, W1, gXx, gXy);
+    grad9(s_c, i2, W2, gcx, gcy);
+    const T ph = s_phi[i2], cv = s_c[i2];
+    const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
+    const T Fy = (-(ph * gmy) - gcy) - cv * gXy;
+    // S4: pull f_i(r) = f*_i(r - e_i), moments with half the force (Eq. 11)
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const int64_t r0 = (int64_t)y * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
+    const T f0 = fin[r0 + x];
+    const T f1 = fin[plane + r0 + xm];
+    const T f2 = fin[2 * plane + rm + x];
+    const T f3 = fin[3 * plane + r0 + xp];
+    const T f4 = fin[4 * plane + rp + x];
+    const T f5 = fin[5 * plane + rm + xm];
+    const T f6 = fin[6 * plane + rm + xp];
+    const T f7 = fin[7 * plane + rp + xp];
+    const T f8 = fin[8 * plane + rp + xm];
+    const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
+    const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
+    const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
+    const T ux = (mx + T(0.5) * Fx) / nn;
+    const T uy = (my + T(0.5) * Fy) / nn;
+    const int64_t o = r0 + x;
+    if (MODE == 2) {
+      buf[I.off_n + o] = nn;
+      buf[I.off_ux + o] = ux;
+      buf[I.off_uy + o] = uy;
+      continue;
+    }
+    buf[I.off_ux + o] = ux;
+    buf[I.off_uy + o] = uy;
+    // S5: collision (Eqs. 10, 12, 13)
+    const T usq = ux * ux + uy * uy;
+    const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
+    const T wn0 = w0 * nn, wn1 = w1 * nn, wn5 = w5 * nn;
+    const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
+    const T s0 = collide1(f0, wn0, cw0, T(0), T(0), nux, nuy, Fx, Fy, usq, omega);
+    const T s1 = collide1(f1, wn1, cw1, ux, Fx, xp1, nuy, Fx, Fy, usq, omega);
+    const T s2 = collide1(f2, wn1, cw1, uy, Fy, nux, yp1, Fx, Fy, usq, omega);
+    const T s3 = collide1(f3, wn1, cw1, nux, nFx, xm1, nuy, Fx, Fy, usq, omega);
+    const T s4 = collide1(f4, wn1, cw1, nuy, nFy, nux, ym1, Fx, Fy, usq, omega);
+    const T s5 = collide1(f5, wn5, cw5, ux + uy, Fx + Fy, xp1, yp1, Fx, Fy, usq, omega);
+    const T s6 = collide1(f6, wn5, cw5, nux + uy, nFx + Fy, xm1, yp1, Fx, Fy, usq, omega);
+    const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
+    const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
+    fout[o] = s0;
+    fout[plane + o] = s1;
+    fout[2 * plane + o] = s2;
+    fout[3 * plane + o] = s3;
+    fout[4 * plane + o] = s4;
+    fout[5 * plane + o] = s5;
+    fout[6 * plane + o] = s6;
+    fout[7 * plane + o] = s7;
+    fout[8 * plane + o] = s8;
+    if (MODE == 1) {
+      const int64_t q = (int64_t)y * nx + x;
+      dbg[0 * nplane + q] = (double)s_mu[i1];
+      dbg[1 * nplane + q] = (double)s_X[i1];
+      dbg[2 * nplane + q] = (double)Fx;
+      dbg[3 * nplane + q] = (double)Fy;
+      dbg[4 * nplane + q] = (double)nn;
+      dbg[5 * nplane + q] = (double)ux;
+      dbg[6 * nplane + q] = (double)uy;
+      const T sv[9] = {s0, s1, s2, s3, s4, s5, s6, s7, s8};
+      for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = (double)sv[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// k_fd: advection half-step, phi and c updates, centre-of-mass partials.  MODE 0: step, 1: + stages.
+template <typename T, int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_fd(int parity, const TileDev* __restrict__ tiles,
+                                                 const InstDev* __restrict__ insts, T* __restrict__ buf,
+                                                 const DropDev* __restrict__ drops, double* __restrict__ part,
+                                                 uint64_t* __restrict__ mask, const int64_t* __restrict__ step,
+                                                 double* __restrict__ dbg, int dbg_inst) {
+  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int W3 = TX + 6, H3 = TY + 6, W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  __shared__ T s_phi[W3 * H3], s_c[W3 * H3], s_ux[W3 * H3], s_uy[W3 * H3];
+  __shared__ T s_ph[W2 * H2], s_ch[W2 * H2];
+  __shared__ T s_M[W1 * H1], s_Xh[W1 * H1];
+  __shared__ int s_col[W3], s_row[H3];
+  __shared__ DropShared sh;
+
+  const TileDev td = tiles[blockIdx.x];
+  if (td.inst < 0) return;
+  if (MODE == 1 && td.inst != dbg_inst) return;
+  const InstDev& I = insts[td.inst];
+  const int nx = I.nx, ny = I.ny, pitch = I.pitch;
+  const int tid = threadIdx.x;
+  const T* __restrict__ phi = buf + I.off_phi[parity];
+  const T* __restrict__ cc = buf + I.off_c[parity];
+  const T* __restrict__ gux = buf + I.off_ux;
+  const T* __restrict__ guy = buf + I.off_uy;
+  T* __restrict__ phi_out = buf + I.off_phi[parity ^ 1];
+  T* __restrict__ c_out = buf + I.off_c[parity ^ 1];
+
+  for (int i = tid; i < W3; i += NTHREADS) s_col[i] = wrap_idx(td.x0 + i - 3, nx);
+  for (int i = tid; i < H3; i += NTHREADS) s_row[i] = wrap_idx(td.y0 + i - 3, ny);
+  __syncthreads();
+  for (int idx = tid; idx < W3 * H3; idx += NTHREADS) {
+    const int ly = idx / W3, lx = idx - ly * W3;
+    const int64_t g = (int64_t)s_row[ly] * pitch + s_col[lx];
+    s_phi[idx] = phi[g];
+    s_c[idx] = cc[g];
+    s_ux[idx] = gux[g];
+    s_uy[idx] = guy[g];
+  }
+  __syncthreads();
+
+  // S7: advection half-step with u^n (Eqs. 16-17) on the tile plus two rings
+  const int adv = I.advection;
+  for (int idx = tid; idx < W2 * H2; idx += NTHREADS) {
+    const int ly = idx / W2, lx = idx - ly * W2;
+    const int i3 = (ly + 1) * W3 + (lx + 1);
+    s_ph[idx] = advect(s_phi, s_ux, s_uy, i3, W3, adv);
+    s_ch[idx] = advect(s_c, s_ux, s_uy, i3, W3, adv);
+  }
+  __syncthreads();
+
+  // S8 bracket M of Eq. (18) and S9 X^{n+1/2} on the tile plus one ring
+  const T a = T(I.a), b = T(I.b), B0 = T(I.B0), B1 = T(I.B1), halfB1 = T(I.halfB1);
+  for (int idx = tid; idx < W1 * H1; idx += NTHREADS) {
+    const int ly = idx / W1, lx = idx - ly * W1;
+    const int i2 = (ly + 1) * W2 + (lx + 1), i3 = (ly + 2) * W3 + (lx + 2);
+    T gphx, gphy, gchx, gchy;
+    grad9(s_ph, i2, W2, gphx, gphy);
+    grad9(s_ch, i2, W2, gchx, gchy);
+    const T lph = lap9(s_ph, i2, W2);
+    const T pn = s_phi[i3];
+    const T Bh = B0 + B1 * s_ch[i2];
+    s_M[idx] = ((a * s_ph[i2] + b * (pn * pn * pn)) - Bh * lph) - B1 * (gchx * gphx + gchy * gphy);
+    s_Xh[idx] = halfB1 * (gphx * gphx + gphy * gphy);
+  }
+  const int bx1 = min(td.x0 + TX, nx) - 1, by1 = min(td.y0 + TY, ny) - 1;
+  if (I.ndrop > 0) {
+    cull_droplets(I, drops, td.x0, bx1, td.y0, by1, sh);  // contains barriers
+  } else {
+    if (tid == 0) sh.n_near = sh.n_src = 0;
+    __syncthreads();
+  }
+
+  const T Gamma = T(I.Gamma), D = T(I.D), gam = T(I.gamma), c0 = T(I.c0);
+  const double tn = (double)(*step);
+  const double A = I.A0 * (tn < I.t_star ? tn : I.t_star);
+  const int64_t nplane = (int64_t)nx * ny;
+  int kd[NPT];
+  double vv[NPT], vx[NPT], vy[NPT];
+  for (int j = 0; j < NPT; ++j) {
+    kd[j] = -1;
+    vv[j] = vx[j] = vy[j] = 0.0;
+    const int idx = tid + j * NTHREADS;
+    const int ly = idx / TX, lx = idx - ly * TX;
+    const int x = td.x0 + lx, y = td.y0 + ly;
+    if (x >= nx || y >= ny) continue;
+    const int i1 = (ly + 1) * W1 + (lx + 1), i2 = (ly + 2) * W2 + (lx + 2);
+    // S8: phi^{n+1} = phi^{n+1/2} + Gamma lap M (Eq. 18)
+    const T phn = s_ph[i2] + Gamma * lap9(s_M, i1, W1);
+    // S9: c^{n+1} (Eq. 19), log-free flux D lap c + div(D c grad X)
+    const T ch = s_ch[i2];
+    const T lch = lap9(s_ch, i2, W2);
+    const T dv = div9(s_ch, i2, W2, D, s_Xh, i1, W1);
+    const double src = A * (double)source_count(I, drops, sh, (double)x, (double)y);
+    const T cn = (((ch + D * lch) + dv) - gam * (ch - c0)) + T(src);
+    const int64_t o = (int64_t)y * pitch + x;
+    phi_out[o] = phn;
+    c_out[o] = cn;
+    // S10 contributions: phi^{n+1} >= 0, nearest previous centre
+    const double v = (double)phn;
+    if (v >= 0.0 && I.ndrop > 0) {
+      const int k = nearest_drop(I, drops, sh, (double)x, (double)y);
+      const DropDev d = drops[I.drop_base + k];
+      kd[j] = k;
+      vv[j] = v;
+      vx[j] = v * minimg((double)x - d.x, (double)nx);
+      vy[j] = v * minimg((double)y - d.y, (double)ny);
+    }
+    if (MODE == 1) {
+      const int64_t q = (int64_t)y * nx + x;
+      dbg[7 * nplane + q] = (double)s_ph[i2];
+      dbg[8 * nplane + q] = (double)ch;
+      dbg[9 * nplane + q] = (double)s_M[i1];
+      dbg[10 * nplane + q] = (double)s_Xh[i1];
+      dbg[11 * nplane + q] = (double)phn;
+      dbg[12 * nplane + q] = (double)cn;
+    }
+  }
+  if (MODE == 0 && I.ndrop > 0)
+    tile_cm_sums(I, td.t - I.tile_base, td.t, kd, vv, vx, vy, sh, part, mask);
+}
+
+// Centre-of-mass partials of the current phi (the first pass at initialisation).
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_cm_partials(int parity, const TileDev* __restrict__ tiles,
+                                                          const InstDev* __restrict__ insts,
+                                                          const T* __restrict__ buf,
+                                                          const DropDev* __restrict__ drops,
+                                                          double* __restrict__ part,
+                                                          uint64_t* __restrict__ mask) {
+  __shared__ DropShared sh;
+  const TileDev td = tiles[blockIdx.x];
+  if (td.inst < 0) return;
+  const InstDev& I = insts[td.inst];
+  if (I.ndrop == 0) return;
+  const int nx = I.nx, ny = I.ny;
+  const int bx1 = min(td.x0 + TILE_X, nx) - 1, by1 = min(td.y0 + TILE_Y, ny) - 1;
+  cull_droplets(I, drops, td.x0, bx1, td.y0, by1, sh);
+  const T* __restrict__ phi = buf + I.off_phi[parity];
+  int kd[NPT];
+  double vv[NPT], vx[NPT], vy[NPT];
+  for (int j = 0; j < NPT; ++j) {
+    kd[j] = -1;
+    vv[j] = vx[j] = vy[j] = 0.0;
+    const int idx = threadIdx.x + j * NTHREADS;
+    const int ly = idx / TILE_X, lx = idx - ly * TILE_X;
+    const int x = td.x0 + lx, y = td.y0 + ly;
+    if (x >= nx || y >= ny) continue;
+    const double v = (double)phi[(int64_t)y * I.pitch + x];
+    if (v >= 0.0) {
+      const int k = nearest_drop(I, drops, sh, (double)x, (double)y);
+      const DropDev d = drops[I.drop_base + k];
+      kd[j] = k;
+      vv[j] = v;
+      vx[j] = v * minimg((double)x - d.x, (double)nx);
+      vy[j] = v * minimg((double)y - d.y, (double)ny);
+    }
+  }
+  tile_cm_sums(I, td.t - I.tile_base, td.t, kd, vv, vx, vy, sh, part, mask);
+}
+
+// One workgroup per droplet: fixed-order sum of the tile partials, new centre of mass (Sec. 4).
+__global__ __launch_bounds__(NTHREADS) void k_reduce(int ndrop_total, const InstDev* __restrict__ insts,
+                                                     DropDev* __restrict__ drops,
+                                                     const double* __restrict__ part,
+                                                     const uint64_t* __restrict__ mask,
+                                                     int64_t* __restrict__ step, int increment) {
+  __shared__ double red[NTHREADS / 64];
+  const int g = blockIdx.x;
+  if (g == 0 && threadIdx.x == 0 && increment) *step = *step + 1;
+  if (g >= ndrop_total) return;
+  const DropDev d = drops[g];
+  const InstDev& I = insts[d.inst];
+  const int k = g - I.drop_base;
+  const int ntl = I.tiles_x * I.tiles_y;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int tl = threadIdx.x; tl < ntl; tl += NTHREADS) {
+    const int64_t t = I.tile_base + tl;
+    if ((mask[t * MASK_WORDS + (k >> 6)] >> (k & 63)) & 1ull) {
+      const double* p = part + I.part_base + ((int64_t)tl * I.ndrop + k) * 3;
+      a0 += p[0];
+      a1 += p[1];
+      a2 += p[2];
+    }
+  }
+  const double s0 = block_reduce(a0, red, OpAdd());
+  const double s1 = block_reduce(a1, red, OpAdd());
+  const double s2 = block_reduce(a2, red, OpAdd());
+  if (threadIdx.x == 0 && s0 > 0.0) {
+    drops[g].x = wrapd(d.x + s1 / s0, (double)I.nx);
+    drops[g].y = wrapd(d.y + s2 / s0, (double)I.ny);
+  }
+}
+
+// Observables of the current state from the n, u planes written by k_lb<MODE 2>:
+// per-tile {mass, sum phi, sum c, min B, max |u|, nonfinite, per droplet (phi, phi ux, phi uy)}.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_obs(int parity, const TileDev* __restrict__ tiles,
+                                                  const InstDev* __restrict__ insts, const T* __restrict__ buf,
+                                                  const DropDev* __restrict__ drops,
+                                                  double* __restrict__ out, int stride) {
+  __shared__ DropShared sh;
+  const TileDev td = tiles[blockIdx.x];
+  if (td.inst < 0) return;
+  const InstDev& I = insts[td.inst];
+  const int nx = I.nx, ny = I.ny, pitch = I.pitch;
+  const int64_t plane = (int64_t)ny * pitch;
+  const int bx1 = min(td.x0 + TILE_X, nx) - 1, by1 = min(td.y0 + TILE_Y, ny) - 1;
+  if (I.ndrop > 0) {
+    cull_droplets(I, drops, td.x0, bx1, td.y0, by1, sh);
+  } else {
+    if (threadIdx.x == 0) sh.n_near = sh.n_src = 0;
+    __syncthreads();
+  }
+  const T* __restrict__ phi = buf + I.off_phi[parity];
+  const T* __restrict__ cc = buf + I.off_c[parity];
+  const T* __restrict__ fst = buf + I.off_f[parity];
+  double m = 0.0, sp = 0.0, sc = 0.0, mb = 1e300, mu = 0.0, nf = 0.0;
+  int kd[NPT];
+  double vv[NPT], vx[NPT], vy[NPT];
+  for (int j = 0; j < NPT; ++j) {
+    kd[j] = -1;
+    vv[j] = vx[j] = vy[j] = 0.0;
+    const int idx = threadIdx.x + j * NTHREADS;
+    const int ly = idx / TILE_X, lx = idx - ly * TILE_X;
+    const int x = td.x0 + lx, y = td.y0 + ly;
+    if (x >= nx || y >= ny) continue;
+    const int64_t o = (int64_t)y * pitch + x;
+    const double p = (double)phi[o], c = (double)cc[o];
+    const double n = (double)buf[I.off_n + o];
+    const double u = (double)buf[I.off_ux + o], v = (double)buf[I.off_uy + o];
+    m += n;
+    sp += p;
+    sc += c;
+    mb = fmin(mb, I.B0 + I.B1 * c);
+    mu = fmax(mu, sqrt(u * u + v * v));
+    bool fin = isfinite(p) && isfinite(c);
+    for (int i = 0; i < 9; ++i) fin = fin && isfinite((double)fst[i * plane + o]);
+    if (!fin) nf = 1.0;
+    if (p >= 0.0 && I.ndrop > 0) {
+      const int k = nearest_drop(I, drops, sh, (double)x, (double)y);
+      kd[j] = k;
+      vv[j] = p;
+      vx[j] = p * u;
+      vy[j] = p * v;
+    }
+  }
+  double* o = out + (int64_t)td.t * stride;
+  const double r0 = block_reduce(m, sh.red, OpAdd());
+  const double r1 = block_reduce(sp, sh.red, OpAdd());
+  const double r2 = block_reduce(sc, sh.red, OpAdd());
+  const double r3 = block_reduce(mb, sh.red, OpMin());
+  const double r4 = block_reduce(mu, sh.red, OpMax());
+  const double r5 = block_reduce(nf, sh.red, OpMax());
+  if (threadIdx.x == 0) {
+    o[0] = r0;
+    o[1] = r1;
+    o[2] = r2;
+    o[3] = r3;
+    o[4] = r4;
+    o[5] = r5;
+  }
+  for (int k = 0; k < I.ndrop; ++k) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int j = 0; j < NPT; ++j)
+      if (kd[j] == k) {
+        a0 += vv[j];
+        a1 += vx[j];
+        a2 += vy[j];
+      }
+    const double s0 = block_reduce(a0, sh.red, OpAdd());
+    const double s1 = block_reduce(a1, sh.red, OpAdd());
+    const double s2 = block_reduce(a2, sh.red, OpAdd());
+    if (threadIdx.x == 0) {
+      o[6 + 3 * k] = s0;
+      o[7 + 3 * k] = s1;
+      o[8 + 3 * k] = s2;
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_lb(hipStream_t s, int mode, int parity, int ntiles_launch, const TileDev* tiles,
+                     const InstDev* inst, T* buf, double* dbg, int dbg_inst) {
+  if (ntiles_launch <= 0) return hipSuccess;
+  dim3 grid(ntiles_launch), block(NTHREADS);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_lb<T, 0>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_lb<T, 1>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
+  else
+    hipLaunchKernelGGL((k_lb<T, 2>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fd(hipStream_t s, int mode, int parity, int ntiles_launch, const TileDev* tiles,
+                     const InstDev* inst, T* buf, const DropDev* drops, double* part, uint64_t* mask,
+                     const int64_t* step, double* dbg, int dbg_inst) {
+  if (ntiles_launch <= 0) return hipSuccess;
+  dim3 grid(ntiles_launch), block(NTHREADS);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_fd<T, 0>), grid, block, 0, s, parity, tiles, inst, buf, drops, part, mask, step,
+                       dbg, dbg_inst);
+  else
+    hipLaunchKernelGGL((k_fd<T, 1>), grid, block, 0, s, parity, tiles, inst, buf, drops, part, mask, step,
+                       dbg, dbg_inst);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cm_partials(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
+                              const InstDev* inst, T* buf, const DropDev* drops, double* part,
+                              uint64_t* mask) {
+  if (ntiles_launch <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_cm_partials<T>), dim3(ntiles_launch), dim3(NTHREADS), 0, s, parity, tiles, inst,
+                     buf, drops, part, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(hipStream_t s, int ndrop_total, const InstDev* inst, DropDev* drops,
+                         const double* part, const uint64_t* mask, int64_t* step, int increment) {
+  hipLaunchKernelGGL(k_reduce, dim3(ndrop_total > 0 ? ndrop_total : 1), dim3(NTHREADS), 0, s, ndrop_total,
+                     inst, drops, part, mask, step, increment);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
+                      const InstDev* inst, T* buf, const DropDev* drops, double* obs_part, int obs_stride) {
+  if (ntiles_launch <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_obs<T>), dim3(ntiles_launch), dim3(NTHREADS), 0, s, parity, tiles, inst, buf, drops,
+                     obs_part, obs_stride);
+  return hipGetLastError();
+}
+
+#define LBM_INSTANTIATE(T)                                                                                \
+  template hipError_t launch_lb<T>(hipStream_t, int, int, int, const TileDev*, const InstDev*, T*,        \
+                                   double*, int);                                                         \
+  template hipError_t launch_fd<T>(hipStream_t, int, int, int, const TileDev*, const InstDev*, T*,        \
+                                   const DropDev*, double*, uint64_t*, const int64_t*, double*, int);     \
+  template hipError_t launch_cm_partials<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,    \
+                                            const DropDev*, double*, uint64_t*);                          \
+  template hipError_t launch_obs<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,            \
+                                    const DropDev*, double*, int);
+
+LBM_INSTANTIATE(double)
+LBM_INSTANTIATE(float)
+
+}  // namespace lbm
