@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled lattice-Boltzmann + finite-difference timestep on one MI355X.
+
+Default workload: the 2048 x 2048 periodic dilute emulsion (64 active droplets, R = 20), FP64 -- the
+configuration on which the HBM-roofline figure is quoted.  Variants in the same JSON line: the same
+lattice in FP32, and the batched two-droplet sweep (32 lattices from 256 x 256 to 512 x 256, FP32) in one
+launch sequence under hipGraph replay.
+
+Timing: W warm-up steps, then exactly K steps bracketed by torch.cuda.synchronize() and hipEvents recorded
+on the library's stream.  MLUPS = lattice nodes x K / seconds / 1e6.  The roofline figure of the dominant
+kernel uses its algorithmic bytes per launch (one read and one write of each value it must move) over its
+average launch duration, measured with hipEvents around each launch of that kernel.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "MLUPS of coupled LB+FD step and % HBM roofline, FP64 vs FP32 vs batched"
+
+# Algorithmic values moved per lattice node by each kernel of the timestep (element size x count).
+#   k_step (fused): reads 9 populations + phi + c, writes the same          -> 22 values
+#   k_lb (split):   reads 9 populations + phi + c, writes 9 populations + ux + uy -> 22 values
+#   k_fd (split):   reads phi + c + ux + uy, writes phi + c                   ->  6 values
+#   whole step, state only (9 populations + phi + c read and written)        -> 22 values
+VALUES_PER_NODE = {"k_step": 22, "k_lb": 22, "k_fd": 6, "step": 22}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1711_10984_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source (null otherwise)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if data.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    ent = data.get("entries", {}).get(f"{kernel}:{workload}:{precision}")
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def build_sim(workloads, precision, graph_steps, path):
+    from paper_1711_10984_amd import lbm
+    return lbm.Sim([w.param_dict() for w in workloads], [w.phi0 for w in workloads], [w.c0 for w in workloads],
+                   [w.drop_dicts() for w in workloads], precision=precision, graph_steps=graph_steps, path=path)
+
+
+def time_steps(sim, steps, warmup):
+    import torch
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    return ms, wall
+
+
+def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=0):
+    from paper_1711_10984_amd import lbm
+    sim = build_sim(workloads, precision, graph_steps, path)
+    nodes = sum(w.nodes for w in workloads)
+    ms, wall = time_steps(sim, steps, warmup)
+    obs = sim.observables(0)
+    per_kernel = sim.time_kernels(prof_steps)  # hipEvents around each launch on the library's stream
+    sim.close()
+    elem = 8 if precision == lbm.LBM_FP64 else 4
+    mlups = nodes * steps / (ms * 1e-3) / 1e6
+    dom = max((k for k in per_kernel if k in VALUES_PER_NODE), key=lambda k: per_kernel[k])
+    alg_bytes = VALUES_PER_NODE[dom] * elem * nodes
+    achieved = alg_bytes / (per_kernel[dom] * 1e-3) / 1e9
+    step_bytes = VALUES_PER_NODE["step"] * elem * nodes
+    step_gbs = step_bytes / (ms * 1e-3 / steps) / 1e9
+    prec = "fp64" if precision == lbm.LBM_FP64 else "fp32"
+    traffic = measured_traffic(dom, label, prec)
+    return {
+        "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
+        "kernel_ms": per_kernel,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": per_kernel[dom]},
+        "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved": round(step_gbs, 1),
+                          "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+        "sanity": {"mass": obs["mass"], "sum_phi": obs["sum_phi"], "min_B": obs["min_B"], "max_u": obs["max_u"],
+                   "unstable": obs["unstable"]},
+    }
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle as it stands on this host's cores, on a bounded sample of the same workload."""
+    from oracle import OracleSim, Params, Drop
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = OracleSim(Params(nx=w.nx, ny=w.ny, **w.params), w.phi0, w.c0, [Drop(**d) for d in w.drop_dicts()])
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        s.run(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 1000:
+            break
+    return {"value": round(w.nodes * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{w.name}: {steps} FP64 steps of the full {w.nx}x{w.ny} lattice in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--prof-steps", type=int, default=50, help="steps timed per kernel with hipEvents")
+    ap.add_argument("--no-variants", action="store_true", help="FP64 2048^2 only")
+    ap.add_argument("--path", type=int, default=0, help="0: fused sweep kernel, 1: split LB + FD kernels")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device copy (reference for rocprofv3 counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the timestep is a single-GPU kernel; the "
+              "multi-GPU decomposition is a design note, not code) -- use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1711_10984_amd import lbm, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    lbm.load_library()
+    if args.copy_calibration:
+        a = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    c5 = W.c5_emulsion()
+    main_res = measure([c5], lbm.LBM_FP64, args.steps, args.warmup, args.graph_steps, "c5", args.prof_steps,
+                       args.path)
+    variants = {}
+    if not args.no_variants:
+        variants["fp32_2048"] = measure([c5], lbm.LBM_FP32, args.steps, args.warmup, args.graph_steps, "c5",
+                                        args.prof_steps, args.path)
+        variants["batched_c3_fp32"] = measure(W.c3_batch(), lbm.LBM_FP32, args.steps, args.warmup,
+                                              args.graph_steps, "c3", args.prof_steps, args.path)
+    for v in variants.values():
+        v["gain_over_fp64"] = round(v["mlups"] / main_res["mlups"], 3)
+    out = {
+        "metric": METRIC,
+        "value": round(main_res["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2048x2048 periodic dilute emulsion, 64 active droplets R=20 (seeded), FP64",
+                   "nx": 2048, "ny": 2048, "droplets": 64, "graph_steps": args.graph_steps,
+                   "kernel_path": "fused" if args.path == 0 else "split"},
+        "roofline": main_res["roofline"],
+        "step_roofline": main_res["step_roofline"],
+        "kernel_ms": main_res["kernel_ms"],
+        "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
+                         "nodes": v["nodes"], "precision": v["precision"], "gain_over_fp64": v["gain_over_fp64"],
+                         "roofline": v["roofline"], "step_roofline": v["step_roofline"],
+                         "kernel_ms": v["kernel_ms"]} for k, v in variants.items()},
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c5, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

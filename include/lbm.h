@@ -53,6 +53,9 @@ extern "C" {
 #define LBM_ADV_PAPER 0 /* advection half-step of Eqs. (16)-(17) as printed */
 #define LBM_ADV_FLUX 1  /* conservative face-upwind flux form of the same half-step */
 
+#define LBM_PATH_FUSED 0 /* one sweeping kernel per step (default) */
+#define LBM_PATH_SPLIT 1 /* lattice-Boltzmann kernel, then finite-difference kernel (reference layout) */
+
 #define LBM_MAXDROP 256 /* droplets per instance */
 #define LBM_NSTAGE 22   /* planes written by lbm_debug_stage */
 
@@ -154,14 +157,18 @@ int lbm_droplets(lbm_ctx* ctx, int32_t inst, lbm_droplet* out);
  * streaming).  Instances of at most 512 x 512 nodes (LBM_E_INVAL otherwise).  Synchronous. */
 int lbm_debug_stage(lbm_ctx* ctx, int32_t inst, double* out);
 
-/* Average device time per launch (ms) of each kernel of the timestep over n eagerly launched
- * steps, measured with hipEvents on the context's stream.  ms_out[0] = lattice-Boltzmann kernel,
- * ms_out[1] = finite-difference kernel, ms_out[2] = centre-of-mass reduction.  Advances the state
- * by n steps.  Synchronous. */
+/* Kernel sequence used by lbm_step and lbm_debug_stage: LBM_PATH_FUSED (default) or LBM_PATH_SPLIT.
+ * Both compute the same arithmetic; the split path stores u^n between its two kernels. */
+int lbm_set_path(lbm_ctx* ctx, int32_t path);
+int32_t lbm_get_path(const lbm_ctx* ctx);
+
+/* Average device time per launch (ms) of each kernel of the timestep over n eagerly launched steps,
+ * measured with hipEvents on the context's stream.  Fused path: ms_out = {k_step, k_reduce, 0};
+ * split path: {k_lb, k_fd, k_reduce}.  Advances the state by n steps.  Synchronous. */
 int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
 
-/* Kernel names for ms_out entries of lbm_time_kernels (static strings). */
-const char* lbm_kernel_name(int32_t which);
+/* Name of kernel `which` (0..2) of lbm_time_kernels for a path (static string, "" if none). */
+const char* lbm_kernel_name(int32_t path, int32_t which);
 
 /* Release the context (graphs, events, host bookkeeping).  The workspace is not freed. */
 void lbm_destroy(lbm_ctx* ctx);

@@ -45,10 +45,11 @@ struct Layout {
   int prec = 0;
   size_t elem = 8;
   std::vector<InstDev> inst;
-  std::vector<TileDev> tiles;  // launch order (XCD-aware), padded with inst = -1
-  int ntiles = 0, ndrop_total = 0, max_nd = 0, obs_stride = 0;
+  std::vector<TileDev> tiles;  // split-kernel tiles in launch order (XCD-aware), padded with inst = -1
+  std::vector<TileDev> segs;   // fused-kernel strips in launch order
+  int ntiles = 0, nsegs = 0, ndrop_total = 0, max_nd = 0, obs_stride = 0;
   int64_t max_nodes = 0;
-  size_t off_pool = 0, off_inst = 0, off_tiles = 0, off_drops = 0, off_part = 0, off_mask = 0,
+  size_t off_pool = 0, off_inst = 0, off_tiles = 0, off_segs = 0, off_drops = 0, off_part = 0, off_mask = 0,
          off_step = 0, off_obs = 0, off_dbg = 0, total = 0;
 };
 
@@ -82,8 +83,8 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
   L.elem = L.prec == LBM_FP64 ? 8 : 4;
   const size_t row_align = ALIGN / L.elem;
   int64_t pool_elems = 0;
-  int tile_base = 0, drop_base = 0;
-  int64_t part_elems = 0;
+  int tile_base = 0, seg_base = 0, drop_base = 0;
+  int64_t part_elems = 0, part_elems1 = 0;
   L.inst.resize(ninst);
   for (int i = 0; i < ninst; ++i) {
     const lbm_config& c = cfgs[i];
@@ -93,9 +94,12 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.ny = c.ny;
     d.pitch = (int32_t)align_up((size_t)c.nx, row_align);
     d.ndrop = ndrop[i];
-    d.tiles_x = (c.nx + TILE_X - 1) / TILE_X;
-    d.tiles_y = (c.ny + TILE_Y - 1) / TILE_Y;
-    d.tile_base = tile_base;
+    d.tiles_x[TILING_SPLIT] = (c.nx + TILE_X - 1) / TILE_X;
+    d.tiles_y[TILING_SPLIT] = (c.ny + TILE_Y - 1) / TILE_Y;
+    d.tile_base[TILING_SPLIT] = tile_base;
+    d.tiles_x[TILING_FUSED] = (c.nx + FUSED_TX - 1) / FUSED_TX;
+    d.tiles_y[TILING_FUSED] = (c.ny + FUSED_SY - 1) / FUSED_SY;
+    d.tile_base[TILING_FUSED] = seg_base;
     d.drop_base = drop_base;
     const int64_t plane = (int64_t)c.ny * d.pitch;
     int64_t o = pool_elems;
@@ -109,8 +113,10 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.off_uy = o;    o += plane;
     d.off_n = o;     o += plane;
     pool_elems = o;
-    d.part_base = part_elems;
-    part_elems += (int64_t)d.tiles_x * d.tiles_y * d.ndrop * 3;
+    d.part_base[TILING_SPLIT] = part_elems;
+    part_elems += (int64_t)d.tiles_x[TILING_SPLIT] * d.tiles_y[TILING_SPLIT] * d.ndrop * 3;
+    d.part_base[TILING_FUSED] = part_elems1;
+    part_elems1 += (int64_t)d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED] * d.ndrop * 3;
     d.advection = c.advection;
     d.a = c.a;
     d.b = c.b;
@@ -125,38 +131,45 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.coef = 1.0 - 1.0 / (2.0 * c.tau);
     d.A0 = c.A0;
     d.t_star = c.t_star;
-    tile_base += d.tiles_x * d.tiles_y;
+    tile_base += d.tiles_x[TILING_SPLIT] * d.tiles_y[TILING_SPLIT];
+    seg_base += d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED];
     drop_base += d.ndrop;
     L.max_nd = std::max(L.max_nd, (int)d.ndrop);
     L.max_nodes = std::max(L.max_nodes, (int64_t)c.nx * c.ny);
   }
   L.ntiles = tile_base;
+  L.nsegs = seg_base;
   L.ndrop_total = drop_base;
   L.obs_stride = 6 + 3 * L.max_nd;
-  // Tile list in launch order: workgroup b runs on XCD (b mod 8); give each XCD a contiguous run of
+  // Work lists in launch order: workgroup b runs on XCD (b mod 8); give each XCD a contiguous run of
   // tiles (raster order within an instance) so that neighbouring tiles share that XCD's L2.
-  std::vector<TileDev> natural;
-  natural.reserve(L.ntiles);
-  for (int i = 0; i < ninst; ++i) {
-    const InstDev& d = L.inst[i];
-    for (int ty = 0; ty < d.tiles_y; ++ty)
-      for (int tx = 0; tx < d.tiles_x; ++tx)
-        natural.push_back(TileDev{i, tx * TILE_X, ty * TILE_Y, (int32_t)natural.size()});
-  }
-  const int nx8 = 8;
-  const int chunk = (L.ntiles + nx8 - 1) / nx8;
-  L.tiles.assign((size_t)chunk * nx8, TileDev{-1, 0, 0, -1});
-  for (int t = 0; t < L.ntiles; ++t) {
-    const int xcd = t / chunk, m = t % chunk;
-    L.tiles[(size_t)m * nx8 + xcd] = natural[t];
-  }
+  auto build_list = [&](int tiling, int tw, int th, int count, std::vector<TileDev>& out) {
+    std::vector<TileDev> natural;
+    natural.reserve(count);
+    for (int i = 0; i < ninst; ++i) {
+      const InstDev& d = L.inst[i];
+      for (int ty = 0; ty < d.tiles_y[tiling]; ++ty)
+        for (int tx = 0; tx < d.tiles_x[tiling]; ++tx)
+          natural.push_back(TileDev{i, tx * tw, ty * th, (int32_t)natural.size()});
+    }
+    const int nxcd = 8;
+    const int chunk = (count + nxcd - 1) / nxcd;
+    out.assign((size_t)chunk * nxcd, TileDev{-1, 0, 0, -1});
+    for (int t = 0; t < count; ++t) out[(size_t)(t % chunk) * nxcd + t / chunk] = natural[t];
+  };
+  build_list(TILING_SPLIT, TILE_X, TILE_Y, L.ntiles, L.tiles);
+  build_list(TILING_FUSED, FUSED_TX, FUSED_SY, L.nsegs, L.segs);
   size_t off = 0;
   L.off_pool = off;  off = align_up(off + (size_t)pool_elems * L.elem, ALIGN);
   L.off_inst = off;  off = align_up(off + sizeof(InstDev) * ninst, ALIGN);
   L.off_tiles = off; off = align_up(off + sizeof(TileDev) * L.tiles.size(), ALIGN);
+  L.off_segs = off;  off = align_up(off + sizeof(TileDev) * L.segs.size(), ALIGN);
   L.off_drops = off; off = align_up(off + sizeof(DropDev) * std::max(1, L.ndrop_total), ALIGN);
-  L.off_part = off;  off = align_up(off + sizeof(double) * std::max<int64_t>(1, part_elems), ALIGN);
-  L.off_mask = off;  off = align_up(off + sizeof(uint64_t) * MASK_WORDS * (size_t)L.ntiles, ALIGN);
+  // the two tilings share the partials and masks (one of them is in use at a time)
+  L.off_part = off;
+  off = align_up(off + sizeof(double) * std::max<int64_t>(1, std::max(part_elems, part_elems1)), ALIGN);
+  L.off_mask = off;
+  off = align_up(off + sizeof(uint64_t) * MASK_WORDS * (size_t)std::max(L.ntiles, L.nsegs), ALIGN);
   L.off_step = off;  off = align_up(off + sizeof(int64_t), ALIGN);
   L.off_obs = off;   off = align_up(off + sizeof(double) * (size_t)L.obs_stride * L.ntiles, ALIGN);
   L.off_dbg = off;
@@ -174,12 +187,14 @@ struct lbm_ctx {
   int parity = 0;
   int64_t step = 0;
   int graph_steps = 0;
+  int path = LBM_PATH_FUSED;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   hipGraph_t graph[2] = {nullptr, nullptr};
 
   void* pool() const { return ws + L.off_pool; }
   InstDev* d_inst() const { return reinterpret_cast<InstDev*>(ws + L.off_inst); }
   TileDev* d_tiles() const { return reinterpret_cast<TileDev*>(ws + L.off_tiles); }
+  TileDev* d_segs() const { return reinterpret_cast<TileDev*>(ws + L.off_segs); }
   DropDev* d_drops() const { return reinterpret_cast<DropDev*>(ws + L.off_drops); }
   double* d_part() const { return reinterpret_cast<double*>(ws + L.off_part); }
   uint64_t* d_mask() const { return reinterpret_cast<uint64_t*>(ws + L.off_mask); }
@@ -187,6 +202,7 @@ struct lbm_ctx {
   double* d_obs() const { return reinterpret_cast<double*>(ws + L.off_obs); }
   double* d_dbg() const { return reinterpret_cast<double*>(ws + L.off_dbg); }
   int nlaunch() const { return (int)L.tiles.size(); }
+  int nseglaunch() const { return (int)L.segs.size(); }
 };
 
 namespace {
@@ -194,13 +210,21 @@ namespace {
 template <typename T>
 hipError_t enqueue_step(lbm_ctx* c, int parity) {
   T* buf = reinterpret_cast<T*>(c->pool());
-  hipError_t e = launch_lb<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+  hipError_t e;
+  if (c->path == LBM_PATH_FUSED) {
+    e = launch_step<T>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(), c->d_part(),
+                       c->d_mask(), c->d_step(), nullptr, -1);
+    if (e != hipSuccess) return e;
+    return launch_reduce(c->stream, TILING_FUSED, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(),
+                         c->d_mask(), c->d_step(), 1);
+  }
+  e = launch_lb<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
   if (e != hipSuccess) return e;
   e = launch_fd<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
                    c->d_part(), c->d_mask(), c->d_step(), nullptr, -1);
   if (e != hipSuccess) return e;
-  return launch_reduce(c->stream, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
-                       c->d_step(), 1);
+  return launch_reduce(c->stream, TILING_SPLIT, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(),
+                       c->d_mask(), c->d_step(), 1);
 }
 
 hipError_t enqueue_step_any(lbm_ctx* c, int parity) {
@@ -337,6 +361,53 @@ int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, do
   return LBM_OK;
 }
 
+// Stage planes of the next step of instance `inst` from the kernels of the current path.
+template <typename T>
+hipError_t debug_launch(lbm_ctx* c, int inst) {
+  T* buf = reinterpret_cast<T*>(c->pool());
+  if (c->path == LBM_PATH_FUSED)
+    return launch_step<T>(c->stream, c->parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(),
+                          c->d_part(), c->d_mask(), c->d_step(), c->d_dbg(), inst);
+  hipError_t e = launch_lb<T>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
+  if (e != hipSuccess) return e;
+  return launch_fd<T>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
+                      c->d_mask(), c->d_step(), c->d_dbg(), inst);
+}
+
+// One eager step with hipEvents between its kernels: ev[0..nk] bracket nk launches.
+template <typename T>
+hipError_t timed_step(lbm_ctx* c, hipEvent_t* ev, int* nk) {
+  T* buf = reinterpret_cast<T*>(c->pool());
+  const int p = c->parity;
+  hipError_t e;
+  (void)hipEventRecord(ev[0], c->stream);
+  if (c->path == LBM_PATH_FUSED) {
+    e = launch_step<T>(c->stream, p, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(), c->d_part(),
+                       c->d_mask(), c->d_step(), nullptr, -1);
+    (void)hipEventRecord(ev[1], c->stream);
+    if (e == hipSuccess)
+      e = launch_reduce(c->stream, TILING_FUSED, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
+                        c->d_step(), 1);
+    (void)hipEventRecord(ev[2], c->stream);
+    *nk = 2;
+  } else {
+    e = launch_lb<T>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+    (void)hipEventRecord(ev[1], c->stream);
+    if (e == hipSuccess)
+      e = launch_fd<T>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
+                       c->d_mask(), c->d_step(), nullptr, -1);
+    (void)hipEventRecord(ev[2], c->stream);
+    if (e == hipSuccess)
+      e = launch_reduce(c->stream, TILING_SPLIT, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
+                        c->d_step(), 1);
+    (void)hipEventRecord(ev[3], c->stream);
+    *nk = 3;
+  }
+  c->parity ^= 1;
+  c->step += 1;
+  return e;
+}
+
 int read_drops(lbm_ctx* c, int inst, std::vector<DropDev>& out) {
   const InstDev& d = c->L.inst[inst];
   out.resize(d.ndrop);
@@ -423,9 +494,12 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
   INIT_CHK(hipMemcpyAsync(c->d_inst(), c->L.inst.data(), sizeof(InstDev) * ninst, hipMemcpyHostToDevice, c->stream));
   INIT_CHK(hipMemcpyAsync(c->d_tiles(), c->L.tiles.data(), sizeof(TileDev) * c->L.tiles.size(), hipMemcpyHostToDevice,
                           c->stream));
+  INIT_CHK(hipMemcpyAsync(c->d_segs(), c->L.segs.data(), sizeof(TileDev) * c->L.segs.size(), hipMemcpyHostToDevice,
+                          c->stream));
   INIT_CHK(hipMemcpyAsync(c->d_drops(), dd.data(), sizeof(DropDev) * dd.size(), hipMemcpyHostToDevice, c->stream));
   INIT_CHK(hipMemcpyAsync(c->d_step(), &c->step, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-  INIT_CHK(hipMemsetAsync(c->d_mask(), 0, sizeof(uint64_t) * MASK_WORDS * c->L.ntiles, c->stream));
+  INIT_CHK(hipMemsetAsync(c->d_mask(), 0, sizeof(uint64_t) * MASK_WORDS * std::max(c->L.ntiles, c->L.nsegs),
+                          c->stream));
   // first centre-of-mass pass on phi0, started from the given centres
   if (c->L.prec == LBM_FP64)
     INIT_CHK(launch_cm_partials<double>(c->stream, 0, c->nlaunch(), c->d_tiles(), c->d_inst(),
@@ -433,8 +507,8 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
   else
     INIT_CHK(launch_cm_partials<float>(c->stream, 0, c->nlaunch(), c->d_tiles(), c->d_inst(),
                                        reinterpret_cast<float*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask()));
-  INIT_CHK(launch_reduce(c->stream, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
-                         c->d_step(), 0));
+  INIT_CHK(launch_reduce(c->stream, TILING_SPLIT, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(),
+                         c->d_mask(), c->d_step(), 0));
   INIT_CHK(hipStreamSynchronize(c->stream));
 #undef INIT_CHK
   *out = c;
@@ -523,9 +597,9 @@ int lbm_observables(lbm_ctx* c, int32_t inst, lbm_obs* obs, double* drop_out) {
                                          c->L.obs_stride);
   if (e != hipSuccess) return fail(LBM_E_HIP, std::string("observables launch: ") + hipGetErrorString(e));
   const InstDev& d = c->L.inst[inst];
-  const int nt = d.tiles_x * d.tiles_y, S = c->L.obs_stride;
+  const int nt = d.tiles_x[TILING_SPLIT] * d.tiles_y[TILING_SPLIT], S = c->L.obs_stride;
   std::vector<double> h((size_t)nt * S);
-  HIPCHK(hipMemcpyAsync(h.data(), c->d_obs() + (size_t)d.tile_base * S, h.size() * sizeof(double),
+  HIPCHK(hipMemcpyAsync(h.data(), c->d_obs() + (size_t)d.tile_base[TILING_SPLIT] * S, h.size() * sizeof(double),
                         hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   std::vector<DropDev> dd;
@@ -574,20 +648,7 @@ int lbm_debug_stage(lbm_ctx* c, int32_t inst, double* out) {
   if (!out) return fail(LBM_E_INVAL, "out must not be NULL");
   const InstDev& d = c->L.inst[inst];
   if ((int64_t)d.nx * d.ny > DEBUG_MAX_NODES) return fail(LBM_E_INVAL, "stage export is limited to 512 x 512 nodes");
-  hipError_t e;
-  if (c->L.prec == LBM_FP64) {
-    double* buf = reinterpret_cast<double*>(c->pool());
-    e = launch_lb<double>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
-    if (e == hipSuccess)
-      e = launch_fd<double>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
-                            c->d_part(), c->d_mask(), c->d_step(), c->d_dbg(), inst);
-  } else {
-    float* buf = reinterpret_cast<float*>(c->pool());
-    e = launch_lb<float>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
-    if (e == hipSuccess)
-      e = launch_fd<float>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
-                           c->d_part(), c->d_mask(), c->d_step(), c->d_dbg(), inst);
-  }
+  hipError_t e = c->L.prec == LBM_FP64 ? debug_launch<double>(c, inst) : debug_launch<float>(c, inst);
   if (e != hipSuccess) return fail(LBM_E_HIP, std::string("stage launch: ") + hipGetErrorString(e));
   const size_t n = (size_t)d.nx * d.ny;
   HIPCHK(hipMemcpyAsync(out, c->d_dbg(), sizeof(double) * LBM_NSTAGE * n, hipMemcpyDeviceToHost, c->stream));
@@ -601,43 +662,18 @@ int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
   std::vector<hipEvent_t> ev((size_t)n * 4);
   for (auto& x : ev) HIPCHK(hipEventCreate(&x));
   hipError_t e = hipSuccess;
-  for (int64_t s = 0; s < n && e == hipSuccess; ++s) {
-    hipEvent_t* E = &ev[(size_t)s * 4];
-    const int p = c->parity;
-    if (c->L.prec == LBM_FP64) {
-      double* buf = reinterpret_cast<double*>(c->pool());
-      (void)hipEventRecord(E[0], c->stream);
-      e = launch_lb<double>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
-      (void)hipEventRecord(E[1], c->stream);
-      if (e == hipSuccess)
-        e = launch_fd<double>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
-                              c->d_mask(), c->d_step(), nullptr, -1);
-    } else {
-      float* buf = reinterpret_cast<float*>(c->pool());
-      (void)hipEventRecord(E[0], c->stream);
-      e = launch_lb<float>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
-      (void)hipEventRecord(E[1], c->stream);
-      if (e == hipSuccess)
-        e = launch_fd<float>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
-                             c->d_mask(), c->d_step(), nullptr, -1);
-    }
-    (void)hipEventRecord(E[2], c->stream);
-    if (e == hipSuccess)
-      e = launch_reduce(c->stream, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(), c->d_step(), 1);
-    (void)hipEventRecord(E[3], c->stream);
-    c->parity ^= 1;
-    c->step += 1;
-  }
+  int nk = 0;
+  for (int64_t s = 0; s < n && e == hipSuccess; ++s)
+    e = c->L.prec == LBM_FP64 ? timed_step<double>(c, &ev[(size_t)s * 4], &nk) : timed_step<float>(c, &ev[(size_t)s * 4], &nk);
   hipError_t es = hipStreamSynchronize(c->stream);
   double acc[3] = {0, 0, 0};
   if (e == hipSuccess && es == hipSuccess) {
-    for (int64_t s = 0; s < n; ++s) {
-      for (int j = 0; j < 3; ++j) {
+    for (int64_t s = 0; s < n; ++s)
+      for (int j = 0; j < nk; ++j) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev[(size_t)s * 4 + j], ev[(size_t)s * 4 + j + 1]);
         acc[j] += ms;
       }
-    }
   }
   for (auto& x : ev) (void)hipEventDestroy(x);
   if (e != hipSuccess) return fail(LBM_E_HIP, std::string("timed launch: ") + hipGetErrorString(e));
@@ -646,14 +682,22 @@ int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
   return LBM_OK;
 }
 
-const char* lbm_kernel_name(int32_t which) {
-  switch (which) {
-    case 0: return "k_lb";
-    case 1: return "k_fd";
-    case 2: return "k_reduce";
-    default: return "";
-  }
+const char* lbm_kernel_name(int32_t path, int32_t which) {
+  static const char* fused[3] = {"k_step", "k_reduce", ""};
+  static const char* split[3] = {"k_lb", "k_fd", "k_reduce"};
+  if (which < 0 || which > 2) return "";
+  return path == LBM_PATH_SPLIT ? split[which] : fused[which];
 }
+
+int lbm_set_path(lbm_ctx* c, int32_t path) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  if (path != LBM_PATH_FUSED && path != LBM_PATH_SPLIT) return fail(LBM_E_INVAL, "unknown path");
+  if (path != c->path) destroy_graphs(c);
+  c->path = path;
+  return LBM_OK;
+}
+
+int32_t lbm_get_path(const lbm_ctx* c) { return c ? c->path : -1; }
 
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;

@@ -7,22 +7,32 @@
 
 namespace lbm {
 
-// Tile of interior nodes processed by one workgroup of the timestep kernels.
+// Tile of interior nodes processed by one workgroup of the split timestep kernels.
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 8;
 constexpr int NTHREADS = 256;
+// Fused kernel: a workgroup owns a strip of FUSED_TX columns and FUSED_SY rows and sweeps it row by
+// row; one wavefront (64 lanes = FUSED_TX + 10 columns) per row, FUSED_R rows per sweep iteration.
+constexpr int FUSED_LANES = 64;
+constexpr int FUSED_TX = FUSED_LANES - 10;
+constexpr int FUSED_R = 4;
+constexpr int FUSED_SY = 64;
+// Tilings: 0 = split-kernel tiles, 1 = fused-kernel strips.
+constexpr int TILING_SPLIT = 0;
+constexpr int TILING_FUSED = 1;
 constexpr int MAXDROP = 256;   // droplets per instance
 constexpr int MASK_WORDS = MAXDROP / 64;  // one presence bit per droplet and tile
 
 // Per-instance description read by every kernel (device copy in the workspace).
 struct InstDev {
   int32_t nx, ny, pitch, ndrop;
-  int32_t tiles_x, tiles_y, tile_base, drop_base;
+  int32_t tiles_x[2], tiles_y[2], tile_base[2];  // per tiling: counts and first natural index
+  int32_t drop_base, pad1;
   int64_t off_f[2];    // element offsets of the two population buffers [9][ny][pitch]
   int64_t off_phi[2];  // the two phi buffers [ny][pitch]
   int64_t off_c[2];    // the two c buffers
   int64_t off_ux, off_uy, off_n;  // velocity planes written by the LB kernel; density (diagnostics)
-  int64_t part_base;   // offset (doubles) of this instance's centre-of-mass partials [tiles][ndrop][3]
+  int64_t part_base[2];  // per tiling: offset (doubles) of the centre-of-mass partials [tiles][ndrop][3]
   int32_t advection, pad0;
   // model parameters, derived on the host in double precision
   double a, b, B0, B1, halfB1, D, Gamma, gamma, c0, omega, coef, A0, t_star;
@@ -52,8 +62,14 @@ template <typename T>
 hipError_t launch_cm_partials(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
                               const InstDev* inst, T* buf, const DropDev* drops, double* part,
                               uint64_t* mask);
-hipError_t launch_reduce(hipStream_t s, int ndrop_total, const InstDev* inst, DropDev* drops,
+hipError_t launch_reduce(hipStream_t s, int tiling, int ndrop_total, const InstDev* inst, DropDev* drops,
                          const double* part, const uint64_t* mask, int64_t* step, int increment);
+// Fused timestep (one launch per step over the strip list); dbg != nullptr exports stage planes of
+// instance dbg_inst instead of advancing.
+template <typename T>
+hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst,
+                       T* buf, const DropDev* drops, double* part, uint64_t* mask, const int64_t* step,
+                       double* dbg, int dbg_inst);
 template <typename T>
 hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
                       const InstDev* inst, T* buf, const DropDev* drops, double* obs_part,

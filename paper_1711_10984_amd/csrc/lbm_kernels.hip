@@ -257,7 +257,7 @@ __device__ void tile_cm_sums(const InstDev& I, int t_local, int t_global, const 
       const double s1 = block_reduce(a1, sh.red, OpAdd());
       const double s2 = block_reduce(a2, sh.red, OpAdd());
       if (tid == 0) {
-        double* p = part + I.part_base + ((int64_t)t_local * I.ndrop + k) * 3;
+        double* p = part + I.part_base[TILING_SPLIT] + ((int64_t)t_local * I.ndrop + k) * 3;
         p[0] = s0;
         p[1] = s1;
         p[2] = s2;
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fd(int parity, const TileDev* __re
     }
   }
   if (MODE == 0 && I.ndrop > 0)
-    tile_cm_sums(I, td.t - I.tile_base, td.t, kd, vv, vx, vy, sh, part, mask);
+    tile_cm_sums(I, td.t - I.tile_base[TILING_SPLIT], td.t, kd, vv, vx, vy, sh, part, mask);
 }
 
 // Centre-of-mass partials of the current phi (the first pass at initialisation).
@@ -559,11 +559,12 @@ __global__ __launch_bounds__(NTHREADS) void k_cm_partials(int parity, const Tile
       vy[j] = v * minimg((double)y - d.y, (double)ny);
     }
   }
-  tile_cm_sums(I, td.t - I.tile_base, td.t, kd, vv, vx, vy, sh, part, mask);
+  tile_cm_sums(I, td.t - I.tile_base[TILING_SPLIT], td.t, kd, vv, vx, vy, sh, part, mask);
 }
 
-// One workgroup per droplet: fixed-order sum of the tile partials, new centre of mass (Sec. 4).
-__global__ __launch_bounds__(NTHREADS) void k_reduce(int ndrop_total, const InstDev* __restrict__ insts,
+// One workgroup per droplet: fixed-order sum of the tile partials of one tiling, new centre of mass
+// (Sec. 4), and the step counter.
+__global__ __launch_bounds__(NTHREADS) void k_reduce(int tiling, int ndrop_total, const InstDev* __restrict__ insts,
                                                      DropDev* __restrict__ drops,
                                                      const double* __restrict__ part,
                                                      const uint64_t* __restrict__ mask,
@@ -575,12 +576,14 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(int ndrop_total, const Inst
   const DropDev d = drops[g];
   const InstDev& I = insts[d.inst];
   const int k = g - I.drop_base;
-  const int ntl = I.tiles_x * I.tiles_y;
+  const int ntl = I.tiles_x[tiling] * I.tiles_y[tiling];
+  const int64_t tb = I.tile_base[tiling];
+  const double* pb = part + I.part_base[tiling];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int tl = threadIdx.x; tl < ntl; tl += NTHREADS) {
-    const int64_t t = I.tile_base + tl;
+    const int64_t t = tb + tl;
     if ((mask[t * MASK_WORDS + (k >> 6)] >> (k & 63)) & 1ull) {
-      const double* p = part + I.part_base + ((int64_t)tl * I.ndrop + k) * 3;
+      const double* p = pb + ((int64_t)tl * I.ndrop + k) * 3;
       a0 += p[0];
       a1 += p[1];
       a2 += p[2];
@@ -682,6 +685,469 @@ __global__ __launch_bounds__(NTHREADS) void k_obs(int parity, const TileDev* __r
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Fused timestep.  A workgroup owns the strip [x0, x0 + FUSED_TX) x [y0, y0 + FUSED_SY) of one
+// instance and sweeps it in y.  Lane l of every wavefront handles column x0 + l - 5 (periodic), so a
+// row of 64 lanes covers the strip plus 5 halo columns on each side.  The six stages of the step are
+// skewed by one row and keep their recent rows in 8-row LDS rings:
+//   s0  phi^n, c^n                                   (global loads, prefetched one sweep ahead)
+//   s1  mu_phi (Eq. 3), X = (B1/2)|grad phi|^2 (Eq. 5)
+//   s2  F (Eq. 14), pulled f, n, u^n (Eq. 11); on owned nodes BGK + forcing (Eqs. 10, 12, 13) -> f*
+//   s3  phi^{n+1/2}, c^{n+1/2} (Eqs. 16-17)
+//   s4  M, the bracket of Eq. (18), and X^{n+1/2}
+//   s5  phi^{n+1} (Eq. 18), c^{n+1} (Eq. 19) on owned nodes; centre-of-mass contributions (Sec. 4)
+// Each sweep iteration advances every stage by FUSED_R rows (one wavefront per row).  Stage s needs rows
+// r-1..r+1 of stage s-1, which the one-row skew provides without recomputing any row in y; only the
+// 5 halo columns per side are computed twice (by both neighbouring strips).
+constexpr int RING = 8;
+
+struct FusedShared {
+  unsigned long long near_mask[MASK_WORDS], src_mask[MASK_WORDS], seg_mask[MASK_WORDS], it_mask[MASK_WORDS];
+  double red[NTHREADS / 64][3];
+  double acc[MAXDROP][3];
+};
+
+// 9-point stencils on three LDS rows: up = row r+1 (N), mid = row r, dn = row r-1 (S); lane l.
+template <typename T>
+__device__ __forceinline__ void grad9r(const T* up, const T* mid, const T* dn, int l, T& gx, T& gy) {
+  const T E = mid[l + 1], Wv = mid[l - 1], N = up[l], S = dn[l];
+  const T NE = up[l + 1], NW = up[l - 1], SW = dn[l - 1], SE = dn[l + 1];
+  gx = (T(4) * (E - Wv) + ((NE - NW) + (SE - SW))) * cst<T>(1.0 / 12.0);
+  gy = (T(4) * (N - S) + ((NE - SE) + (NW - SW))) * cst<T>(1.0 / 12.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T lap9r(const T* up, const T* mid, const T* dn, int l) {
+  const T E = mid[l + 1], Wv = mid[l - 1], N = up[l], S = dn[l];
+  const T NE = up[l + 1], NW = up[l - 1], SW = dn[l - 1], SE = dn[l + 1];
+  return (T(4) * ((E + Wv) + (N + S)) + ((NE + NW) + (SE + SW)) - T(20) * mid[l]) * cst<T>(1.0 / 6.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T div9r(const T* cu, const T* cm, const T* cd, T D, const T* Xu, const T* Xm,
+                                   const T* Xd, int l) {
+  const T k0 = D * cm[l], X0 = Xm[l];
+  const T t1 = (k0 + D * cm[l + 1]) * (Xm[l + 1] - X0);
+  const T t2 = (k0 + D * cu[l]) * (Xu[l] - X0);
+  const T t3 = (k0 + D * cm[l - 1]) * (Xm[l - 1] - X0);
+  const T t4 = (k0 + D * cd[l]) * (Xd[l] - X0);
+  const T t5 = (k0 + D * cu[l + 1]) * (Xu[l + 1] - X0);
+  const T t6 = (k0 + D * cu[l - 1]) * (Xu[l - 1] - X0);
+  const T t7 = (k0 + D * cd[l - 1]) * (Xd[l - 1] - X0);
+  const T t8 = (k0 + D * cd[l + 1]) * (Xd[l + 1] - X0);
+  return (T(4) * ((t1 + t3) + (t2 + t4)) + ((t5 + t6) + (t7 + t8))) * cst<T>(1.0 / 12.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T advect_r(const T* gu, const T* gm, const T* gd, const T* xu, const T* xm,
+                                      const T* xd, const T* yu, const T* ym, const T* yd, int l, int mode) {
+  // xm/ym: velocity rows (x and y components) at row r; xu.. at r+1, xd.. at r-1
+  const T gc = gm[l];
+  if (mode == 0) {
+    const T divu = T(0.5) * (xm[l + 1] - xm[l - 1]) + T(0.5) * (yu[l] - yd[l]);
+    const T u = xm[l], v = ym[l];
+    const T dgx = u > T(0) ? gc - gm[l - 1] : gm[l + 1] - gc;
+    const T dgy = v > T(0) ? gc - gd[l] : gu[l] - gc;
+    return gc - ((gc * divu + u * dgx) + v * dgy);
+  }
+  const T uxr = T(0.5) * (xm[l] + xm[l + 1]), uxl = T(0.5) * (xm[l - 1] + xm[l]);
+  const T uyt = T(0.5) * (ym[l] + yu[l]), uyb = T(0.5) * (yd[l] + ym[l]);
+  const T Fr = uxr * (uxr >= T(0) ? gc : gm[l + 1]);
+  const T Fl = uxl * (uxl >= T(0) ? gm[l - 1] : gc);
+  const T Ft = uyt * (uyt >= T(0) ? gc : gu[l]);
+  const T Fb = uyb * (uyb >= T(0) ? gd[l] : gc);
+  return gc - ((Fr - Fl) + (Ft - Fb));
+}
+
+// Sum of three values over the workgroup in a fixed order (lane 0's butterfly result per wave, waves
+// in order); every thread receives the result.
+__device__ __forceinline__ void block_reduce3(double& a, double& b, double& c, double (*red)[3]) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wv][0] = a;
+    red[wv][1] = b;
+    red[wv][2] = c;
+  }
+  __syncthreads();
+  a = red[0][0];
+  b = red[0][1];
+  c = red[0][2];
+  for (int w = 1; w < NTHREADS / 64; ++w) {
+    a += red[w][0];
+    b += red[w][1];
+    c += red[w][2];
+  }
+  __syncthreads();
+}
+
+template <typename T, bool DBG>
+__global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __restrict__ segs,
+                                                   const InstDev* __restrict__ insts, T* __restrict__ buf,
+                                                   const DropDev* __restrict__ drops, double* __restrict__ part,
+                                                   uint64_t* __restrict__ mask, const int64_t* __restrict__ step,
+                                                   double* __restrict__ dbg, int dbg_inst) {
+  constexpr int L = FUSED_LANES;
+  __shared__ T r_phi[RING][L], r_c[RING][L], r_mu[RING][L], r_X[RING][L], r_ux[RING][L], r_uy[RING][L];
+  __shared__ T r_ph[RING][L], r_ch[RING][L], r_M[RING][L], r_Xh[RING][L];
+  __shared__ FusedShared sh;
+
+  const TileDev sd = segs[blockIdx.x];
+  if (sd.inst < 0) return;
+  if (DBG && sd.inst != dbg_inst) return;
+  const InstDev& I = insts[sd.inst];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nx = I.nx, ny = I.ny, pitch = I.pitch, nd = I.ndrop;
+  const int x0 = sd.x0, y0 = sd.y0;
+  const int yend = min(y0 + FUSED_SY, ny);
+  const int xend = min(x0 + FUSED_TX, nx);
+  const int col = lane - 5;                   // column offset of this lane
+  const int gx = wrap_idx(x0 + col, nx);      // periodic global column
+  const int gxm = gx == 0 ? nx - 1 : gx - 1, gxp = gx == nx - 1 ? 0 : gx + 1;
+  const bool own_col = col >= 0 && col < FUSED_TX && x0 + col < nx;
+  const int64_t plane = (int64_t)ny * pitch;
+  const T* __restrict__ phi_in = buf + I.off_phi[parity];
+  const T* __restrict__ c_in = buf + I.off_c[parity];
+  const T* __restrict__ fin = buf + I.off_f[parity];
+  T* __restrict__ fout = buf + I.off_f[parity ^ 1];
+  T* __restrict__ phi_out = buf + I.off_phi[parity ^ 1];
+  T* __restrict__ c_out = buf + I.off_c[parity ^ 1];
+  const int64_t nplane = (int64_t)nx * ny;
+
+  // --- droplet culling for the owned box [x0, xend) x [y0, yend); thread k handles droplet k
+  if (nd > 0) {
+    const double Lx = nx, Ly = ny;
+    const double xm = 0.5 * (x0 + xend - 1), ym = 0.5 * (y0 + yend - 1);
+    const double hx = 0.5 * (xend - 1 - x0), hy = 0.5 * (yend - 1 - y0);
+    double maxd2 = 1e300, mind2 = 1e300;
+    bool srcf = false;
+    if (tid < nd) {
+      const DropDev d = drops[I.drop_base + tid];
+      const double ddx = fabs(minimg(xm - d.x, Lx)), ddy = fabs(minimg(ym - d.y, Ly));
+      const double ux = ddx + hx, uy = ddy + hy;
+      maxd2 = ux * ux + uy * uy;
+      const double lx = fmax(0.0, ddx - hx), ly = fmax(0.0, ddy - hy);
+      mind2 = lx * lx + ly * ly;
+      if (d.active) {
+        const double px = d.x + (d.R - d.Rs) * d.ex, py = d.y + (d.R - d.Rs) * d.ey;
+        const double sdx = fmax(0.0, fabs(minimg(xm - px, Lx)) - hx);
+        const double sdy = fmax(0.0, fabs(minimg(ym - py, Ly)) - hy);
+        const double rr = d.Rs + 1e-6;
+        srcf = sdx * sdx + sdy * sdy <= rr * rr;
+      }
+    }
+    double thr = maxd2;
+    for (int o = 32; o > 0; o >>= 1) thr = fmin(thr, __shfl_xor(thr, o, 64));
+    if (lane == 0) sh.red[wv][0] = thr;
+    __syncthreads();
+    thr = fmin(fmin(sh.red[0][0], sh.red[1][0]), fmin(sh.red[2][0], sh.red[3][0]));
+    const double lim = thr * (1.0 + 1e-12) + 1e-6;
+    const unsigned long long nb = __ballot(tid < nd && mind2 <= lim);
+    const unsigned long long sb = __ballot(srcf);
+    if (lane == 0) {
+      sh.near_mask[wv] = nb;
+      sh.src_mask[wv] = sb;
+      sh.seg_mask[wv] = 0ull;
+    }
+    __syncthreads();
+  }
+  const double tn = (double)(*step);
+  const double A = I.A0 * (tn < I.t_star ? tn : I.t_star);
+
+  const T a = T(I.a), b = T(I.b), B0 = T(I.B0), B1 = T(I.B1), halfB1 = T(I.halfB1);
+  const T omega = T(I.omega), coef = T(I.coef);
+  const T w0 = cst<T>(4.0 / 9.0), w1 = cst<T>(1.0 / 9.0), w5 = cst<T>(1.0 / 36.0);
+  const T cw0 = coef * w0, cw1 = coef * w1, cw5 = coef * w5;
+  const T Gamma = T(I.Gamma), D = T(I.D), gam = T(I.gamma), c0 = T(I.c0);
+  const int adv = I.advection;
+
+  // stage row validity windows: stage s computes rows [y0 - (5 - s), yend + (5 - s))
+  const bool l1 = lane >= 1 && lane < L - 1, l2 = lane >= 2 && lane < L - 2, l3 = lane >= 3 && lane < L - 3;
+  const bool l4 = lane >= 4 && lane < L - 4;
+  const int H = yend - y0;
+  const int nit = (H + 6 + FUSED_R - 1) / FUSED_R + 1;
+
+  // prefetch registers: phi, c of the stage-0 row and the pulled populations of the stage-2 row
+  T pf_phi = T(0), pf_c = T(0);
+  T pf[9];
+  for (int i = 0; i < 9; ++i) pf[i] = T(0);
+  auto load_s0 = [&](int it) {
+    const int r = y0 - 5 + it * FUSED_R + wv;
+    if (r < yend + 5) {
+      const int gy = wrap_idx(r, ny);
+      const int64_t o = (int64_t)gy * pitch + gx;
+      pf_phi = phi_in[o];
+      pf_c = c_in[o];
+    }
+  };
+  auto load_s2 = [&](int it) {
+    const int r = y0 - 5 + it * FUSED_R + wv - 2;
+    if (l2 && r >= y0 - 3 && r < yend + 3) {
+      const int gy = wrap_idx(r, ny);
+      const int gym = gy == 0 ? ny - 1 : gy - 1, gyp = gy == ny - 1 ? 0 : gy + 1;
+      const int64_t r0 = (int64_t)gy * pitch, rm = (int64_t)gym * pitch, rp = (int64_t)gyp * pitch;
+      pf[0] = fin[r0 + gx];
+      pf[1] = fin[plane + r0 + gxm];
+      pf[2] = fin[2 * plane + rm + gx];
+      pf[3] = fin[3 * plane + r0 + gxp];
+      pf[4] = fin[4 * plane + rp + gx];
+      pf[5] = fin[5 * plane + rm + gxm];
+      pf[6] = fin[6 * plane + rm + gxp];
+      pf[7] = fin[7 * plane + rp + gxp];
+      pf[8] = fin[8 * plane + rp + gxm];
+    }
+  };
+  load_s0(0);
+  load_s2(0);
+
+  for (int it = 0; it < nit; ++it) {
+    const int q0 = y0 - 5 + it * FUSED_R;
+    // ---- s0: store phi^n, c^n of row q0 + wv, then prefetch the next sweep's row
+    {
+      const int r = q0 + wv;
+      if (r < yend + 5) {
+        r_phi[r & (RING - 1)][lane] = pf_phi;
+        r_c[r & (RING - 1)][lane] = pf_c;
+      }
+      load_s0(it + 1);
+    }
+    __syncthreads();
+    // ---- s1: mu_phi and X (Eqs. 3, 5)
+    {
+      const int r = q0 - 1 + wv;
+      if (l1 && r >= y0 - 4 && r < yend + 4) {
+        const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
+        T gpx, gpy, gcx, gcy;
+        grad9r(r_phi[su], r_phi[sm], r_phi[sdn], lane, gpx, gpy);
+        grad9r(r_c[su], r_c[sm], r_c[sdn], lane, gcx, gcy);
+        const T lp = lap9r(r_phi[su], r_phi[sm], r_phi[sdn], lane);
+        const T ph = r_phi[sm][lane];
+        const T B = B0 + B1 * r_c[sm][lane];
+        const T mu = ((a * ph + b * (ph * ph * ph)) - B * lp) - B1 * (gpx * gcx + gpy * gcy);
+        const T X = halfB1 * (gpx * gpx + gpy * gpy);
+        r_mu[sm][lane] = mu;
+        r_X[sm][lane] = X;
+        if (DBG && own_col && r >= y0 && r < yend) {
+          const int64_t q = (int64_t)r * nx + (x0 + col);
+          dbg[0 * nplane + q] = (double)mu;
+          dbg[1 * nplane + q] = (double)X;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- s2: force, moments, collision
+    {
+      const int r = q0 - 2 + wv;
+      if (l2 && r >= y0 - 3 && r < yend + 3) {
+        const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
+        T gmx, gmy, gXx, gXy, gcx, gcy;
+        grad9r(r_mu[su], r_mu[sm], r_mu[sdn], lane, gmx, gmy);
+        grad9r(r_X[su], r_X[sm], r_X[sdn], lane, gXx, gXy);
+        grad9r(r_c[su], r_c[sm], r_c[sdn], lane, gcx, gcy);
+        const T ph = r_phi[sm][lane], cv = r_c[sm][lane];
+        const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
+        const T Fy = (-(ph * gmy) - gcy) - cv * gXy;
+        const T f0 = pf[0], f1 = pf[1], f2 = pf[2], f3 = pf[3], f4 = pf[4], f5 = pf[5], f6 = pf[6], f7 = pf[7],
+                f8 = pf[8];
+        const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
+        const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
+        const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
+        const T ux = (mx + T(0.5) * Fx) / nn;
+        const T uy = (my + T(0.5) * Fy) / nn;
+        r_ux[sm][lane] = ux;
+        r_uy[sm][lane] = uy;
+        if (own_col && r >= y0 && r < yend) {
+          const T usq = ux * ux + uy * uy;
+          const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
+          const T wn0 = w0 * nn, wn1 = w1 * nn, wn5 = w5 * nn;
+          const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
+          const T s0 = collide1(f0, wn0, cw0, T(0), T(0), nux, nuy, Fx, Fy, usq, omega);
+          const T s1 = collide1(f1, wn1, cw1, ux, Fx, xp1, nuy, Fx, Fy, usq, omega);
+          const T s2 = collide1(f2, wn1, cw1, uy, Fy, nux, yp1, Fx, Fy, usq, omega);
+          const T s3 = collide1(f3, wn1, cw1, nux, nFx, xm1, nuy, Fx, Fy, usq, omega);
+          const T s4 = collide1(f4, wn1, cw1, nuy, nFy, nux, ym1, Fx, Fy, usq, omega);
+          const T s5 = collide1(f5, wn5, cw5, ux + uy, Fx + Fy, xp1, yp1, Fx, Fy, usq, omega);
+          const T s6 = collide1(f6, wn5, cw5, nux + uy, nFx + Fy, xm1, yp1, Fx, Fy, usq, omega);
+          const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
+          const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
+          const int64_t o = (int64_t)r * pitch + gx;
+          fout[o] = s0;
+          fout[plane + o] = s1;
+          fout[2 * plane + o] = s2;
+          fout[3 * plane + o] = s3;
+          fout[4 * plane + o] = s4;
+          fout[5 * plane + o] = s5;
+          fout[6 * plane + o] = s6;
+          fout[7 * plane + o] = s7;
+          fout[8 * plane + o] = s8;
+          if (DBG) {
+            const int64_t q = (int64_t)r * nx + (x0 + col);
+            dbg[2 * nplane + q] = (double)Fx;
+            dbg[3 * nplane + q] = (double)Fy;
+            dbg[4 * nplane + q] = (double)nn;
+            dbg[5 * nplane + q] = (double)ux;
+            dbg[6 * nplane + q] = (double)uy;
+            const T sv[9] = {s0, s1, s2, s3, s4, s5, s6, s7, s8};
+            for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = (double)sv[i];
+          }
+        }
+      }
+      load_s2(it + 1);
+    }
+    __syncthreads();
+    // ---- s3: advection half-step (Eqs. 16-17)
+    {
+      const int r = q0 - 3 + wv;
+      if (l3 && r >= y0 - 2 && r < yend + 2) {
+        const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
+        const T ph = advect_r(r_phi[su], r_phi[sm], r_phi[sdn], r_ux[su], r_ux[sm], r_ux[sdn], r_uy[su], r_uy[sm],
+                              r_uy[sdn], lane, adv);
+        const T ch = advect_r(r_c[su], r_c[sm], r_c[sdn], r_ux[su], r_ux[sm], r_ux[sdn], r_uy[su], r_uy[sm],
+                              r_uy[sdn], lane, adv);
+        r_ph[sm][lane] = ph;
+        r_ch[sm][lane] = ch;
+        if (DBG && own_col && r >= y0 && r < yend) {
+          const int64_t q = (int64_t)r * nx + (x0 + col);
+          dbg[7 * nplane + q] = (double)ph;
+          dbg[8 * nplane + q] = (double)ch;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- s4: bracket M of Eq. (18) and X^{n+1/2}
+    {
+      const int r = q0 - 4 + wv;
+      if (l4 && r >= y0 - 1 && r < yend + 1) {
+        const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
+        T gphx, gphy, gchx, gchy;
+        grad9r(r_ph[su], r_ph[sm], r_ph[sdn], lane, gphx, gphy);
+        grad9r(r_ch[su], r_ch[sm], r_ch[sdn], lane, gchx, gchy);
+        const T lph = lap9r(r_ph[su], r_ph[sm], r_ph[sdn], lane);
+        const T pn = r_phi[sm][lane];
+        const T Bh = B0 + B1 * r_ch[sm][lane];
+        const T M = ((a * r_ph[sm][lane] + b * (pn * pn * pn)) - Bh * lph) - B1 * (gchx * gphx + gchy * gphy);
+        const T Xh = halfB1 * (gphx * gphx + gphy * gphy);
+        r_M[sm][lane] = M;
+        r_Xh[sm][lane] = Xh;
+        if (DBG && own_col && r >= y0 && r < yend) {
+          const int64_t q = (int64_t)r * nx + (x0 + col);
+          dbg[9 * nplane + q] = (double)M;
+          dbg[10 * nplane + q] = (double)Xh;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- s5: phi^{n+1}, c^{n+1} (Eqs. 18, 19) and centre-of-mass contributions
+    int kd = -1;
+    double cv0 = 0.0, cv1 = 0.0, cv2 = 0.0;
+    {
+      const int r = q0 - 5 + wv;
+      if (own_col && r >= y0 && r < yend) {
+        const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
+        const T phn = r_ph[sm][lane] + Gamma * lap9r(r_M[su], r_M[sm], r_M[sdn], lane);
+        const T ch = r_ch[sm][lane];
+        const T lch = lap9r(r_ch[su], r_ch[sm], r_ch[sdn], lane);
+        const T dv = div9r(r_ch[su], r_ch[sm], r_ch[sdn], D, r_Xh[su], r_Xh[sm], r_Xh[sdn], lane);
+        const double xd = (double)(x0 + col), yd = (double)r;
+        int cnt = 0;
+        if (nd > 0) {
+          for (int w = 0; w < MASK_WORDS; ++w) {
+            unsigned long long m = sh.src_mask[w];
+            while (m) {
+              const int k = w * 64 + __ffsll(m) - 1;
+              m &= m - 1;
+              const DropDev d = drops[I.drop_base + k];
+              const double px = d.x + (d.R - d.Rs) * d.ex, py = d.y + (d.R - d.Rs) * d.ey;
+              const double dx = minimg(xd - px, (double)nx), dy = minimg(yd - py, (double)ny);
+              if (dx * dx + dy * dy <= d.Rs * d.Rs) ++cnt;
+            }
+          }
+        }
+        const double src = A * (double)cnt;
+        const T cn = (((ch + D * lch) + dv) - gam * (ch - c0)) + T(src);
+        const int64_t o = (int64_t)r * pitch + gx;
+        if (!DBG) {
+          phi_out[o] = phn;
+          c_out[o] = cn;
+        } else {
+          const int64_t q = (int64_t)r * nx + (x0 + col);
+          dbg[11 * nplane + q] = (double)phn;
+          dbg[12 * nplane + q] = (double)cn;
+        }
+        const double v = (double)phn;
+        if (!DBG && nd > 0 && v >= 0.0) {
+          int best = -1;
+          double bd = 0.0;
+          for (int w = 0; w < MASK_WORDS; ++w) {
+            unsigned long long m = sh.near_mask[w];
+            while (m) {
+              const int k = w * 64 + __ffsll(m) - 1;
+              m &= m - 1;
+              const DropDev d = drops[I.drop_base + k];
+              const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, (double)ny);
+              const double d2 = dx * dx + dy * dy;
+              if (best < 0 || d2 < bd) {
+                best = k;
+                bd = d2;
+              }
+            }
+          }
+          const DropDev d = drops[I.drop_base + best];
+          kd = best;
+          cv0 = v;
+          cv1 = v * minimg(xd - d.x, (double)nx);
+          cv2 = v * minimg(yd - d.y, (double)ny);
+        }
+      }
+    }
+    // deterministic per-sweep reduction of the centre-of-mass contributions (only when some node of
+    // this sweep iteration has phi^{n+1} >= 0)
+    if (!DBG && nd > 0 && __syncthreads_or(kd >= 0)) {
+      if (tid < MASK_WORDS) sh.it_mask[tid] = 0ull;
+      __syncthreads();
+      if (kd >= 0) atomicOr(&sh.it_mask[kd >> 6], 1ull << (kd & 63));
+      __syncthreads();
+      for (int w = 0; w < MASK_WORDS; ++w) {
+        unsigned long long m = sh.it_mask[w];
+        while (m) {
+          const int k = w * 64 + __ffsll(m) - 1;
+          m &= m - 1;
+          double s0 = kd == k ? cv0 : 0.0, s1 = kd == k ? cv1 : 0.0, s2 = kd == k ? cv2 : 0.0;
+          block_reduce3(s0, s1, s2, sh.red);
+          if (tid == 0) {
+            const unsigned long long bit = 1ull << (k & 63);
+            if (sh.seg_mask[k >> 6] & bit) {
+              sh.acc[k][0] += s0;
+              sh.acc[k][1] += s1;
+              sh.acc[k][2] += s2;
+            } else {
+              sh.seg_mask[k >> 6] |= bit;
+              sh.acc[k][0] = s0;
+              sh.acc[k][1] = s1;
+              sh.acc[k][2] = s2;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (DBG || nd == 0) return;
+  // partials of the droplets present in this strip, and the presence mask
+  __syncthreads();
+  const int t_local = sd.t - I.tile_base[TILING_FUSED];
+  if (tid < nd && ((sh.seg_mask[tid >> 6] >> (tid & 63)) & 1ull)) {
+    double* p = part + I.part_base[TILING_FUSED] + ((int64_t)t_local * nd + tid) * 3;
+    p[0] = sh.acc[tid][0];
+    p[1] = sh.acc[tid][1];
+    p[2] = sh.acc[tid][2];
+  }
+  if (tid < MASK_WORDS) mask[(int64_t)sd.t * MASK_WORDS + tid] = sh.seg_mask[tid];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------------
@@ -724,10 +1190,10 @@ hipError_t launch_cm_partials(hipStream_t s, int parity, int ntiles_launch, cons
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(hipStream_t s, int ndrop_total, const InstDev* inst, DropDev* drops,
+hipError_t launch_reduce(hipStream_t s, int tiling, int ndrop_total, const InstDev* inst, DropDev* drops,
                          const double* part, const uint64_t* mask, int64_t* step, int increment) {
-  hipLaunchKernelGGL(k_reduce, dim3(ndrop_total > 0 ? ndrop_total : 1), dim3(NTHREADS), 0, s, ndrop_total,
-                     inst, drops, part, mask, step, increment);
+  hipLaunchKernelGGL(k_reduce, dim3(ndrop_total > 0 ? ndrop_total : 1), dim3(NTHREADS), 0, s, tiling,
+                     ndrop_total, inst, drops, part, mask, step, increment);
   return hipGetLastError();
 }
 
@@ -740,6 +1206,20 @@ hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDe
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst, T* buf,
+                       const DropDev* drops, double* part, uint64_t* mask, const int64_t* step, double* dbg,
+                       int dbg_inst) {
+  if (nseg_launch <= 0) return hipSuccess;
+  if (dbg)
+    hipLaunchKernelGGL((k_step<T, true>), dim3(nseg_launch), dim3(NTHREADS), 0, s, parity, segs, inst, buf, drops,
+                       part, mask, step, dbg, dbg_inst);
+  else
+    hipLaunchKernelGGL((k_step<T, false>), dim3(nseg_launch), dim3(NTHREADS), 0, s, parity, segs, inst, buf, drops,
+                       part, mask, step, dbg, dbg_inst);
+  return hipGetLastError();
+}
+
 #define LBM_INSTANTIATE(T)                                                                                \
   template hipError_t launch_lb<T>(hipStream_t, int, int, int, const TileDev*, const InstDev*, T*,        \
                                    double*, int);                                                         \
@@ -748,7 +1228,9 @@ hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDe
   template hipError_t launch_cm_partials<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,    \
                                             const DropDev*, double*, uint64_t*);                          \
   template hipError_t launch_obs<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,            \
-                                    const DropDev*, double*, int);
+                                    const DropDev*, double*, int);                                        \
+  template hipError_t launch_step<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*, const DropDev*,  \
+                                     double*, uint64_t*, const int64_t*, double*, int);
 
 LBM_INSTANTIATE(double)
 LBM_INSTANTIATE(float)

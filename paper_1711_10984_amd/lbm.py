@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32 = 0, 1
 LBM_ADV_PAPER, LBM_ADV_FLUX = 0, 1
+LBM_PATH_FUSED, LBM_PATH_SPLIT = 0, 1
 LBM_MAXDROP = 256
 LBM_NSTAGE = 22
 STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "phi_new", "c_new"] + [
@@ -26,7 +27,8 @@ STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "p
 ]
 EXPORTED = ["lbm_workspace_bytes", "lbm_init_batch", "lbm_init", "lbm_step", "lbm_set_graph", "lbm_sync",
             "lbm_get_step", "lbm_fields", "lbm_observables", "lbm_droplets", "lbm_debug_stage",
-            "lbm_time_kernels", "lbm_kernel_name", "lbm_destroy", "lbm_last_error"]
+            "lbm_time_kernels", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_destroy",
+            "lbm_last_error"]
 
 
 class LBMError(RuntimeError):
@@ -81,8 +83,11 @@ def load_library(path: Optional[str] = None):
     lib.lbm_droplets.argtypes = [vp, C.c_int32, C.POINTER(lbm_droplet)]
     lib.lbm_debug_stage.argtypes = [vp, C.c_int32, dp]
     lib.lbm_time_kernels.argtypes = [vp, C.c_int64, dp]
-    lib.lbm_kernel_name.argtypes = [C.c_int32]
+    lib.lbm_kernel_name.argtypes = [C.c_int32, C.c_int32]
     lib.lbm_kernel_name.restype = C.c_char_p
+    lib.lbm_set_path.argtypes = [vp, C.c_int32]
+    lib.lbm_get_path.argtypes = [vp]
+    lib.lbm_get_path.restype = C.c_int32
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.restype = C.c_char_p
@@ -188,8 +193,16 @@ def lbm_time_kernels(ctx: int, n: int) -> np.ndarray:
     return out
 
 
-def lbm_kernel_name(which: int) -> str:
-    return load_library().lbm_kernel_name(which).decode()
+def lbm_kernel_name(path: int, which: int) -> str:
+    return load_library().lbm_kernel_name(path, which).decode()
+
+
+def lbm_set_path(ctx: int, path: int) -> None:
+    _check(load_library().lbm_set_path(C.c_void_p(ctx), int(path)))
+
+
+def lbm_get_path(ctx: int) -> int:
+    return int(load_library().lbm_get_path(C.c_void_p(ctx)))
 
 
 def lbm_destroy(ctx: int) -> None:
@@ -207,7 +220,7 @@ class Sim:
     def __init__(self, params: List[dict], phi0: List[np.ndarray], c0: List[np.ndarray],
                  drops: Optional[List[List[dict]]] = None, precision: int = LBM_FP64,
                  f_pre: Optional[List[np.ndarray]] = None, step: int = 0, device: str = "cuda:0",
-                 graph_steps: Optional[int] = None):
+                 graph_steps: Optional[int] = None, path: int = LBM_PATH_FUSED):
         import torch
 
         if not torch.cuda.is_available():
@@ -232,6 +245,7 @@ class Sim:
         torch.cuda.synchronize(self.device)
         self.ctx = lbm_init_batch(self.cfgs, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream, cat(phi0),
                                   cat(c0), fp, self.ndrop, dl, step)
+        lbm_set_path(self.ctx, path)
         if graph_steps is not None:
             lbm_set_graph(self.ctx, graph_steps)
 
@@ -285,6 +299,11 @@ class Sim:
         lbm_debug_stage(self.ctx, inst, buf)
         return {name: buf[i] for i, name in enumerate(STAGES)}
 
+    def set_path(self, path: int) -> None:
+        lbm_set_path(self.ctx, path)
+
     def time_kernels(self, n: int) -> Dict[str, float]:
+        """Average ms per launch of each kernel of the current path (hipEvents on the library's stream)."""
         ms = lbm_time_kernels(self.ctx, n)
-        return {lbm_kernel_name(i): float(ms[i]) for i in range(3)}
+        path = lbm_get_path(self.ctx)
+        return {lbm_kernel_name(path, i): float(ms[i]) for i in range(3) if lbm_kernel_name(path, i)}

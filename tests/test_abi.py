@@ -111,4 +111,5 @@ def test_init_rejects_bad_workspace_before_any_device_call():
 
 def test_kernel_names():
     lbm = _lbm()
-    assert [lbm.lbm_kernel_name(i) for i in range(3)] == ["k_lb", "k_fd", "k_reduce"]
+    assert [lbm.lbm_kernel_name(lbm.LBM_PATH_SPLIT, i) for i in range(3)] == ["k_lb", "k_fd", "k_reduce"]
+    assert [lbm.lbm_kernel_name(lbm.LBM_PATH_FUSED, i) for i in range(3)] == ["k_step", "k_reduce", ""]

@@ -27,11 +27,14 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / den) if den > 0 else float(np.max(np.abs(a - b)))
 
 
-def gpu_sim(w, precision=0, graph_steps=None, step=0, f_pre=None, phi=None, c=None, drops=None):
+def gpu_sim(w, precision=0, graph_steps=None, step=0, f_pre=None, phi=None, c=None, drops=None, path=0):
     lbm = _lbm()
     return lbm.Sim([w.param_dict()], [w.phi0 if phi is None else phi], [w.c0 if c is None else c],
                    [w.drop_dicts() if drops is None else drops], precision=precision, graph_steps=graph_steps,
-                   step=step, f_pre=None if f_pre is None else [f_pre])
+                   step=step, f_pre=None if f_pre is None else [f_pre], path=path)
+
+
+PATHS = [0, 1]  # fused sweep kernel, split LB + FD kernels
 
 
 def oracle_sim(w, step=0, f_pre=None):
@@ -56,11 +59,12 @@ def random_workload(nx, ny, seed, ndrop=1, A0=1e-3):
     return W.Workload(f"random_{nx}x{ny}", nx, ny, p, phi, c, drops), f
 
 
-@pytest.mark.parametrize("shape", [(3, 3), (5, 7), (8, 8), (70, 37), (130, 19), (64, 16)])
-def test_stages_match_oracle_bitwise(shape):
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("shape", [(3, 3), (5, 7), (8, 8), (70, 37), (130, 19), (64, 16), (55, 129), (200, 67)])
+def test_stages_match_oracle_bitwise(shape, path):
     nx, ny = shape
     w, f = random_workload(nx, ny, seed=nx * 100 + ny, ndrop=2)
-    sim = gpu_sim(w, f_pre=f, step=3)
+    sim = gpu_sim(w, f_pre=f, step=3, path=path)
     got = sim.stages()
     ref = oracle_sim(w, step=3, f_pre=f).stages()
     for k in ref:
@@ -68,11 +72,11 @@ def test_stages_match_oracle_bitwise(shape):
     sim.close()
 
 
-@pytest.mark.parametrize("advection", [0, 1])
-def test_c1_equilibrium_droplet_1000_2000_steps(advection):
+@pytest.mark.parametrize("advection,path", [(0, 0), (1, 0), (0, 1)])
+def test_c1_equilibrium_droplet_1000_2000_steps(advection, path):
     w = W.c1_equilibrium()
     w.params["advection"] = advection
-    sim = gpu_sim(w)
+    sim = gpu_sim(w, path=path)
     ref = oracle_sim(w)
     for steps in (1000, 1000):
         sim.step(steps)
@@ -130,6 +134,22 @@ def test_batched_uneven_instances_match_oracle():
         ref.run(300)
         compare(sim.fields(i), ref.fields(), 1e-12, w.name)
     sim.close()
+
+
+def test_fused_and_split_paths_agree_bitwise():
+    w = W.c5_emulsion(n=384, ndrop=6, R=16.0, seed=21)
+    s1 = gpu_sim(w, path=0, graph_steps=10)
+    s2 = gpu_sim(w, path=1, graph_steps=10)
+    s1.step(120)
+    s2.step(120)
+    f1, f2 = s1.fields(), s2.fields()
+    for k in FIELDS:
+        assert np.array_equal(f1[k], f2[k]), k
+    d1, d2 = s1.droplets(), s2.droplets()
+    for a, b in zip(d1, d2):
+        assert abs(a["x"] - b["x"]) < 1e-12 and abs(a["y"] - b["y"]) < 1e-12
+    s1.close()
+    s2.close()
 
 
 def test_graph_replay_equals_eager_bitwise():
