@@ -34,7 +34,7 @@ VALUES_PER_NODE = {"k_step": 22, "k_lb": 22, "k_fd": 6, "step": 22}
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lbm_internal.h"):
+    for f in ("lbm_kernels_impl.h", "lbm_kernels_f64.hip", "lbm_kernels_f32.hip", "lbm_internal.h"):
         with open(os.path.join(ROOT, "paper_1711_10984_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -81,6 +81,7 @@ def time_steps(sim, steps, warmup):
 def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=0):
     from paper_1711_10984_amd import lbm
     sim = build_sim(workloads, precision, graph_steps, path)
+    seg_rows, tune_ms = sim.autotune(5) if path == 0 else (None, {})
     nodes = sum(w.nodes for w in workloads)
     ms, wall = time_steps(sim, steps, warmup)
     obs = sim.observables(0)
@@ -97,7 +98,7 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     traffic = measured_traffic(dom, label, prec)
     return {
         "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
-        "kernel_ms": per_kernel,
+        "kernel_ms": per_kernel, "seg_rows": seg_rows, "autotune_ms": tune_ms,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": per_kernel[dom]},
@@ -186,10 +187,11 @@ def main():
         "roofline": main_res["roofline"],
         "step_roofline": main_res["step_roofline"],
         "kernel_ms": main_res["kernel_ms"],
+        "autotune": {"seg_rows": main_res["seg_rows"], "ms_per_launch": main_res["autotune_ms"]},
         "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
                          "nodes": v["nodes"], "precision": v["precision"], "gain_over_fp64": v["gain_over_fp64"],
                          "roofline": v["roofline"], "step_roofline": v["step_roofline"],
-                         "kernel_ms": v["kernel_ms"]} for k, v in variants.items()},
+                         "kernel_ms": v["kernel_ms"], "seg_rows": v["seg_rows"]} for k, v in variants.items()},
         "kernel_source_hash": kernel_source_hash(),
     }
     if not args.no_cpu_baseline:

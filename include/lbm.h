@@ -162,6 +162,18 @@ int lbm_debug_stage(lbm_ctx* ctx, int32_t inst, double* out);
 int lbm_set_path(lbm_ctx* ctx, int32_t path);
 int32_t lbm_get_path(const lbm_ctx* ctx);
 
+/* Rows per strip segment of the fused kernel: 16, 32, 64 (default), 128 or 256.  Taller segments
+ * recompute fewer halo rows; shorter ones give more workgroups.  Synchronous. */
+int lbm_set_seg_rows(lbm_ctx* ctx, int32_t rows);
+int32_t lbm_get_seg_rows(const lbm_ctx* ctx);
+
+/* Autotuner: time `launches` launches of the fused kernel for each segment height and keep the
+ * fastest.  The trial launches read the current state and write only scratch (the inactive halves of
+ * the ping-pong buffers and the centre-of-mass partials): the state, the droplet table and the step
+ * counter are unchanged.  chosen (may be NULL) receives the height; ms_out (may be NULL, 5 entries)
+ * the average ms per launch of each candidate 16, 32, 64, 128, 256 (-1 if skipped).  Synchronous. */
+int lbm_autotune(lbm_ctx* ctx, int32_t launches, int32_t* chosen, double* ms_out);
+
 /* Average device time per launch (ms) of each kernel of the timestep over n eagerly launched steps,
  * measured with hipEvents on the context's stream.  Fused path: ms_out = {k_step, k_reduce, 0};
  * split path: {k_lb, k_fd, k_reduce}.  Advances the state by n steps.  Synchronous. */

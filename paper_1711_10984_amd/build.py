@@ -1,28 +1,41 @@
 """Build the HIP library paper_1711_10984_amd/liblbm.so for gfx950 (MI355X).
 
-FMA contraction is off so that the FP64 path evaluates every expression in the order written;
-packed FP32 instructions are disabled.
+FP64 kernels and the host side are compiled without floating-point contraction, so that the FP64 path
+evaluates every expression in the order written; the FP32 kernels are compiled with fused multiply-add
+contraction.  Packed FP32 instructions are disabled everywhere.
 """
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", "lbm_kernels.hip"), os.path.join(HERE, "csrc", "lbm_api.hip")]
+CSRC = os.path.join(HERE, "csrc")
+# (source, floating-point contraction)
+SRC = [("lbm_kernels_f64.hip", "off"), ("lbm_kernels_f32.hip", "fast"), ("lbm_api.hip", "off")]
 LIB = os.path.join(HERE, "liblbm.so")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 
 def hipcc_flags():
-    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
+    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(os.path.dirname(HERE), "include"), "-Wall", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False) -> str:
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for src, contract in SRC:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        cmd = [hipcc] + hipcc_flags() + ["-ffp-contract=" + contract, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + hipcc_flags() + ["-shared", "-o", tmp] + SRC
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -48,6 +48,7 @@ struct Layout {
   std::vector<TileDev> tiles;  // split-kernel tiles in launch order (XCD-aware), padded with inst = -1
   std::vector<TileDev> segs;   // fused-kernel strips in launch order
   int ntiles = 0, nsegs = 0, ndrop_total = 0, max_nd = 0, obs_stride = 0;
+  int max_segs = 0, max_seg_launch = 0, seg_rows = 0;
   int64_t max_nodes = 0;
   size_t off_pool = 0, off_inst = 0, off_tiles = 0, off_segs = 0, off_drops = 0, off_part = 0, off_mask = 0,
          off_step = 0, off_obs = 0, off_dbg = 0, total = 0;
@@ -98,7 +99,7 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.tiles_y[TILING_SPLIT] = (c.ny + TILE_Y - 1) / TILE_Y;
     d.tile_base[TILING_SPLIT] = tile_base;
     d.tiles_x[TILING_FUSED] = (c.nx + FUSED_TX - 1) / FUSED_TX;
-    d.tiles_y[TILING_FUSED] = (c.ny + FUSED_SY - 1) / FUSED_SY;
+    d.tiles_y[TILING_FUSED] = (c.ny + SEG_ROWS_MIN - 1) / SEG_ROWS_MIN;  // upper bound; see set_segments
     d.tile_base[TILING_FUSED] = seg_base;
     d.drop_base = drop_base;
     const int64_t plane = (int64_t)c.ny * d.pitch;
@@ -158,12 +159,14 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     for (int t = 0; t < count; ++t) out[(size_t)(t % chunk) * nxcd + t / chunk] = natural[t];
   };
   build_list(TILING_SPLIT, TILE_X, TILE_Y, L.ntiles, L.tiles);
-  build_list(TILING_FUSED, FUSED_TX, FUSED_SY, L.nsegs, L.segs);
+  L.max_segs = L.nsegs;  // strips of the smallest segment height: sizes the strip list and partials
+  L.max_seg_launch = ((L.nsegs + 7) / 8) * 8;
+  (void)build_list;
   size_t off = 0;
   L.off_pool = off;  off = align_up(off + (size_t)pool_elems * L.elem, ALIGN);
   L.off_inst = off;  off = align_up(off + sizeof(InstDev) * ninst, ALIGN);
   L.off_tiles = off; off = align_up(off + sizeof(TileDev) * L.tiles.size(), ALIGN);
-  L.off_segs = off;  off = align_up(off + sizeof(TileDev) * L.segs.size(), ALIGN);
+  L.off_segs = off;  off = align_up(off + sizeof(TileDev) * (size_t)L.max_seg_launch, ALIGN);
   L.off_drops = off; off = align_up(off + sizeof(DropDev) * std::max(1, L.ndrop_total), ALIGN);
   // the two tilings share the partials and masks (one of them is in use at a time)
   L.off_part = off;
@@ -175,6 +178,36 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
   L.off_dbg = off;
   off = align_up(off + sizeof(double) * (size_t)LBM_NSTAGE * std::min(L.max_nodes, DEBUG_MAX_NODES), ALIGN);
   L.total = off;
+}
+
+// Fused-kernel strips for a segment height: per-instance counts, natural indices, partial offsets and
+// the launch list (XCD-aware order).  Fits in the regions sized for SEG_ROWS_MIN.
+void set_segments(Layout& L, int seg_rows) {
+  int base = 0;
+  int64_t part = 0;
+  for (auto& d : L.inst) {
+    d.seg_rows = seg_rows;
+    d.tiles_x[TILING_FUSED] = (d.nx + FUSED_TX - 1) / FUSED_TX;
+    d.tiles_y[TILING_FUSED] = (d.ny + seg_rows - 1) / seg_rows;
+    d.tile_base[TILING_FUSED] = base;
+    d.part_base[TILING_FUSED] = part;
+    base += d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED];
+    part += (int64_t)d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED] * d.ndrop * 3;
+  }
+  L.nsegs = base;
+  L.seg_rows = seg_rows;
+  std::vector<TileDev> natural;
+  natural.reserve(base);
+  for (size_t i = 0; i < L.inst.size(); ++i) {
+    const InstDev& d = L.inst[i];
+    for (int ty = 0; ty < d.tiles_y[TILING_FUSED]; ++ty)
+      for (int tx = 0; tx < d.tiles_x[TILING_FUSED]; ++tx)
+        natural.push_back(TileDev{(int32_t)i, tx * FUSED_TX, ty * seg_rows, (int32_t)natural.size()});
+  }
+  const int nxcd = 8;
+  const int chunk = (base + nxcd - 1) / nxcd;
+  L.segs.assign((size_t)chunk * nxcd, TileDev{-1, 0, 0, -1});
+  for (int t = 0; t < base; ++t) L.segs[(size_t)(t % chunk) * nxcd + t / chunk] = natural[t];
 }
 
 }  // namespace
@@ -454,6 +487,7 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
   }
   lbm_ctx* c = new lbm_ctx();
   make_layout(ninst, cfgs, ndrop, c->L);
+  set_segments(c->L, SEG_ROWS_DEFAULT);
   if (workspace_bytes < c->L.total) {
     delete c;
     return fail(LBM_E_NOMEM, "workspace smaller than lbm_workspace_bytes()");
@@ -498,7 +532,7 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
                           c->stream));
   INIT_CHK(hipMemcpyAsync(c->d_drops(), dd.data(), sizeof(DropDev) * dd.size(), hipMemcpyHostToDevice, c->stream));
   INIT_CHK(hipMemcpyAsync(c->d_step(), &c->step, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-  INIT_CHK(hipMemsetAsync(c->d_mask(), 0, sizeof(uint64_t) * MASK_WORDS * std::max(c->L.ntiles, c->L.nsegs),
+  INIT_CHK(hipMemsetAsync(c->d_mask(), 0, sizeof(uint64_t) * MASK_WORDS * std::max(c->L.ntiles, c->L.max_segs),
                           c->stream));
   // first centre-of-mass pass on phi0, started from the given centres
   if (c->L.prec == LBM_FP64)
@@ -679,6 +713,91 @@ int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
   if (e != hipSuccess) return fail(LBM_E_HIP, std::string("timed launch: ") + hipGetErrorString(e));
   if (es != hipSuccess) return fail(LBM_E_HIP, std::string("timed sync: ") + hipGetErrorString(es));
   for (int j = 0; j < 3; ++j) ms_out[j] = acc[j] / (double)n;
+  return LBM_OK;
+}
+
+int lbm_set_seg_rows(lbm_ctx* c, int32_t rows) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  bool ok = false;
+  for (int r : SEG_ROWS_CANDIDATES) ok = ok || r == rows;
+  if (!ok) return fail(LBM_E_INVAL, "segment height must be one of 16, 32, 64, 128, 256");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  destroy_graphs(c);
+  set_segments(c->L, rows);
+  HIPCHK(hipMemcpyAsync(c->d_inst(), c->L.inst.data(), sizeof(InstDev) * c->L.inst.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_segs(), c->L.segs.data(), sizeof(TileDev) * c->L.segs.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int32_t lbm_get_seg_rows(const lbm_ctx* c) { return c ? c->L.seg_rows : -1; }
+
+int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t* chosen, double* ms_out) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  if (launches <= 0) return fail(LBM_E_INVAL, "launches must be > 0");
+  if (c->path != LBM_PATH_FUSED) {
+    if (chosen) *chosen = c->L.seg_rows;
+    return LBM_OK;
+  }
+  int max_ny = 0;
+  for (const auto& d : c->L.inst) max_ny = std::max(max_ny, (int)d.ny);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = c->L.seg_rows;
+  double best_ms = 1e300;
+  int rc = LBM_OK;
+  const int ncand = (int)(sizeof(SEG_ROWS_CANDIDATES) / sizeof(SEG_ROWS_CANDIDATES[0]));
+  std::vector<double> cand_ms(ncand, 1e300);
+  // Trial launches read the current state and write only the inactive half of every ping-pong buffer
+  // and the partials; the parity, the droplet table and the step counter are untouched.  Launches of
+  // one candidate run back to back; two passes over the candidates (the first also warms clocks and
+  // caches), keeping each candidate's faster pass.
+  auto trial = [&](int n) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int rep = 0; rep < n && e == hipSuccess; ++rep)
+      e = c->L.prec == LBM_FP64
+              ? launch_step<double>(c->stream, c->parity, c->nseglaunch(), c->d_segs(), c->d_inst(),
+                                    reinterpret_cast<double*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask(),
+                                    c->d_step(), nullptr, -1)
+              : launch_step<float>(c->stream, c->parity, c->nseglaunch(), c->d_segs(), c->d_inst(),
+                                   reinterpret_cast<float*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask(),
+                                   c->d_step(), nullptr, -1);
+    return e;
+  };
+  for (int pass = 0; pass < 2 && rc == LBM_OK; ++pass) {
+    for (int k = 0; k < ncand; ++k) {
+      const int rows = SEG_ROWS_CANDIDATES[k];
+      if (rows > 2 * max_ny && rows != SEG_ROWS_MIN) continue;  // same strips as a smaller height
+      if ((rc = lbm_set_seg_rows(c, rows)) != LBM_OK) break;
+      hipError_t e = trial(1);
+      (void)hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) e = trial(launches);
+      (void)hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e != hipSuccess) {
+        rc = fail(LBM_E_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      cand_ms[k] = std::min(cand_ms[k], (double)ms / launches);
+    }
+  }
+  for (int k = 0; k < ncand; ++k) {
+    if (ms_out) ms_out[k] = cand_ms[k] < 1e299 ? cand_ms[k] : -1.0;
+    if (cand_ms[k] < best_ms) {
+      best_ms = cand_ms[k];
+      best = SEG_ROWS_CANDIDATES[k];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != LBM_OK) return rc;
+  if ((rc = lbm_set_seg_rows(c, best)) != LBM_OK) return rc;
+  if (chosen) *chosen = best;
   return LBM_OK;
 }
 

@@ -16,7 +16,10 @@ constexpr int NTHREADS = 256;
 constexpr int FUSED_LANES = 64;
 constexpr int FUSED_TX = FUSED_LANES - 10;
 constexpr int FUSED_R = 4;
-constexpr int FUSED_SY = 64;
+// Rows per strip segment: chosen at run time among these (the autotuner picks one per context).
+constexpr int SEG_ROWS_MIN = 16;
+constexpr int SEG_ROWS_DEFAULT = 64;
+constexpr int SEG_ROWS_CANDIDATES[] = {16, 32, 64, 128, 256};
 // Tilings: 0 = split-kernel tiles, 1 = fused-kernel strips.
 constexpr int TILING_SPLIT = 0;
 constexpr int TILING_FUSED = 1;
@@ -27,7 +30,7 @@ constexpr int MASK_WORDS = MAXDROP / 64;  // one presence bit per droplet and ti
 struct InstDev {
   int32_t nx, ny, pitch, ndrop;
   int32_t tiles_x[2], tiles_y[2], tile_base[2];  // per tiling: counts and first natural index
-  int32_t drop_base, pad1;
+  int32_t drop_base, seg_rows;  // seg_rows: rows per fused-kernel strip segment
   int64_t off_f[2];    // element offsets of the two population buffers [9][ny][pitch]
   int64_t off_phi[2];  // the two phi buffers [ny][pitch]
   int64_t off_c[2];    // the two c buffers

@@ -17,6 +17,12 @@
 // Floating-point expressions keep the grouping of the plain definitions (x- and y-reflection
 // symmetric sums); the library is compiled without FMA contraction, so the FP64 path is IEEE
 // arithmetic in a fixed order.
+//
+// This header holds the templated kernels; lbm_kernels_f64.hip and lbm_kernels_f32.hip instantiate them
+// for one precision each, so that each translation unit gets its own floating-point contraction
+// setting (none for FP64, whose arithmetic follows the plain definitions term by term; fused
+// multiply-add for FP32).
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.h"
@@ -33,6 +39,12 @@ __device__ __forceinline__ constexpr T cst(double x) {
 __device__ __forceinline__ int wrap_idx(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
+}
+
+// Periodic wrap of an index that lies within 8 nodes of [0, n): one conditional when n >= 8.
+__device__ __forceinline__ int wrap_near(int v, int n) {
+  if (n >= 8) return v < 0 ? v + n : (v >= n ? v - n : v);
+  return wrap_idx(v, n);
 }
 
 __device__ __forceinline__ double minimg(double d, double L) {
@@ -686,7 +698,7 @@ __global__ __launch_bounds__(NTHREADS) void k_obs(int parity, const TileDev* __r
 }
 
 // ------------------------------------------------------------------------------------------------
-// Fused timestep.  A workgroup owns the strip [x0, x0 + FUSED_TX) x [y0, y0 + FUSED_SY) of one
+// Fused timestep.  A workgroup owns the strip [x0, x0 + FUSED_TX) x [y0, y0 + seg_rows) of one
 // instance and sweeps it in y.  Lane l of every wavefront handles column x0 + l - 5 (periodic), so a
 // row of 64 lanes covers the strip plus 5 halo columns on each side.  The six stages of the step are
 // skewed by one row and keep their recent rows in 8-row LDS rings:
@@ -803,7 +815,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nx = I.nx, ny = I.ny, pitch = I.pitch, nd = I.ndrop;
   const int x0 = sd.x0, y0 = sd.y0;
-  const int yend = min(y0 + FUSED_SY, ny);
+  const int yend = min(y0 + I.seg_rows, ny);
   const int xend = min(x0 + FUSED_TX, nx);
   const int col = lane - 5;                   // column offset of this lane
   const int gx = wrap_idx(x0 + col, nx);      // periodic global column
@@ -878,7 +890,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   auto load_s0 = [&](int it) {
     const int r = y0 - 5 + it * FUSED_R + wv;
     if (r < yend + 5) {
-      const int gy = wrap_idx(r, ny);
+      const int gy = wrap_near(r, ny);
       const int64_t o = (int64_t)gy * pitch + gx;
       pf_phi = phi_in[o];
       pf_c = c_in[o];
@@ -887,7 +899,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   auto load_s2 = [&](int it) {
     const int r = y0 - 5 + it * FUSED_R + wv - 2;
     if (l2 && r >= y0 - 3 && r < yend + 3) {
-      const int gy = wrap_idx(r, ny);
+      const int gy = wrap_near(r, ny);
       const int gym = gy == 0 ? ny - 1 : gy - 1, gyp = gy == ny - 1 ? 0 : gy + 1;
       const int64_t r0 = (int64_t)gy * pitch, rm = (int64_t)gym * pitch, rp = (int64_t)gyp * pitch;
       pf[0] = fin[r0 + gx];
@@ -1190,13 +1202,6 @@ hipError_t launch_cm_partials(hipStream_t s, int parity, int ntiles_launch, cons
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(hipStream_t s, int tiling, int ndrop_total, const InstDev* inst, DropDev* drops,
-                         const double* part, const uint64_t* mask, int64_t* step, int increment) {
-  hipLaunchKernelGGL(k_reduce, dim3(ndrop_total > 0 ? ndrop_total : 1), dim3(NTHREADS), 0, s, tiling,
-                     ndrop_total, inst, drops, part, mask, step, increment);
-  return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
                       const InstDev* inst, T* buf, const DropDev* drops, double* obs_part, int obs_stride) {
@@ -1232,7 +1237,5 @@ hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev
   template hipError_t launch_step<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*, const DropDev*,  \
                                      double*, uint64_t*, const int64_t*, double*, int);
 
-LBM_INSTANTIATE(double)
-LBM_INSTANTIATE(float)
 
 }  // namespace lbm

@@ -27,8 +27,9 @@ STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "p
 ]
 EXPORTED = ["lbm_workspace_bytes", "lbm_init_batch", "lbm_init", "lbm_step", "lbm_set_graph", "lbm_sync",
             "lbm_get_step", "lbm_fields", "lbm_observables", "lbm_droplets", "lbm_debug_stage",
-            "lbm_time_kernels", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_destroy",
-            "lbm_last_error"]
+            "lbm_time_kernels", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_set_seg_rows",
+            "lbm_get_seg_rows", "lbm_autotune", "lbm_destroy", "lbm_last_error"]
+SEG_ROWS_CANDIDATES = (16, 32, 64, 128, 256)
 
 
 class LBMError(RuntimeError):
@@ -88,6 +89,10 @@ def load_library(path: Optional[str] = None):
     lib.lbm_set_path.argtypes = [vp, C.c_int32]
     lib.lbm_get_path.argtypes = [vp]
     lib.lbm_get_path.restype = C.c_int32
+    lib.lbm_set_seg_rows.argtypes = [vp, C.c_int32]
+    lib.lbm_get_seg_rows.argtypes = [vp]
+    lib.lbm_get_seg_rows.restype = C.c_int32
+    lib.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), dp]
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.restype = C.c_char_p
@@ -205,6 +210,21 @@ def lbm_get_path(ctx: int) -> int:
     return int(load_library().lbm_get_path(C.c_void_p(ctx)))
 
 
+def lbm_set_seg_rows(ctx: int, rows: int) -> None:
+    _check(load_library().lbm_set_seg_rows(C.c_void_p(ctx), int(rows)))
+
+
+def lbm_get_seg_rows(ctx: int) -> int:
+    return int(load_library().lbm_get_seg_rows(C.c_void_p(ctx)))
+
+
+def lbm_autotune(ctx: int, launches: int):
+    chosen = C.c_int32(0)
+    ms = np.zeros(len(SEG_ROWS_CANDIDATES))
+    _check(load_library().lbm_autotune(C.c_void_p(ctx), int(launches), C.byref(chosen), _dptr(ms)))
+    return int(chosen.value), {r: float(m) for r, m in zip(SEG_ROWS_CANDIDATES, ms) if m >= 0}
+
+
 def lbm_destroy(ctx: int) -> None:
     load_library().lbm_destroy(C.c_void_p(ctx))
 
@@ -301,6 +321,13 @@ class Sim:
 
     def set_path(self, path: int) -> None:
         lbm_set_path(self.ctx, path)
+
+    def set_seg_rows(self, rows: int) -> None:
+        lbm_set_seg_rows(self.ctx, rows)
+
+    def autotune(self, launches: int = 5):
+        """Pick the fused kernel's segment height by timing each candidate (the state is unchanged)."""
+        return lbm_autotune(self.ctx, launches)
 
     def time_kernels(self, n: int) -> Dict[str, float]:
         """Average ms per launch of each kernel of the current path (hipEvents on the library's stream)."""

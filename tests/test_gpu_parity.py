@@ -256,3 +256,52 @@ def test_no_droplets_and_tiny_lattice():
     ref.run(25)
     compare(sim.fields(), ref.fields(), 1e-12, "tiny 3x4")
     sim.close()
+
+
+def test_segment_heights_agree_bitwise_and_autotune_keeps_state():
+    """The fused kernel's strip height changes only the work decomposition: every height gives the same
+    bits; the autotuner's trial launches leave the state, droplets and step counter untouched."""
+    w = W.c5_emulsion(n=300, ndrop=4, R=14.0, seed=31)
+    ref = None
+    for rows in (16, 32, 64, 128, 256):
+        s = gpu_sim(w, graph_steps=0)
+        s.set_seg_rows(rows)
+        s.step(37)
+        f = s.fields()
+        if ref is None:
+            ref = f
+        else:
+            for k in FIELDS:
+                assert np.array_equal(f[k], ref[k]), (rows, k)
+        s.close()
+    s = gpu_sim(w, graph_steps=10)
+    s.step(5)
+    before, drops_before, step_before = s.fields(), s.droplets(), s.step_count
+    chosen, times = s.autotune(3)
+    assert chosen in (16, 32, 64, 128, 256) and len(times) >= 3
+    after = s.fields()
+    for k in FIELDS:
+        assert np.array_equal(before[k], after[k]), k
+    assert s.droplets() == drops_before and s.step_count == step_before
+    s.step(32)
+    f = s.fields()
+    for k in FIELDS:
+        assert np.array_equal(f[k], ref[k]), k
+    s.close()
+
+
+def test_fp32_batched_instances_match_single_runs():
+    """Batching does not change any instance's arithmetic (FP32, uneven sizes)."""
+    lbm = _lbm()
+    ws = W.c3_batch()[::7]
+    sim = lbm.Sim([w.param_dict() for w in ws], [w.phi0 for w in ws], [w.c0 for w in ws],
+                  [w.drop_dicts() for w in ws], precision=lbm.LBM_FP32, graph_steps=10)
+    sim.step(60)
+    for i, w in enumerate(ws):
+        single = gpu_sim(w, precision=1, graph_steps=10)
+        single.step(60)
+        a, b = sim.fields(i), single.fields()
+        for k in FIELDS:
+            assert np.array_equal(a[k], b[k]), (w.name, k)
+        single.close()
+    sim.close()
