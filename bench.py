@@ -40,9 +40,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, precision: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel source (null otherwise)."""
+def measured_traffic(kernel: str, workload: str, precision: str, seg_rows):
+    """HBM bytes per launch from the committed rocprofv3 counter summary (profiles/traffic.json), if it
+    was taken on the current kernel source and the same strip height (null otherwise)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -52,7 +52,9 @@ def measured_traffic(kernel: str, workload: str, precision: str):
     if data.get("kernel_source_hash") != kernel_source_hash():
         return None
     ent = data.get("entries", {}).get(f"{kernel}:{workload}:{precision}")
-    return None if ent is None else ent.get("bytes_per_launch")
+    if ent is None or ent.get("seg_rows") != seg_rows:
+        return None
+    return ent.get("bytes_per_launch")
 
 
 def build_sim(workloads, precision, graph_steps, path):
@@ -78,10 +80,16 @@ def time_steps(sim, steps, warmup):
     return ms, wall
 
 
-def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=0):
+def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=0, seg_rows=0):
     from paper_1711_10984_amd import lbm
     sim = build_sim(workloads, precision, graph_steps, path)
-    seg_rows, tune_ms = sim.autotune(5) if path == 0 else (None, {})
+    tune_ms = {}
+    if path == 0 and seg_rows == 0:
+        seg_rows, tune_ms = sim.autotune(10)  # state-preserving: trial launches write scratch only
+    elif path == 0:
+        sim.set_seg_rows(seg_rows)
+    else:
+        seg_rows = None
     nodes = sum(w.nodes for w in workloads)
     ms, wall = time_steps(sim, steps, warmup)
     obs = sim.observables(0)
@@ -95,7 +103,7 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     step_bytes = VALUES_PER_NODE["step"] * elem * nodes
     step_gbs = step_bytes / (ms * 1e-3 / steps) / 1e9
     prec = "fp64" if precision == lbm.LBM_FP64 else "fp32"
-    traffic = measured_traffic(dom, label, prec)
+    traffic = measured_traffic(dom, label, prec, seg_rows)
     return {
         "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
         "kernel_ms": per_kernel, "seg_rows": seg_rows, "autotune_ms": tune_ms,
@@ -134,6 +142,9 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=50, help="steps timed per kernel with hipEvents")
     ap.add_argument("--no-variants", action="store_true", help="FP64 2048^2 only")
     ap.add_argument("--path", type=int, default=0, help="0: fused sweep kernel, 1: split LB + FD kernels")
+    ap.add_argument("--seg-rows", type=int, default=0, help="fused-kernel strip height (0: autotune)")
+    ap.add_argument("--only", choices=["fp64", "fp32", "c3"], default=None,
+                    help="run one configuration (for profiling); the JSON line then reports that one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -158,14 +169,22 @@ def main():
         torch.cuda.synchronize()
 
     c5 = W.c5_emulsion()
+    if args.only in ("fp32", "c3"):
+        wl, prec, label = ([c5], lbm.LBM_FP32, "c5") if args.only == "fp32" else (W.c3_batch(), lbm.LBM_FP32, "c3")
+        r = measure(wl, prec, args.steps, args.warmup, args.graph_steps, label, args.prof_steps, args.path,
+                    args.seg_rows)
+        print(json.dumps({"only": args.only, "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
+                          "roofline": r["roofline"], "kernel_ms": r["kernel_ms"], "seg_rows": r["seg_rows"]}),
+              flush=True)
+        return
     main_res = measure([c5], lbm.LBM_FP64, args.steps, args.warmup, args.graph_steps, "c5", args.prof_steps,
-                       args.path)
+                       args.path, args.seg_rows)
     variants = {}
-    if not args.no_variants:
+    if not args.no_variants and args.only is None:
         variants["fp32_2048"] = measure([c5], lbm.LBM_FP32, args.steps, args.warmup, args.graph_steps, "c5",
-                                        args.prof_steps, args.path)
+                                        args.prof_steps, args.path, args.seg_rows)
         variants["batched_c3_fp32"] = measure(W.c3_batch(), lbm.LBM_FP32, args.steps, args.warmup,
-                                              args.graph_steps, "c3", args.prof_steps, args.path)
+                                              args.graph_steps, "c3", args.prof_steps, args.path, args.seg_rows)
     for v in variants.values():
         v["gain_over_fp64"] = round(v["mlups"] / main_res["mlups"], 3)
     out = {
