@@ -117,6 +117,45 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     }
 
 
+def _minimg(d, L):
+    return (d + 0.5 * L) % L - 0.5 * L
+
+
+def fp32_accuracy(workloads, steps, log_every, graph_steps):
+    """FP32 against FP64 on the GPU for the same inputs: largest centre-of-mass deviation over the run
+    (trajectories logged every `log_every` steps), drift of the phi integral in both precisions, and the
+    relative L2 difference of the velocity field at the end (first lattice)."""
+    import numpy as np
+    from paper_1711_10984_amd import lbm
+    traj = {}
+    end = {}
+    phi_sum = {}
+    for prec in (lbm.LBM_FP64, lbm.LBM_FP32):
+        sim = build_sim(workloads, prec, graph_steps, 0)
+        t = []
+        s0 = [sim.observables(i)["sum_phi"] for i in range(len(workloads))]
+        for k in range(steps // log_every):
+            sim.step(log_every)
+            t.append([[(d["x"], d["y"]) for d in sim.droplets(i)] for i in range(len(workloads))])
+        traj[prec] = t
+        end[prec] = sim.fields(0)
+        phi_sum[prec] = [sim.observables(i)["sum_phi"] - s0[i] for i in range(len(workloads))]
+        sim.close()
+    dev = 0.0
+    for a, b in zip(traj[lbm.LBM_FP64], traj[lbm.LBM_FP32]):
+        for i, w in enumerate(workloads):
+            for (xa, ya), (xb, yb) in zip(a[i], b[i]):
+                dev = max(dev, float(np.hypot(_minimg(xa - xb, w.nx), _minimg(ya - yb, w.ny))))
+    u64, u32 = end[lbm.LBM_FP64], end[lbm.LBM_FP32]
+    num = np.sqrt(np.sum((u64["ux"] - u32["ux"]) ** 2 + (u64["uy"] - u32["uy"]) ** 2))
+    den = np.sqrt(np.sum(u64["ux"] ** 2 + u64["uy"] ** 2))
+    return {"steps": steps, "lattices": len(workloads), "log_every": log_every,
+            "max_cm_deviation_lu": round(dev, 6),
+            "phi_integral_drift_fp64": round(float(max(phi_sum[lbm.LBM_FP64], key=abs)), 6),
+            "phi_integral_drift_fp32": round(float(max(phi_sum[lbm.LBM_FP32], key=abs)), 6),
+            "velocity_l2_rel_diff": float(num / den) if den > 0 else None}
+
+
 def cpu_baseline(w, budget_s):
     """The FP64 oracle as it stands on this host's cores, on a bounded sample of the same workload."""
     from oracle import OracleSim, Params, Drop
@@ -147,6 +186,7 @@ def main():
                     help="run one configuration (for profiling); the JSON line then reports that one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-vs-FP64 accuracy runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (reference for rocprofv3 counters)")
     args = ap.parse_args()
@@ -213,6 +253,11 @@ def main():
                          "kernel_ms": v["kernel_ms"], "seg_rows": v["seg_rows"]} for k, v in variants.items()},
         "kernel_source_hash": kernel_source_hash(),
     }
+    if not args.no_accuracy and not args.no_variants:
+        out["fp32_accuracy"] = {
+            "single_droplet_256": fp32_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps),
+            "batched_c3": fp32_accuracy(W.c3_batch(), 20000, 100, args.graph_steps),
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c5, args.cpu_budget)
     print(json.dumps(out), flush=True)
