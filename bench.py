@@ -26,10 +26,12 @@ METRIC = "MLUPS of coupled LB+FD step and % HBM roofline, FP64 vs FP32 vs batche
 
 # Algorithmic values moved per lattice node by each kernel of the timestep (element size x count).
 #   k_step (fused): reads 9 populations + phi + c, writes the same          -> 22 values
+#   k_wave (fused, one wavefront per strip): the same                      -> 22 values
 #   k_lb (split):   reads 9 populations + phi + c, writes 9 populations + ux + uy -> 22 values
 #   k_fd (split):   reads phi + c + ux + uy, writes phi + c                   ->  6 values
 #   whole step, state only (9 populations + phi + c read and written)        -> 22 values
-VALUES_PER_NODE = {"k_step": 22, "k_lb": 22, "k_fd": 6, "step": 22}
+VALUES_PER_NODE = {"k_step": 22, "k_wave": 22, "k_lb": 22, "k_fd": 6, "step": 22}
+PATH_NAMES = {0: "fused", 1: "split", 2: "wave"}
 
 
 def kernel_source_hash() -> str:
@@ -80,13 +82,17 @@ def time_steps(sim, steps, warmup):
     return ms, wall
 
 
-def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=0, seg_rows=0):
+def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=-1, seg_rows=0):
+    """path -1: the autotuner picks the sweeping kernel (fused or wave) and its strip height."""
     from paper_1711_10984_amd import lbm
-    sim = build_sim(workloads, precision, graph_steps, path)
+    sim = build_sim(workloads, precision, graph_steps, 0 if path < 0 else path)
     tune_ms = {}
-    if path == 0 and seg_rows == 0:
-        seg_rows, tune_ms = sim.autotune(10)  # state-preserving: trial launches write scratch only
-    elif path == 0:
+    if path != 1 and seg_rows == 0:
+        # state-preserving: the trial launches write scratch only
+        seg_rows, path, tune_ms = sim.autotune(10, both_paths=path < 0)
+    elif path != 1:
+        if path < 0:
+            path = 0
         sim.set_seg_rows(seg_rows)
     else:
         seg_rows = None
@@ -106,7 +112,7 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     traffic = measured_traffic(dom, label, prec, seg_rows)
     return {
         "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
-        "kernel_ms": per_kernel, "seg_rows": seg_rows, "autotune_ms": tune_ms,
+        "kernel_ms": per_kernel, "seg_rows": seg_rows, "autotune_ms": tune_ms, "path": PATH_NAMES[path],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": per_kernel[dom]},
@@ -121,7 +127,7 @@ def _minimg(d, L):
     return (d + 0.5 * L) % L - 0.5 * L
 
 
-def fp32_accuracy(workloads, steps, log_every, graph_steps):
+def fp32_accuracy(workloads, steps, log_every, graph_steps, path):
     """FP32 against FP64 on the GPU for the same inputs: largest centre-of-mass deviation over the run
     (trajectories logged every `log_every` steps), drift of the phi integral in both precisions, and the
     relative L2 difference of the velocity field at the end (first lattice)."""
@@ -131,7 +137,7 @@ def fp32_accuracy(workloads, steps, log_every, graph_steps):
     end = {}
     phi_sum = {}
     for prec in (lbm.LBM_FP64, lbm.LBM_FP32):
-        sim = build_sim(workloads, prec, graph_steps, 0)
+        sim = build_sim(workloads, prec, graph_steps, max(path, 0))
         t = []
         s0 = [sim.observables(i)["sum_phi"] for i in range(len(workloads))]
         for k in range(steps // log_every):
@@ -180,7 +186,9 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=20)
     ap.add_argument("--prof-steps", type=int, default=50, help="steps timed per kernel with hipEvents")
     ap.add_argument("--no-variants", action="store_true", help="FP64 2048^2 only")
-    ap.add_argument("--path", type=int, default=0, help="0: fused sweep kernel, 1: split LB + FD kernels")
+    ap.add_argument("--path", type=int, default=-1, choices=[-1] + sorted(PATH_NAMES),
+                    help="-1: autotuned choice of 0 or 2; 0: fused sweep kernel; 1: split LB + FD kernels; "
+                         "2: wavefront-per-strip sweep kernel")
     ap.add_argument("--seg-rows", type=int, default=0, help="fused-kernel strip height (0: autotune)")
     ap.add_argument("--only", choices=["fp64", "fp32", "c3"], default=None,
                     help="run one configuration (for profiling); the JSON line then reports that one")
@@ -214,7 +222,8 @@ def main():
         r = measure(wl, prec, args.steps, args.warmup, args.graph_steps, label, args.prof_steps, args.path,
                     args.seg_rows)
         print(json.dumps({"only": args.only, "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
-                          "roofline": r["roofline"], "kernel_ms": r["kernel_ms"], "seg_rows": r["seg_rows"]}),
+                          "roofline": r["roofline"], "kernel_ms": r["kernel_ms"], "seg_rows": r["seg_rows"],
+                          "path": r["path"]}),
               flush=True)
         return
     main_res = measure([c5], lbm.LBM_FP64, args.steps, args.warmup, args.graph_steps, "c5", args.prof_steps,
@@ -242,21 +251,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2048x2048 periodic dilute emulsion, 64 active droplets R=20 (seeded), FP64",
                    "nx": 2048, "ny": 2048, "droplets": 64, "graph_steps": args.graph_steps,
-                   "kernel_path": "fused" if args.path == 0 else "split"},
+                   "kernel_path": main_res["path"]},
         "roofline": main_res["roofline"],
         "step_roofline": main_res["step_roofline"],
         "kernel_ms": main_res["kernel_ms"],
-        "autotune": {"seg_rows": main_res["seg_rows"], "ms_per_launch": main_res["autotune_ms"]},
+        "autotune": {"seg_rows": main_res["seg_rows"], "path": main_res["path"],
+                     "ms_per_launch": main_res["autotune_ms"]},
         "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
                          "nodes": v["nodes"], "precision": v["precision"], "gain_over_fp64": v["gain_over_fp64"],
                          "roofline": v["roofline"], "step_roofline": v["step_roofline"],
-                         "kernel_ms": v["kernel_ms"], "seg_rows": v["seg_rows"]} for k, v in variants.items()},
+                         "kernel_ms": v["kernel_ms"], "seg_rows": v["seg_rows"], "path": v["path"]}
+                     for k, v in variants.items()},
         "kernel_source_hash": kernel_source_hash(),
     }
     if not args.no_accuracy and not args.no_variants:
         out["fp32_accuracy"] = {
-            "single_droplet_256": fp32_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps),
-            "batched_c3": fp32_accuracy(W.c3_batch(), 20000, 100, args.graph_steps),
+            "single_droplet_256": fp32_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
+                                                args.path),
+            "batched_c3": fp32_accuracy(W.c3_batch(), 20000, 100, args.graph_steps, args.path),
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c5, args.cpu_budget)

@@ -55,6 +55,7 @@ extern "C" {
 
 #define LBM_PATH_FUSED 0 /* one sweeping kernel per step (default) */
 #define LBM_PATH_SPLIT 1 /* lattice-Boltzmann kernel, then finite-difference kernel (reference layout) */
+#define LBM_PATH_WAVE 2  /* one sweeping kernel per step, one wavefront per strip, no workgroup barriers */
 
 #define LBM_MAXDROP 256 /* droplets per instance */
 #define LBM_NSTAGE 22   /* planes written by lbm_debug_stage */
@@ -157,26 +158,39 @@ int lbm_droplets(lbm_ctx* ctx, int32_t inst, lbm_droplet* out);
  * streaming).  Instances of at most 512 x 512 nodes (LBM_E_INVAL otherwise).  Synchronous. */
 int lbm_debug_stage(lbm_ctx* ctx, int32_t inst, double* out);
 
-/* Kernel sequence used by lbm_step and lbm_debug_stage: LBM_PATH_FUSED (default) or LBM_PATH_SPLIT.
- * Both compute the same arithmetic; the split path stores u^n between its two kernels. */
+/* Kernel sequence used by lbm_step and lbm_debug_stage: LBM_PATH_FUSED (default), LBM_PATH_SPLIT or
+ * LBM_PATH_WAVE.  All compute the same arithmetic; the split path stores u^n between its two kernels,
+ * the wave path sweeps each strip with a single wavefront.  LBM_E_INVAL for another value. */
 int lbm_set_path(lbm_ctx* ctx, int32_t path);
 int32_t lbm_get_path(const lbm_ctx* ctx);
 
-/* Rows per strip segment of the fused kernel: 16, 32, 64 (default), 128 or 256.  Taller segments
- * recompute fewer halo rows; shorter ones give more workgroups.  Synchronous. */
+/* Rows per strip segment of the sweeping kernels (fused and wave paths), LBM_SEG_ROWS_MIN ..
+ * LBM_SEG_ROWS_MAX (default 64; LBM_E_INVAL outside).  Taller segments recompute fewer halo rows;
+ * shorter ones give more workgroups.  Synchronous. */
+#define LBM_SEG_ROWS_MIN 16
+#define LBM_SEG_ROWS_MAX 4096
 int lbm_set_seg_rows(lbm_ctx* ctx, int32_t rows);
 int32_t lbm_get_seg_rows(const lbm_ctx* ctx);
 
-/* Autotuner: time `launches` launches of the fused kernel for each segment height and keep the
- * fastest.  The trial launches read the current state and write only scratch (the inactive halves of
- * the ping-pong buffers and the centre-of-mass partials): the state, the droplet table and the step
- * counter are unchanged.  chosen (may be NULL) receives the height; ms_out (may be NULL, 5 entries)
- * the average ms per launch of each candidate 16, 32, 64, 128, 256 (-1 if skipped).  Synchronous. */
-int lbm_autotune(lbm_ctx* ctx, int32_t launches, int32_t* chosen, double* ms_out);
+/* The LBM_TUNE_NROWS segment heights tried by lbm_autotune, ascending (static array). */
+#define LBM_TUNE_NROWS 16
+const int32_t* lbm_tune_rows(void);
+
+/* Autotuner: time `launches` back-to-back launches of the sweeping kernel for each candidate height
+ * (heights giving the same number of segments as a smaller one are skipped) -- for both sweeping
+ * kernels (LBM_PATH_FUSED, LBM_PATH_WAVE) when both_paths != 0, else for the current path only -- and
+ * set the path and height of the fastest.  The trial launches read the current state and write only
+ * scratch (the inactive halves of the ping-pong buffers and the centre-of-mass partials): the state,
+ * the droplet table and the step counter are unchanged.  On the split path nothing is tried.
+ * rows_out, path_out (may be NULL) receive the choice; ms_out (may be NULL, 2 * LBM_TUNE_NROWS entries,
+ * [fused heights..., wave heights...]) the average ms per launch of each candidate (-1 if not tried).
+ * Synchronous. */
+int lbm_autotune(lbm_ctx* ctx, int32_t launches, int32_t both_paths, int32_t* rows_out, int32_t* path_out,
+                 double* ms_out);
 
 /* Average device time per launch (ms) of each kernel of the timestep over n eagerly launched steps,
  * measured with hipEvents on the context's stream.  Fused path: ms_out = {k_step, k_reduce, 0};
- * split path: {k_lb, k_fd, k_reduce}.  Advances the state by n steps.  Synchronous. */
+ * wave path: {k_wave, k_reduce, 0}; split path: {k_lb, k_fd, k_reduce}.  Advances the state by n steps.  Synchronous. */
 int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
 
 /* Name of kernel `which` (0..2) of lbm_time_kernels for a path (static string, "" if none). */

@@ -240,13 +240,23 @@ struct lbm_ctx {
 
 namespace {
 
+// The sweeping kernel of a strip path (LBM_PATH_FUSED or LBM_PATH_WAVE) over the strip list.
+template <typename T>
+hipError_t launch_sweep(lbm_ctx* c, int parity, double* dbg, int dbg_inst) {
+  T* buf = reinterpret_cast<T*>(c->pool());
+  if (c->path == LBM_PATH_WAVE)
+    return launch_wave<T>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(),
+                          c->d_part(), c->d_mask(), c->d_step(), dbg, dbg_inst);
+  return launch_step<T>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(), c->d_part(),
+                        c->d_mask(), c->d_step(), dbg, dbg_inst);
+}
+
 template <typename T>
 hipError_t enqueue_step(lbm_ctx* c, int parity) {
   T* buf = reinterpret_cast<T*>(c->pool());
   hipError_t e;
-  if (c->path == LBM_PATH_FUSED) {
-    e = launch_step<T>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(), c->d_part(),
-                       c->d_mask(), c->d_step(), nullptr, -1);
+  if (c->path != LBM_PATH_SPLIT) {
+    e = launch_sweep<T>(c, parity, nullptr, -1);
     if (e != hipSuccess) return e;
     return launch_reduce(c->stream, TILING_FUSED, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(),
                          c->d_mask(), c->d_step(), 1);
@@ -398,9 +408,7 @@ int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, do
 template <typename T>
 hipError_t debug_launch(lbm_ctx* c, int inst) {
   T* buf = reinterpret_cast<T*>(c->pool());
-  if (c->path == LBM_PATH_FUSED)
-    return launch_step<T>(c->stream, c->parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(),
-                          c->d_part(), c->d_mask(), c->d_step(), c->d_dbg(), inst);
+  if (c->path != LBM_PATH_SPLIT) return launch_sweep<T>(c, c->parity, c->d_dbg(), inst);
   hipError_t e = launch_lb<T>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
   if (e != hipSuccess) return e;
   return launch_fd<T>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
@@ -414,9 +422,8 @@ hipError_t timed_step(lbm_ctx* c, hipEvent_t* ev, int* nk) {
   const int p = c->parity;
   hipError_t e;
   (void)hipEventRecord(ev[0], c->stream);
-  if (c->path == LBM_PATH_FUSED) {
-    e = launch_step<T>(c->stream, p, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(), c->d_part(),
-                       c->d_mask(), c->d_step(), nullptr, -1);
+  if (c->path != LBM_PATH_SPLIT) {
+    e = launch_sweep<T>(c, p, nullptr, -1);
     (void)hipEventRecord(ev[1], c->stream);
     if (e == hipSuccess)
       e = launch_reduce(c->stream, TILING_FUSED, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
@@ -718,9 +725,9 @@ int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
 
 int lbm_set_seg_rows(lbm_ctx* c, int32_t rows) {
   if (!c) return fail(LBM_E_INVAL, "null context");
-  bool ok = false;
-  for (int r : SEG_ROWS_CANDIDATES) ok = ok || r == rows;
-  if (!ok) return fail(LBM_E_INVAL, "segment height must be one of 16, 32, 64, 128, 256");
+  if (rows < SEG_ROWS_MIN || rows > SEG_ROWS_MAX)
+    return fail(LBM_E_INVAL, "segment height must lie in [" + std::to_string(SEG_ROWS_MIN) + ", " +
+                                 std::to_string(SEG_ROWS_MAX) + "]");
   HIPCHK(hipStreamSynchronize(c->stream));
   destroy_graphs(c);
   set_segments(c->L, rows);
@@ -734,23 +741,39 @@ int lbm_set_seg_rows(lbm_ctx* c, int32_t rows) {
 
 int32_t lbm_get_seg_rows(const lbm_ctx* c) { return c ? c->L.seg_rows : -1; }
 
-int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t* chosen, double* ms_out) {
+const int32_t* lbm_tune_rows(void) { return TUNE_ROWS; }
+
+int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows_out, int32_t* path_out,
+                 double* ms_out) {
   if (!c) return fail(LBM_E_INVAL, "null context");
   if (launches <= 0) return fail(LBM_E_INVAL, "launches must be > 0");
-  if (c->path != LBM_PATH_FUSED) {
-    if (chosen) *chosen = c->L.seg_rows;
+  if (ms_out)
+    for (int k = 0; k < 2 * LBM_TUNE_NROWS; ++k) ms_out[k] = -1.0;
+  if (c->path == LBM_PATH_SPLIT) {
+    if (rows_out) *rows_out = c->L.seg_rows;
+    if (path_out) *path_out = c->path;
     return LBM_OK;
   }
-  int max_ny = 0;
-  for (const auto& d : c->L.inst) max_ny = std::max(max_ny, (int)d.ny);
+  const int paths[2] = {LBM_PATH_FUSED, LBM_PATH_WAVE};
+  const int start_path = c->path;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int best = c->L.seg_rows;
+  int best_rows = c->L.seg_rows, best_path = c->path;
   double best_ms = 1e300;
   int rc = LBM_OK;
-  const int ncand = (int)(sizeof(SEG_ROWS_CANDIDATES) / sizeof(SEG_ROWS_CANDIDATES[0]));
-  std::vector<double> cand_ms(ncand, 1e300);
+  std::vector<double> cand_ms(2 * LBM_TUNE_NROWS, 1e300);
+  // Heights that give the same number of strip segments as a smaller candidate are skipped.
+  std::vector<bool> skip(LBM_TUNE_NROWS, false);
+  {
+    std::vector<int64_t> seen;
+    for (int k = 0; k < LBM_TUNE_NROWS; ++k) {
+      int64_t nseg = 0;
+      for (const auto& d : c->L.inst) nseg += (d.ny + TUNE_ROWS[k] - 1) / TUNE_ROWS[k];
+      skip[k] = std::find(seen.begin(), seen.end(), nseg) != seen.end();
+      seen.push_back(nseg);
+    }
+  }
   // Trial launches read the current state and write only the inactive half of every ping-pong buffer
   // and the partials; the parity, the droplet table and the step counter are untouched.  Launches of
   // one candidate run back to back; two passes over the candidates (the first also warms clocks and
@@ -758,59 +781,66 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t* chosen, double* ms_out) 
   auto trial = [&](int n) -> hipError_t {
     hipError_t e = hipSuccess;
     for (int rep = 0; rep < n && e == hipSuccess; ++rep)
-      e = c->L.prec == LBM_FP64
-              ? launch_step<double>(c->stream, c->parity, c->nseglaunch(), c->d_segs(), c->d_inst(),
-                                    reinterpret_cast<double*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask(),
-                                    c->d_step(), nullptr, -1)
-              : launch_step<float>(c->stream, c->parity, c->nseglaunch(), c->d_segs(), c->d_inst(),
-                                   reinterpret_cast<float*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask(),
-                                   c->d_step(), nullptr, -1);
+      e = c->L.prec == LBM_FP64 ? launch_sweep<double>(c, c->parity, nullptr, -1)
+                                : launch_sweep<float>(c, c->parity, nullptr, -1);
     return e;
   };
   for (int pass = 0; pass < 2 && rc == LBM_OK; ++pass) {
-    for (int k = 0; k < ncand; ++k) {
-      const int rows = SEG_ROWS_CANDIDATES[k];
-      if (rows > 2 * max_ny && rows != SEG_ROWS_MIN) continue;  // same strips as a smaller height
-      if ((rc = lbm_set_seg_rows(c, rows)) != LBM_OK) break;
-      hipError_t e = trial(1);
-      (void)hipEventRecord(e0, c->stream);
-      if (e == hipSuccess) e = trial(launches);
-      (void)hipEventRecord(e1, c->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e != hipSuccess) {
-        rc = fail(LBM_E_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
-        break;
+    for (int pi = 0; pi < 2 && rc == LBM_OK; ++pi) {
+      if (!both_paths && paths[pi] != start_path) continue;
+      c->path = paths[pi];
+      for (int k = 0; k < LBM_TUNE_NROWS; ++k) {
+        if (skip[k]) continue;
+        if ((rc = lbm_set_seg_rows(c, TUNE_ROWS[k])) != LBM_OK) break;
+        hipError_t e = trial(1);
+        (void)hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) e = trial(launches);
+        (void)hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+          rc = fail(LBM_E_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        double& m = cand_ms[pi * LBM_TUNE_NROWS + k];
+        m = std::min(m, (double)ms / launches);
       }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      cand_ms[k] = std::min(cand_ms[k], (double)ms / launches);
     }
   }
-  for (int k = 0; k < ncand; ++k) {
-    if (ms_out) ms_out[k] = cand_ms[k] < 1e299 ? cand_ms[k] : -1.0;
-    if (cand_ms[k] < best_ms) {
-      best_ms = cand_ms[k];
-      best = SEG_ROWS_CANDIDATES[k];
+  for (int pi = 0; pi < 2; ++pi)
+    for (int k = 0; k < LBM_TUNE_NROWS; ++k) {
+      const double m = cand_ms[pi * LBM_TUNE_NROWS + k];
+      if (ms_out && m < 1e299) ms_out[pi * LBM_TUNE_NROWS + k] = m;
+      if (m < best_ms) {
+        best_ms = m;
+        best_rows = TUNE_ROWS[k];
+        best_path = paths[pi];
+      }
     }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  c->path = start_path;
   if (rc != LBM_OK) return rc;
-  if ((rc = lbm_set_seg_rows(c, best)) != LBM_OK) return rc;
-  if (chosen) *chosen = best;
+  if ((rc = lbm_set_path(c, best_path)) != LBM_OK) return rc;
+  if ((rc = lbm_set_seg_rows(c, best_rows)) != LBM_OK) return rc;
+  if (rows_out) *rows_out = best_rows;
+  if (path_out) *path_out = best_path;
   return LBM_OK;
 }
 
 const char* lbm_kernel_name(int32_t path, int32_t which) {
   static const char* fused[3] = {"k_step", "k_reduce", ""};
   static const char* split[3] = {"k_lb", "k_fd", "k_reduce"};
+  static const char* wave[3] = {"k_wave", "k_reduce", ""};
   if (which < 0 || which > 2) return "";
-  return path == LBM_PATH_SPLIT ? split[which] : fused[which];
+  return path == LBM_PATH_SPLIT ? split[which] : path == LBM_PATH_WAVE ? wave[which] : fused[which];
 }
 
 int lbm_set_path(lbm_ctx* c, int32_t path) {
   if (!c) return fail(LBM_E_INVAL, "null context");
-  if (path != LBM_PATH_FUSED && path != LBM_PATH_SPLIT) return fail(LBM_E_INVAL, "unknown path");
+  if (path != LBM_PATH_FUSED && path != LBM_PATH_SPLIT && path != LBM_PATH_WAVE)
+    return fail(LBM_E_INVAL, "unknown path");
   if (path != c->path) destroy_graphs(c);
   c->path = path;
   return LBM_OK;

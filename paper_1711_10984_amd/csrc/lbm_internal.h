@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbm.h"
+
 namespace lbm {
 
 // Tile of interior nodes processed by one workgroup of the split timestep kernels.
@@ -17,9 +19,12 @@ constexpr int FUSED_LANES = 64;
 constexpr int FUSED_TX = FUSED_LANES - 10;
 constexpr int FUSED_R = 4;
 // Rows per strip segment: chosen at run time among these (the autotuner picks one per context).
-constexpr int SEG_ROWS_MIN = 16;
+constexpr int SEG_ROWS_MIN = LBM_SEG_ROWS_MIN;
+constexpr int SEG_ROWS_MAX = LBM_SEG_ROWS_MAX;
 constexpr int SEG_ROWS_DEFAULT = 64;
-constexpr int SEG_ROWS_CANDIDATES[] = {16, 32, 64, 128, 256};
+// Heights tried by the autotuner (LBM_TUNE_NROWS of them).
+constexpr int32_t TUNE_ROWS[] = {16, 20, 24, 26, 28, 32, 36, 40, 44, 48, 54, 64, 80, 96, 128, 256};
+static_assert(sizeof(TUNE_ROWS) / sizeof(TUNE_ROWS[0]) == LBM_TUNE_NROWS, "tune list length");
 // Tilings: 0 = split-kernel tiles, 1 = fused-kernel strips.
 constexpr int TILING_SPLIT = 0;
 constexpr int TILING_FUSED = 1;
@@ -71,6 +76,11 @@ hipError_t launch_reduce(hipStream_t s, int tiling, int ndrop_total, const InstD
 // instance dbg_inst instead of advancing.
 template <typename T>
 hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst,
+                       T* buf, const DropDev* drops, double* part, uint64_t* mask, const int64_t* step,
+                       double* dbg, int dbg_inst);
+// Same step as launch_step, computed by one 64-lane wavefront per strip segment (no workgroup barriers).
+template <typename T>
+hipError_t launch_wave(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst,
                        T* buf, const DropDev* drops, double* part, uint64_t* mask, const int64_t* step,
                        double* dbg, int dbg_inst);
 template <typename T>

@@ -1160,6 +1160,527 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   if (tid < MASK_WORDS) mask[(int64_t)sd.t * MASK_WORDS + tid] = sh.seg_mask[tid];
 }
 
+// ------------------------------------------------------------------------------------------------
+// Wavefront-per-strip timestep.  The same six skewed stages as k_step, but each 64-lane wavefront
+// (a workgroup of its own) owns one strip segment and sweeps it one row per iteration with no
+// workgroup barrier: the rows that a stage's y-stencil needs stay in registers (a short window per
+// field, rotated every iteration), and the x-neighbours come from whole-wave DPP lane shifts.  Lane l
+// handles column x0 + l - 5 (periodic); the 5 halo lanes per side absorb the invalid edge lanes of
+// the shifts (each stencil stage spoils one more lane at each end, five stages in all).
+
+// Whole-wave DPP lane shifts: E receives the value of lane l + 1 (the east neighbour column), W that of
+// lane l - 1 (west).  Written as one asm group per neighbourhood so that the shifted registers need no
+// initialisation (the lane without a source keeps an unspecified value; it lies in the halo) and a single
+// s_nop covers the read-after-VALU-write hazard of DPP.
+__device__ __forceinline__ void shift_ew(float v, float& e, float& w) {
+  int ei, wi;
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %2 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(ei), "=&v"(wi)
+      : "v"(__float_as_int(v)));
+  e = __int_as_float(ei);
+  w = __int_as_float(wi);
+}
+__device__ __forceinline__ void shift_ew(double v, double& e, double& w) {
+  int elo, ehi, wlo, whi;
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %4 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %1, %5 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %2, %4 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %3, %5 wave_shr:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(elo), "=&v"(ehi), "=&v"(wlo), "=&v"(whi)
+      : "v"(__double2loint(v)), "v"(__double2hiint(v)));
+  e = __hiloint2double(ehi, elo);
+  w = __hiloint2double(whi, wlo);
+}
+
+// Element at a per-lane byte offset from a wave-uniform row pointer (selects the scalar-base form of the
+// global load/store instructions).
+template <typename T>
+__device__ __forceinline__ T ld_col(const T* row, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_col(T* row, unsigned byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(row) + byte_off) = v;
+}
+
+// 64-bit value held by lane `l` (uniform) of a wavefront.
+__device__ __forceinline__ unsigned long long read_lane64(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(v & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// The nine values of a 3 x 3 neighbourhood of one lane: rows up = r + 1 (north), mid = r, dn = r - 1.
+template <typename T>
+struct Nbr {
+  T c, e, w, n, s, ne, nw, se, sw;
+};
+
+__device__ __forceinline__ Nbr<float> nbr(float up, float mid, float dn) {
+  Nbr<float> g;
+  g.c = mid;
+  g.n = up;
+  g.s = dn;
+  int r[6];
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %6 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %1, %6 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %2, %7 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %3, %7 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %4, %8 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %5, %8 wave_shr:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5])
+      : "v"(__float_as_int(mid)), "v"(__float_as_int(up)), "v"(__float_as_int(dn)));
+  g.e = __int_as_float(r[0]);
+  g.w = __int_as_float(r[1]);
+  g.ne = __int_as_float(r[2]);
+  g.nw = __int_as_float(r[3]);
+  g.se = __int_as_float(r[4]);
+  g.sw = __int_as_float(r[5]);
+  return g;
+}
+
+__device__ __forceinline__ Nbr<double> nbr(double up, double mid, double dn) {
+  Nbr<double> g;
+  g.c = mid;
+  g.n = up;
+  g.s = dn;
+  int r[12];
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %12 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %1, %13 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %2, %12 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %3, %13 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %4, %14 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %5, %15 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %6, %14 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %7, %15 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %8, %16 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %9, %17 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %10, %16 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %11, %17 wave_shr:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7]),
+        "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11])
+      : "v"(__double2loint(mid)), "v"(__double2hiint(mid)), "v"(__double2loint(up)), "v"(__double2hiint(up)),
+        "v"(__double2loint(dn)), "v"(__double2hiint(dn)));
+  g.e = __hiloint2double(r[1], r[0]);
+  g.w = __hiloint2double(r[3], r[2]);
+  g.ne = __hiloint2double(r[5], r[4]);
+  g.nw = __hiloint2double(r[7], r[6]);
+  g.se = __hiloint2double(r[9], r[8]);
+  g.sw = __hiloint2double(r[11], r[10]);
+  return g;
+}
+
+template <typename T>
+__device__ __forceinline__ void grad9n(const Nbr<T>& g, T& gx, T& gy) {
+  gx = (T(4) * (g.e - g.w) + ((g.ne - g.nw) + (g.se - g.sw))) * cst<T>(1.0 / 12.0);
+  gy = (T(4) * (g.n - g.s) + ((g.ne - g.se) + (g.nw - g.sw))) * cst<T>(1.0 / 12.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T lap9n(const Nbr<T>& g) {
+  return (T(4) * ((g.e + g.w) + (g.n + g.s)) + ((g.ne + g.nw) + (g.se + g.sw)) - T(20) * g.c) * cst<T>(1.0 / 6.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T div9n(const Nbr<T>& c, const Nbr<T>& X, T D) {
+  const T k0 = D * c.c, X0 = X.c;
+  const T t1 = (k0 + D * c.e) * (X.e - X0);
+  const T t2 = (k0 + D * c.n) * (X.n - X0);
+  const T t3 = (k0 + D * c.w) * (X.w - X0);
+  const T t4 = (k0 + D * c.s) * (X.s - X0);
+  const T t5 = (k0 + D * c.ne) * (X.ne - X0);
+  const T t6 = (k0 + D * c.nw) * (X.nw - X0);
+  const T t7 = (k0 + D * c.sw) * (X.sw - X0);
+  const T t8 = (k0 + D * c.se) * (X.se - X0);
+  return (T(4) * ((t1 + t3) + (t2 + t4)) + ((t5 + t6) + (t7 + t8))) * cst<T>(1.0 / 12.0);
+}
+
+// Advection half-step of Eqs. (16)-(17) at one lane: scalar g (centre, east, west, north, south),
+// velocity x-component at the centre and its east/west neighbours, y-component at the centre and its
+// north/south neighbours.
+template <typename T>
+__device__ __forceinline__ T advect_n(T gc, T ge, T gw, T gn, T gs, T uc, T ue, T uw, T vc, T vn, T vs, int mode) {
+  if (mode == 0) {
+    const T divu = T(0.5) * (ue - uw) + T(0.5) * (vn - vs);
+    const T dgx = uc > T(0) ? gc - gw : ge - gc;
+    const T dgy = vc > T(0) ? gc - gs : gn - gc;
+    return gc - ((gc * divu + uc * dgx) + vc * dgy);
+  }
+  const T uxr = T(0.5) * (uc + ue), uxl = T(0.5) * (uw + uc);
+  const T uyt = T(0.5) * (vc + vn), uyb = T(0.5) * (vs + vc);
+  const T Fr = uxr * (uxr >= T(0) ? gc : ge);
+  const T Fl = uxl * (uxl >= T(0) ? gw : gc);
+  const T Ft = uyt * (uyt >= T(0) ? gc : gn);
+  const T Fb = uyb * (uyb >= T(0) ? gs : gc);
+  return gc - ((Fr - Fl) + (Ft - Fb));
+}
+
+template <typename T, bool DBG>
+// Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD;
+// FP32 fits three.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
+                                             const InstDev* __restrict__ insts, T* __restrict__ buf,
+                                             const DropDev* __restrict__ drops, double* __restrict__ part,
+                                             uint64_t* __restrict__ mask, const int64_t* __restrict__ step,
+                                             double* __restrict__ dbg, int dbg_inst) {
+  __shared__ double acc[MAXDROP][3];
+
+  const TileDev sd = segs[blockIdx.x];
+  if (sd.inst < 0) return;
+  if (DBG && sd.inst != dbg_inst) return;
+  const InstDev& I = insts[sd.inst];
+  const int lane = threadIdx.x;
+  const int nx = I.nx, ny = I.ny, pitch = I.pitch, nd = I.ndrop;
+  const int x0 = sd.x0, y0 = sd.y0;
+  const int yend = min(y0 + I.seg_rows, ny);
+  const int xend = min(x0 + FUSED_TX, nx);
+  const int col = lane - 5;
+  const int gx = wrap_idx(x0 + col, nx);
+  const int gxm = gx == 0 ? nx - 1 : gx - 1, gxp = gx == nx - 1 ? 0 : gx + 1;
+  const bool own_col = col >= 0 && col < FUSED_TX && x0 + col < nx;
+  const int64_t plane = (int64_t)ny * pitch;
+  const T* __restrict__ phi_in = buf + I.off_phi[parity];
+  const T* __restrict__ c_in = buf + I.off_c[parity];
+  const T* __restrict__ fin = buf + I.off_f[parity];
+  T* __restrict__ fout = buf + I.off_f[parity ^ 1];
+  T* __restrict__ phi_out = buf + I.off_phi[parity ^ 1];
+  T* __restrict__ c_out = buf + I.off_c[parity ^ 1];
+  const int64_t nplane = (int64_t)nx * ny;
+
+  // --- droplet culling for the owned box [x0, xend) x [y0, yend); lane l examines droplets l + 64 w.
+  // The candidate masks are kept lane-distributed (lane w holds word w) to spare scalar registers.
+  unsigned long long near_v = 0ull, src_v = 0ull, seg_v = 0ull;
+  bool any_src = false;
+  if (nd > 0) {
+    const double Lx = nx, Ly = ny;
+    const double xm = 0.5 * (x0 + xend - 1), ym = 0.5 * (y0 + yend - 1);
+    const double hx = 0.5 * (xend - 1 - x0), hy = 0.5 * (yend - 1 - y0);
+    double mind2[MASK_WORDS];
+    bool srcf[MASK_WORDS];
+    double thr = 1e300;
+    for (int w = 0; w < MASK_WORDS; ++w) {
+      const int k = w * 64 + lane;
+      mind2[w] = 1e300;
+      srcf[w] = false;
+      if (k < nd) {
+        const DropDev d = drops[I.drop_base + k];
+        const double ddx = fabs(minimg(xm - d.x, Lx)), ddy = fabs(minimg(ym - d.y, Ly));
+        const double ux = ddx + hx, uy = ddy + hy;
+        thr = fmin(thr, ux * ux + uy * uy);
+        const double lx = fmax(0.0, ddx - hx), ly = fmax(0.0, ddy - hy);
+        mind2[w] = lx * lx + ly * ly;
+        if (d.active) {
+          const double px = d.x + (d.R - d.Rs) * d.ex, py = d.y + (d.R - d.Rs) * d.ey;
+          const double sdx = fmax(0.0, fabs(minimg(xm - px, Lx)) - hx);
+          const double sdy = fmax(0.0, fabs(minimg(ym - py, Ly)) - hy);
+          const double rr = d.Rs + 1e-6;
+          srcf[w] = sdx * sdx + sdy * sdy <= rr * rr;
+        }
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) thr = fmin(thr, __shfl_xor(thr, o, 64));
+    const double lim = thr * (1.0 + 1e-12) + 1e-6;
+    for (int w = 0; w < MASK_WORDS; ++w) {
+      const unsigned long long nb = __ballot(w * 64 + lane < nd && mind2[w] <= lim);
+      const unsigned long long sb = __ballot(srcf[w]);
+      if (lane == w) {
+        near_v = nb;
+        src_v = sb;
+      }
+      any_src = any_src || sb != 0ull;
+    }
+  }
+  const double tn = (double)(*step);
+  const double A = I.A0 * (tn < I.t_star ? tn : I.t_star);
+
+  const T a = T(I.a), b = T(I.b), B0 = T(I.B0), B1 = T(I.B1), halfB1 = T(I.halfB1);
+  const T omega = T(I.omega), coef = T(I.coef);
+  const T w0 = cst<T>(4.0 / 9.0), w1 = cst<T>(1.0 / 9.0), w5 = cst<T>(1.0 / 36.0);
+  const T cw0 = coef * w0, cw1 = coef * w1, cw5 = coef * w5;
+  const T Gamma = T(I.Gamma), D = T(I.D), gam = T(I.gamma), c0 = T(I.c0);
+  const int adv = I.advection;
+
+  // Register windows.  In the iteration whose stage-0 row is q, stage s works on row q - s; the
+  // digit in a window name is the row offset below q (P2 = phi^n of row q - 2, ...).
+  T P0 = T(0), P1 = T(0), P2 = T(0), P3 = T(0), P4 = T(0);     // phi^n
+  T C0 = T(0), C1 = T(0), C2 = T(0), C3 = T(0), C4 = T(0);     // c^n
+  T MU1 = T(0), MU2 = T(0), MU3 = T(0), X1 = T(0), X2 = T(0), X3 = T(0);  // mu_phi, X
+  T GCX1 = T(0), GCX2 = T(0), GCY1 = T(0), GCY2 = T(0);  // grad c^n (9-point), from stage 1 for stage 2
+  T UX2 = T(0), UX3 = T(0), UX4 = T(0), UY2 = T(0), UY3 = T(0), UY4 = T(0);  // u^n
+  T PH3 = T(0), PH4 = T(0), PH5 = T(0), CH3 = T(0), CH4 = T(0), CH5 = T(0), CH6 = T(0);  // phi, c at n+1/2
+  T M4 = T(0), M5 = T(0), M6 = T(0), XH4 = T(0), XH5 = T(0), XH6 = T(0);  // M, X^{n+1/2}
+
+  // Prefetch sets: phi, c of a coming stage-0 row and the pulled populations of a coming stage-2 row,
+  // PFD rows ahead.  With PFD = 2 the sweep is unrolled by two and the sets alternate, so that no
+  // register holding an outstanding load is ever copied.
+  constexpr int PFD = sizeof(T) == 8 ? 2 : 1;
+  struct Pref {
+    T phi, c, f[9];
+  };
+  Pref pfs[PFD];
+  // Addresses: a wave-uniform row pointer (scalar registers) plus a per-lane 32-bit column byte offset.
+  const unsigned bx = (unsigned)gx * sizeof(T), bxm = (unsigned)gxm * sizeof(T), bxp = (unsigned)gxp * sizeof(T);
+  auto load_s0 = [&](Pref& p, int r) {
+    const int64_t ro = (int64_t)wrap_near(r, ny) * pitch;
+    p.phi = ld_col(phi_in + ro, bx);
+    p.c = ld_col(c_in + ro, bx);
+  };
+  auto load_s2 = [&](Pref& p, int r) {
+    const int gy = wrap_near(r, ny);
+    const int gym = gy == 0 ? ny - 1 : gy - 1, gyp = gy == ny - 1 ? 0 : gy + 1;
+    const int64_t r0 = (int64_t)gy * pitch, rm = (int64_t)gym * pitch, rp = (int64_t)gyp * pitch;
+    p.f[0] = ld_col(fin + r0, bx);
+    p.f[1] = ld_col(fin + plane + r0, bxm);
+    p.f[2] = ld_col(fin + 2 * plane + rm, bx);
+    p.f[3] = ld_col(fin + 3 * plane + r0, bxp);
+    p.f[4] = ld_col(fin + 4 * plane + rp, bx);
+    p.f[5] = ld_col(fin + 5 * plane + rm, bxm);
+    p.f[6] = ld_col(fin + 6 * plane + rm, bxp);
+    p.f[7] = ld_col(fin + 7 * plane + rp, bxp);
+    p.f[8] = ld_col(fin + 8 * plane + rp, bxm);
+  };
+  for (int j = 0; j < PFD; ++j) {
+    load_s0(pfs[j], y0 - 5 + j);
+    load_s2(pfs[j], y0 - 3 + j);
+  }
+
+  const int nit = (yend - y0) + 10;
+  // one sweep iteration; `pf` holds the stage-0 row q and the stage-2 row q - 2, and is refilled for
+  // the rows PFD further on
+  auto sweep = [&](int it, Pref& pf) {
+    const int q = y0 - 5 + it;
+    // ---- s0: phi^n, c^n of row q; prefetch row q + PFD
+    P0 = pf.phi;
+    C0 = pf.c;
+    if (q + PFD < yend + 5) load_s0(pf, q + PFD);
+    // ---- s1: mu_phi and X (Eqs. 3, 5) at row q - 1
+    if (q - 1 >= y0 - 4 && q - 1 < yend + 4) {
+      const Nbr<T> gp = nbr(P0, P1, P2), gc = nbr(C0, C1, C2);
+      T gpx, gpy, gcx, gcy;
+      grad9n(gp, gpx, gpy);
+      grad9n(gc, gcx, gcy);
+      GCX1 = gcx;
+      GCY1 = gcy;
+      const T lp = lap9n(gp);
+      const T ph = P1;
+      const T B = B0 + B1 * C1;
+      MU1 = ((a * ph + b * (ph * ph * ph)) - B * lp) - B1 * (gpx * gcx + gpy * gcy);
+      X1 = halfB1 * (gpx * gpx + gpy * gpy);
+      if (DBG && own_col && q - 1 >= y0 && q - 1 < yend) {
+        const int64_t qq = (int64_t)(q - 1) * nx + (x0 + col);
+        dbg[0 * nplane + qq] = (double)MU1;
+        dbg[1 * nplane + qq] = (double)X1;
+      }
+    }
+    // ---- s2: force, moments, collision at row q - 2
+    if (q - 2 >= y0 - 3 && q - 2 < yend + 3) {
+      const int r = q - 2;
+      const Nbr<T> gm = nbr(MU1, MU2, MU3), gX = nbr(X1, X2, X3);
+      T gmx, gmy, gXx, gXy;
+      grad9n(gm, gmx, gmy);
+      grad9n(gX, gXx, gXy);
+      const T gcx = GCX2, gcy = GCY2;
+      const T ph = P2, cv = C2;
+      const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
+      const T Fy = (-(ph * gmy) - gcy) - cv * gXy;
+      const T f0 = pf.f[0], f1 = pf.f[1], f2 = pf.f[2], f3 = pf.f[3], f4 = pf.f[4], f5 = pf.f[5], f6 = pf.f[6],
+              f7 = pf.f[7], f8 = pf.f[8];
+      const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
+      const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
+      const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
+      const T ux = (mx + T(0.5) * Fx) / nn;
+      const T uy = (my + T(0.5) * Fy) / nn;
+      UX2 = ux;
+      UY2 = uy;
+      if (own_col && r >= y0 && r < yend) {
+        const T usq = ux * ux + uy * uy;
+        const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
+        const T wn0 = w0 * nn, wn1 = w1 * nn, wn5 = w5 * nn;
+        const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
+        const T s0 = collide1(f0, wn0, cw0, T(0), T(0), nux, nuy, Fx, Fy, usq, omega);
+        const T s1 = collide1(f1, wn1, cw1, ux, Fx, xp1, nuy, Fx, Fy, usq, omega);
+        const T s2 = collide1(f2, wn1, cw1, uy, Fy, nux, yp1, Fx, Fy, usq, omega);
+        const T s3 = collide1(f3, wn1, cw1, nux, nFx, xm1, nuy, Fx, Fy, usq, omega);
+        const T s4 = collide1(f4, wn1, cw1, nuy, nFy, nux, ym1, Fx, Fy, usq, omega);
+        const T s5 = collide1(f5, wn5, cw5, ux + uy, Fx + Fy, xp1, yp1, Fx, Fy, usq, omega);
+        const T s6 = collide1(f6, wn5, cw5, nux + uy, nFx + Fy, xm1, yp1, Fx, Fy, usq, omega);
+        const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
+        const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
+        T* const o = fout + (int64_t)r * pitch;
+        st_col(o, bx, s0);
+        st_col(o + plane, bx, s1);
+        st_col(o + 2 * plane, bx, s2);
+        st_col(o + 3 * plane, bx, s3);
+        st_col(o + 4 * plane, bx, s4);
+        st_col(o + 5 * plane, bx, s5);
+        st_col(o + 6 * plane, bx, s6);
+        st_col(o + 7 * plane, bx, s7);
+        st_col(o + 8 * plane, bx, s8);
+        if (DBG) {
+          const int64_t qq = (int64_t)r * nx + (x0 + col);
+          dbg[2 * nplane + qq] = (double)Fx;
+          dbg[3 * nplane + qq] = (double)Fy;
+          dbg[4 * nplane + qq] = (double)nn;
+          dbg[5 * nplane + qq] = (double)ux;
+          dbg[6 * nplane + qq] = (double)uy;
+          const T sv[9] = {s0, s1, s2, s3, s4, s5, s6, s7, s8};
+          for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + qq] = (double)sv[i];
+        }
+      }
+      if (r + PFD < yend + 3) load_s2(pf, r + PFD);
+    }
+    // ---- s3: advection half-step (Eqs. 16-17) at row q - 3
+    if (q - 3 >= y0 - 2 && q - 3 < yend + 2) {
+      T ue, uw, pe, pw, ce, cw;
+      shift_ew(UX3, ue, uw);
+      shift_ew(P3, pe, pw);
+      shift_ew(C3, ce, cw);
+      PH3 = advect_n(P3, pe, pw, P2, P4, UX3, ue, uw, UY3, UY2, UY4, adv);
+      CH3 = advect_n(C3, ce, cw, C2, C4, UX3, ue, uw, UY3, UY2, UY4, adv);
+      if (DBG && own_col && q - 3 >= y0 && q - 3 < yend) {
+        const int64_t qq = (int64_t)(q - 3) * nx + (x0 + col);
+        dbg[7 * nplane + qq] = (double)PH3;
+        dbg[8 * nplane + qq] = (double)CH3;
+      }
+    }
+    // ---- s4: bracket M of Eq. (18) and X^{n+1/2} at row q - 4
+    if (q - 4 >= y0 - 1 && q - 4 < yend + 1) {
+      const Nbr<T> gph = nbr(PH3, PH4, PH5), gch = nbr(CH3, CH4, CH5);
+      T gphx, gphy, gchx, gchy;
+      grad9n(gph, gphx, gphy);
+      grad9n(gch, gchx, gchy);
+      const T lph = lap9n(gph);
+      const T pn = P4;
+      const T Bh = B0 + B1 * CH4;
+      M4 = ((a * PH4 + b * (pn * pn * pn)) - Bh * lph) - B1 * (gchx * gphx + gchy * gphy);
+      XH4 = halfB1 * (gphx * gphx + gphy * gphy);
+      if (DBG && own_col && q - 4 >= y0 && q - 4 < yend) {
+        const int64_t qq = (int64_t)(q - 4) * nx + (x0 + col);
+        dbg[9 * nplane + qq] = (double)M4;
+        dbg[10 * nplane + qq] = (double)XH4;
+      }
+    }
+    // ---- s5: phi^{n+1}, c^{n+1} (Eqs. 18, 19) at row q - 5 and centre-of-mass contributions
+    if (q - 5 >= y0) {
+      const int r = q - 5;
+      const Nbr<T> gM = nbr(M4, M5, M6), gch = nbr(CH4, CH5, CH6), gXh = nbr(XH4, XH5, XH6);
+      const T phn = PH5 + Gamma * lap9n(gM);
+      const T ch = CH5;
+      const T lch = lap9n(gch);
+      const T dv = div9n(gch, gXh, D);
+      const double xd = (double)(x0 + col), yd = (double)r;
+      int cnt = 0;
+      for (int w = 0; any_src && w < MASK_WORDS; ++w) {
+        unsigned long long m = read_lane64(src_v, w);
+        while (m) {
+          const int k = w * 64 + __ffsll(m) - 1;
+          m &= m - 1;
+          const DropDev d = drops[I.drop_base + k];
+          const double px = d.x + (d.R - d.Rs) * d.ex, py = d.y + (d.R - d.Rs) * d.ey;
+          const double dx = minimg(xd - px, (double)nx), dy = minimg(yd - py, (double)ny);
+          if (dx * dx + dy * dy <= d.Rs * d.Rs) ++cnt;
+        }
+      }
+      const double src = A * (double)cnt;
+      const T cn = (((ch + D * lch) + dv) - gam * (ch - c0)) + T(src);
+      int kd = -1;
+      double cv0 = 0.0, cv1 = 0.0, cv2 = 0.0;
+      if (own_col) {
+        if (!DBG) {
+          st_col(phi_out + (int64_t)r * pitch, bx, phn);
+          st_col(c_out + (int64_t)r * pitch, bx, cn);
+        } else {
+          const int64_t qq = (int64_t)r * nx + (x0 + col);
+          dbg[11 * nplane + qq] = (double)phn;
+          dbg[12 * nplane + qq] = (double)cn;
+        }
+        const double v = (double)phn;
+        if (!DBG && nd > 0 && v >= 0.0) {
+          int best = -1;
+          double bd = 0.0;
+          for (int w = 0; w < MASK_WORDS; ++w) {
+            unsigned long long m = read_lane64(near_v, w);
+            while (m) {
+              const int k = w * 64 + __ffsll(m) - 1;
+              m &= m - 1;
+              const DropDev d = drops[I.drop_base + k];
+              const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, (double)ny);
+              const double d2 = dx * dx + dy * dy;
+              if (best < 0 || d2 < bd) {
+                best = k;
+                bd = d2;
+              }
+            }
+          }
+          const DropDev d = drops[I.drop_base + best];
+          kd = best;
+          cv0 = v;
+          cv1 = v * minimg(xd - d.x, (double)nx);
+          cv2 = v * minimg(yd - d.y, (double)ny);
+        }
+      }
+      // per-row wave sums of the centre-of-mass contributions, one droplet at a time (fixed butterfly order)
+      if (!DBG && nd > 0) {
+        unsigned long long pend = __ballot(kd >= 0);
+        while (pend) {
+          const int k = __builtin_amdgcn_readlane(kd, __ffsll(pend) - 1);
+          const bool sel = kd == k;
+          double s0 = sel ? cv0 : 0.0, s1 = sel ? cv1 : 0.0, s2 = sel ? cv2 : 0.0;
+          for (int o = 32; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o, 64);
+            s1 += __shfl_xor(s1, o, 64);
+            s2 += __shfl_xor(s2, o, 64);
+          }
+          const unsigned long long bit = 1ull << (k & 63);
+          const bool seen = (read_lane64(seg_v, k >> 6) & bit) != 0ull;
+          if (lane == (k >> 6)) seg_v |= bit;
+          if (lane == 0) {
+            if (seen) {
+              acc[k][0] += s0;
+              acc[k][1] += s1;
+              acc[k][2] += s2;
+            } else {
+              acc[k][0] = s0;
+              acc[k][1] = s1;
+              acc[k][2] = s2;
+            }
+          }
+          pend &= ~__ballot(sel);
+        }
+      }
+    }
+    // ---- rotate the windows by one row
+    P4 = P3; P3 = P2; P2 = P1; P1 = P0;
+    C4 = C3; C3 = C2; C2 = C1; C1 = C0;
+    MU3 = MU2; MU2 = MU1; X3 = X2; X2 = X1; GCX2 = GCX1; GCY2 = GCY1;
+    UX4 = UX3; UX3 = UX2; UY4 = UY3; UY3 = UY2;
+    PH5 = PH4; PH4 = PH3; CH6 = CH5; CH5 = CH4; CH4 = CH3;
+    M6 = M5; M5 = M4; XH6 = XH5; XH5 = XH4;
+  };
+  for (int it = 0; it < nit; it += PFD) {
+    sweep(it, pfs[0]);
+    if (PFD > 1 && it + 1 < nit) sweep(it + 1, pfs[PFD - 1]);
+  }
+  if (DBG || nd == 0) return;
+  __syncthreads();  // acc was written by lane 0
+  const int t_local = sd.t - I.tile_base[TILING_FUSED];
+  for (int w = 0; w < MASK_WORDS; ++w) {
+    const int k = w * 64 + lane;
+    if (k < nd && ((read_lane64(seg_v, w) >> lane) & 1ull)) {
+      double* p = part + I.part_base[TILING_FUSED] + ((int64_t)t_local * nd + k) * 3;
+      p[0] = acc[k][0];
+      p[1] = acc[k][1];
+      p[2] = acc[k][2];
+    }
+  }
+  if (lane < MASK_WORDS) mask[(int64_t)sd.t * MASK_WORDS + lane] = seg_v;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------------
@@ -1225,6 +1746,20 @@ hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_wave(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst, T* buf,
+                       const DropDev* drops, double* part, uint64_t* mask, const int64_t* step, double* dbg,
+                       int dbg_inst) {
+  if (nseg_launch <= 0) return hipSuccess;
+  if (dbg)
+    hipLaunchKernelGGL((k_wave<T, true>), dim3(nseg_launch), dim3(64), 0, s, parity, segs, inst, buf, drops, part,
+                       mask, step, dbg, dbg_inst);
+  else
+    hipLaunchKernelGGL((k_wave<T, false>), dim3(nseg_launch), dim3(64), 0, s, parity, segs, inst, buf, drops, part,
+                       mask, step, dbg, dbg_inst);
+  return hipGetLastError();
+}
+
 #define LBM_INSTANTIATE(T)                                                                                \
   template hipError_t launch_lb<T>(hipStream_t, int, int, int, const TileDev*, const InstDev*, T*,        \
                                    double*, int);                                                         \
@@ -1235,6 +1770,8 @@ hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev
   template hipError_t launch_obs<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,            \
                                     const DropDev*, double*, int);                                        \
   template hipError_t launch_step<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*, const DropDev*,  \
+                                     double*, uint64_t*, const int64_t*, double*, int); \
+  template hipError_t launch_wave<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*, const DropDev*,  \
                                      double*, uint64_t*, const int64_t*, double*, int);
 
 

@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("LBM_LIBRARY", os.path.join(_HERE, "liblbm.so"))
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32 = 0, 1
 LBM_ADV_PAPER, LBM_ADV_FLUX = 0, 1
-LBM_PATH_FUSED, LBM_PATH_SPLIT = 0, 1
+LBM_PATH_FUSED, LBM_PATH_SPLIT, LBM_PATH_WAVE = 0, 1, 2
 LBM_MAXDROP = 256
 LBM_NSTAGE = 22
 STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "phi_new", "c_new"] + [
@@ -29,8 +29,9 @@ STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "p
 EXPORTED = ["lbm_workspace_bytes", "lbm_init_batch", "lbm_init", "lbm_step", "lbm_set_graph", "lbm_sync",
             "lbm_get_step", "lbm_fields", "lbm_observables", "lbm_droplets", "lbm_debug_stage",
             "lbm_time_kernels", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_set_seg_rows",
-            "lbm_get_seg_rows", "lbm_autotune", "lbm_destroy", "lbm_last_error"]
-SEG_ROWS_CANDIDATES = (16, 32, 64, 128, 256)
+            "lbm_get_seg_rows", "lbm_tune_rows", "lbm_autotune", "lbm_destroy", "lbm_last_error"]
+LBM_SEG_ROWS_MIN, LBM_SEG_ROWS_MAX, LBM_TUNE_NROWS = 16, 4096, 16
+PATH_NAMES = {LBM_PATH_FUSED: "fused", LBM_PATH_SPLIT: "split", LBM_PATH_WAVE: "wave"}
 
 
 class LBMError(RuntimeError):
@@ -93,7 +94,9 @@ def load_library(path: Optional[str] = None):
     lib.lbm_set_seg_rows.argtypes = [vp, C.c_int32]
     lib.lbm_get_seg_rows.argtypes = [vp]
     lib.lbm_get_seg_rows.restype = C.c_int32
-    lib.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), dp]
+    lib.lbm_tune_rows.argtypes = []
+    lib.lbm_tune_rows.restype = C.POINTER(C.c_int32)
+    lib.lbm_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.restype = C.c_char_p
@@ -219,11 +222,24 @@ def lbm_get_seg_rows(ctx: int) -> int:
     return int(load_library().lbm_get_seg_rows(C.c_void_p(ctx)))
 
 
-def lbm_autotune(ctx: int, launches: int):
-    chosen = C.c_int32(0)
-    ms = np.zeros(len(SEG_ROWS_CANDIDATES))
-    _check(load_library().lbm_autotune(C.c_void_p(ctx), int(launches), C.byref(chosen), _dptr(ms)))
-    return int(chosen.value), {r: float(m) for r, m in zip(SEG_ROWS_CANDIDATES, ms) if m >= 0}
+def lbm_tune_rows():
+    p = load_library().lbm_tune_rows()
+    return [int(p[i]) for i in range(LBM_TUNE_NROWS)]
+
+
+def lbm_autotune(ctx: int, launches: int, both_paths: bool = True):
+    """Returns (rows, path, {"fused:rows" / "wave:rows": ms per launch}) for the candidates tried."""
+    rows, path = C.c_int32(0), C.c_int32(0)
+    ms = np.zeros(2 * LBM_TUNE_NROWS)
+    _check(load_library().lbm_autotune(C.c_void_p(ctx), int(launches), int(bool(both_paths)), C.byref(rows),
+                                       C.byref(path), _dptr(ms)))
+    cand = lbm_tune_rows()
+    times = {}
+    for pi, name in enumerate(("fused", "wave")):
+        for k, r in enumerate(cand):
+            if ms[pi * LBM_TUNE_NROWS + k] >= 0:
+                times[f"{name}:{r}"] = float(ms[pi * LBM_TUNE_NROWS + k])
+    return int(rows.value), int(path.value), times
 
 
 def lbm_destroy(ctx: int) -> None:
@@ -323,12 +339,20 @@ class Sim:
     def set_path(self, path: int) -> None:
         lbm_set_path(self.ctx, path)
 
+    def tune_rows(self):
+        return lbm_tune_rows()
+
+    @property
+    def path(self) -> int:
+        return lbm_get_path(self.ctx)
+
     def set_seg_rows(self, rows: int) -> None:
         lbm_set_seg_rows(self.ctx, rows)
 
-    def autotune(self, launches: int = 5):
-        """Pick the fused kernel's segment height by timing each candidate (the state is unchanged)."""
-        return lbm_autotune(self.ctx, launches)
+    def autotune(self, launches: int = 5, both_paths: bool = True):
+        """Pick the sweeping kernel (fused or wave) and its segment height by timing each candidate (the
+        state is unchanged).  Returns (rows, path, times)."""
+        return lbm_autotune(self.ctx, launches, both_paths)
 
     def time_kernels(self, n: int) -> Dict[str, float]:
         """Average ms per launch of each kernel of the current path (hipEvents on the library's stream)."""

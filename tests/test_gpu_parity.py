@@ -34,7 +34,7 @@ def gpu_sim(w, precision=0, graph_steps=None, step=0, f_pre=None, phi=None, c=No
                    step=step, f_pre=None if f_pre is None else [f_pre], path=path)
 
 
-PATHS = [0, 1]  # fused sweep kernel, split LB + FD kernels
+PATHS = [0, 1, 2]  # fused sweep kernel, split LB + FD kernels, wavefront-per-strip sweep kernel
 
 
 def oracle_sim(w, step=0, f_pre=None):
@@ -72,7 +72,7 @@ def test_stages_match_oracle_bitwise(shape, path):
     sim.close()
 
 
-@pytest.mark.parametrize("advection,path", [(0, 0), (1, 0), (0, 1)])
+@pytest.mark.parametrize("advection,path", [(0, 0), (1, 0), (0, 1), (0, 2), (1, 2)])
 def test_c1_equilibrium_droplet_1000_2000_steps(advection, path):
     w = W.c1_equilibrium()
     w.params["advection"] = advection
@@ -87,9 +87,10 @@ def test_c1_equilibrium_droplet_1000_2000_steps(advection, path):
     sim.close()
 
 
-def test_c2_active_droplet_256_first_1000_steps():
+@pytest.mark.parametrize("path", [0, 2])
+def test_c2_active_droplet_256_first_1000_steps(path):
     w = W.c2_single_active()
-    sim = gpu_sim(w, graph_steps=20)
+    sim = gpu_sim(w, graph_steps=20, path=path)
     ref = oracle_sim(w)
     sim.step(1000)
     ref.run(1000)
@@ -103,11 +104,12 @@ def test_c2_active_droplet_256_first_1000_steps():
     sim.close()
 
 
-def test_c5_emulsion_2048_bench_configuration():
+@pytest.mark.parametrize("path", [0, 2])
+def test_c5_emulsion_2048_bench_configuration(path):
     """Full-size 2048^2 emulsion with 64 droplets, graph replay as the benchmark runs it: every field
     after a few steps against the oracle on the whole lattice."""
     w = W.c5_emulsion()
-    sim = gpu_sim(w, graph_steps=2)
+    sim = gpu_sim(w, graph_steps=2, path=path)
     ref = oracle_sim(w)
     sim.step(4)
     ref.run(4)
@@ -136,10 +138,11 @@ def test_batched_uneven_instances_match_oracle():
     sim.close()
 
 
-def test_fused_and_split_paths_agree_bitwise():
+@pytest.mark.parametrize("other", [1, 2])
+def test_fused_and_other_paths_agree_bitwise(other):
     w = W.c5_emulsion(n=384, ndrop=6, R=16.0, seed=21)
     s1 = gpu_sim(w, path=0, graph_steps=10)
-    s2 = gpu_sim(w, path=1, graph_steps=10)
+    s2 = gpu_sim(w, path=other, graph_steps=10)
     s1.step(120)
     s2.step(120)
     f1, f2 = s1.fields(), s2.fields()
@@ -217,11 +220,12 @@ def test_determinism_bitwise():
     assert runs[0][1] == runs[1][1]
 
 
-def test_fp32_against_fp64_oracle():
+@pytest.mark.parametrize("path", [0, 2])
+def test_fp32_against_fp64_oracle(path):
     """FP32 storage and arithmetic: relative deviation of a few 1e-6 per field after 200 steps (unit
     roundoff 6e-8 amplified by the ~100 operations per node and step and by the dynamics)."""
     w = W.c1_equilibrium()
-    sim = gpu_sim(w, precision=1)
+    sim = gpu_sim(w, precision=1, path=path)
     ref = oracle_sim(w)
     sim.step(200)
     ref.run(200)
@@ -246,11 +250,12 @@ def test_instability_is_reported():
     sim.close()
 
 
-def test_no_droplets_and_tiny_lattice():
+@pytest.mark.parametrize("path", PATHS)
+def test_no_droplets_and_tiny_lattice(path):
     w = W.c1_equilibrium()
     f, phi, c = W.random_state(3, 4, 3)
     tiny = W.Workload("tiny", 3, 4, dict(w.params), phi, c, [])
-    sim = gpu_sim(tiny, f_pre=f)
+    sim = gpu_sim(tiny, f_pre=f, path=path)
     ref = oracle_sim(tiny, f_pre=f)
     sim.step(25)
     ref.run(25)
@@ -258,13 +263,14 @@ def test_no_droplets_and_tiny_lattice():
     sim.close()
 
 
-def test_segment_heights_agree_bitwise_and_autotune_keeps_state():
-    """The fused kernel's strip height changes only the work decomposition: every height gives the same
-    bits; the autotuner's trial launches leave the state, droplets and step counter untouched."""
+@pytest.mark.parametrize("path", [0, 2])
+def test_segment_heights_agree_bitwise_and_autotune_keeps_state(path):
+    """The sweeping kernels' strip height changes only the work decomposition: every height gives the
+    same bits; the autotuner's trial launches leave the state, droplets and step counter untouched."""
     w = W.c5_emulsion(n=300, ndrop=4, R=14.0, seed=31)
     ref = None
     for rows in (16, 32, 64, 128, 256):
-        s = gpu_sim(w, graph_steps=0)
+        s = gpu_sim(w, graph_steps=0, path=path)
         s.set_seg_rows(rows)
         s.step(37)
         f = s.fields()
@@ -274,11 +280,11 @@ def test_segment_heights_agree_bitwise_and_autotune_keeps_state():
             for k in FIELDS:
                 assert np.array_equal(f[k], ref[k]), (rows, k)
         s.close()
-    s = gpu_sim(w, graph_steps=10)
+    s = gpu_sim(w, graph_steps=10, path=path)
     s.step(5)
     before, drops_before, step_before = s.fields(), s.droplets(), s.step_count
-    chosen, times = s.autotune(3)
-    assert chosen in (16, 32, 64, 128, 256) and len(times) >= 3
+    chosen, chosen_path, times = s.autotune(3, both_paths=False)
+    assert chosen_path == path and chosen in s.tune_rows() and len(times) >= 3
     after = s.fields()
     for k in FIELDS:
         assert np.array_equal(before[k], after[k]), k
