@@ -103,6 +103,7 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.tile_base[TILING_FUSED] = seg_base;
     d.drop_base = drop_base;
     const int64_t plane = (int64_t)c.ny * d.pitch;
+    d.pstride = plane;
     int64_t o = pool_elems;
     d.off_f[0] = o;  o += 9 * plane;
     d.off_f[1] = o;  o += 9 * plane;
@@ -309,7 +310,7 @@ template <typename T>
 int upload_instance(lbm_ctx* c, int i, const double* phi0, const double* c0, const double* f_pre) {
   const InstDev& d = c->L.inst[i];
   const int nx = d.nx, ny = d.ny, pitch = d.pitch;
-  const size_t plane = (size_t)ny * pitch;
+  const size_t plane = (size_t)d.pstride;
   std::vector<T> h(plane * 9);
   T* base = reinterpret_cast<T*>(c->pool());
   to_device_layout(phi0, h.data(), nx, ny, pitch);
@@ -363,7 +364,7 @@ int run_diag(lbm_ctx* c) {
 
 template <typename T>
 int download_plane(lbm_ctx* c, int64_t off, const InstDev& d, double* out) {
-  const size_t plane = (size_t)d.ny * d.pitch;
+  const size_t plane = (size_t)d.pstride;
   std::vector<T> h(plane);
   HIPCHK(hipMemcpyAsync(h.data(), reinterpret_cast<T*>(c->pool()) + off, plane * sizeof(T), hipMemcpyDeviceToHost,
                         c->stream));
@@ -387,7 +388,7 @@ int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, do
   if (ux && (rc = download_plane<T>(c, d.off_ux, d, ux)) != LBM_OK) return rc;
   if (uy && (rc = download_plane<T>(c, d.off_uy, d, uy)) != LBM_OK) return rc;
   if (f_pre) {
-    const size_t plane = (size_t)d.ny * d.pitch;
+    const size_t plane = (size_t)d.pstride;
     std::vector<T> h(9 * plane);
     HIPCHK(hipMemcpyAsync(h.data(), reinterpret_cast<T*>(c->pool()) + d.off_f[c->parity], 9 * plane * sizeof(T),
                           hipMemcpyDeviceToHost, c->stream));

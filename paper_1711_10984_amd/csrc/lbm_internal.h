@@ -36,7 +36,8 @@ struct InstDev {
   int32_t nx, ny, pitch, ndrop;
   int32_t tiles_x[2], tiles_y[2], tile_base[2];  // per tiling: counts and first natural index
   int32_t drop_base, seg_rows;  // seg_rows: rows per fused-kernel strip segment
-  int64_t off_f[2];    // element offsets of the two population buffers [9][ny][pitch]
+  int64_t pstride;     // elements between consecutive planes of the pool (ny * pitch)
+  int64_t off_f[2];    // element offsets of the two population buffers [9][ny][pitch], planes pstride apart
   int64_t off_phi[2];  // the two phi buffers [ny][pitch]
   int64_t off_c[2];    // the two c buffers
   int64_t off_ux, off_uy, off_n;  // velocity planes written by the LB kernel; density (diagnostics)

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
   const InstDev& I = insts[td.inst];
   const int nx = I.nx, ny = I.ny, pitch = I.pitch;
   const int tid = threadIdx.x;
-  const int64_t plane = (int64_t)ny * pitch;
+  const int64_t plane = I.pstride;
   const T* __restrict__ phi = buf + I.off_phi[parity];
   const T* __restrict__ cc = buf + I.off_c[parity];
   const T* __restrict__ fin = buf + I.off_f[parity];
@@ -622,7 +622,7 @@ __global__ __launch_bounds__(NTHREADS) void k_obs(int parity, const TileDev* __r
   if (td.inst < 0) return;
   const InstDev& I = insts[td.inst];
   const int nx = I.nx, ny = I.ny, pitch = I.pitch;
-  const int64_t plane = (int64_t)ny * pitch;
+  const int64_t plane = I.pstride;
   const int bx1 = min(td.x0 + TILE_X, nx) - 1, by1 = min(td.y0 + TILE_Y, ny) - 1;
   if (I.ndrop > 0) {
     cull_droplets(I, drops, td.x0, bx1, td.y0, by1, sh);
@@ -821,7 +821,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   const int gx = wrap_idx(x0 + col, nx);      // periodic global column
   const int gxm = gx == 0 ? nx - 1 : gx - 1, gxp = gx == nx - 1 ? 0 : gx + 1;
   const bool own_col = col >= 0 && col < FUSED_TX && x0 + col < nx;
-  const int64_t plane = (int64_t)ny * pitch;
+  const int64_t plane = I.pstride;
   const T* __restrict__ phi_in = buf + I.off_phi[parity];
   const T* __restrict__ c_in = buf + I.off_c[parity];
   const T* __restrict__ fin = buf + I.off_f[parity];
@@ -1343,7 +1343,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int gx = wrap_idx(x0 + col, nx);
   const int gxm = gx == 0 ? nx - 1 : gx - 1, gxp = gx == nx - 1 ? 0 : gx + 1;
   const bool own_col = col >= 0 && col < FUSED_TX && x0 + col < nx;
-  const int64_t plane = (int64_t)ny * pitch;
+  const int64_t plane = I.pstride;
   const T* __restrict__ phi_in = buf + I.off_phi[parity];
   const T* __restrict__ c_in = buf + I.off_c[parity];
   const T* __restrict__ fin = buf + I.off_f[parity];
@@ -1444,9 +1444,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     p.f[7] = ld_col(fin + 7 * plane + rp, bxp);
     p.f[8] = ld_col(fin + 8 * plane + rp, bxm);
   };
+  // Set j serves the iterations it = j (mod PFD): stage-0 row y0 - 5 + it, stage-2 row y0 - 7 + it, whose
+  // first valid row y0 - 3 comes at it = 4.
   for (int j = 0; j < PFD; ++j) {
     load_s0(pfs[j], y0 - 5 + j);
-    load_s2(pfs[j], y0 - 3 + j);
+    load_s2(pfs[j], y0 - 3 + ((j - 4) % PFD + PFD) % PFD);
   }
 
   const int nit = (yend - y0) + 10;
@@ -1663,8 +1665,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     M6 = M5; M5 = M4; XH6 = XH5; XH5 = XH4;
   };
   for (int it = 0; it < nit; it += PFD) {
-    sweep(it, pfs[0]);
-    if (PFD > 1 && it + 1 < nit) sweep(it + 1, pfs[PFD - 1]);
+#pragma unroll
+    for (int j = 0; j < PFD; ++j)
+      if (it + j < nit) sweep(it + j, pfs[j]);
   }
   if (DBG || nd == 0) return;
   __syncthreads();  // acc was written by lane 0
