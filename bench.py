@@ -24,19 +24,29 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "MLUPS of coupled LB+FD step and % HBM roofline, FP64 vs FP32 vs batched"
 
-# Algorithmic values moved per lattice node by each kernel of the timestep (element size x count).
-#   k_step (fused): reads 9 populations + phi + c, writes the same          -> 22 values
-#   k_wave (fused, one wavefront per strip): the same                      -> 22 values
-#   k_lb (split):   reads 9 populations + phi + c, writes 9 populations + ux + uy -> 22 values
-#   k_fd (split):   reads phi + c + ux + uy, writes phi + c                   ->  6 values
-#   whole step, state only (9 populations + phi + c read and written)        -> 22 values
-VALUES_PER_NODE = {"k_step": 22, "k_wave": 22, "k_lb": 22, "k_fd": 6, "step": 22}
+# Algorithmic values moved per lattice node by each kernel of the timestep: (populations, field values).
+#   k_step (fused): reads 9 populations + phi + c, writes the same          -> (18, 4)
+#   k_wave (fused, one wavefront per strip): the same                      -> (18, 4)
+#   k_lb (split):   reads 9 populations + phi + c, writes 9 populations + ux + uy -> (18, 4)
+#   k_fd (split):   reads phi + c + ux + uy, writes phi + c                   -> (0, 6)
+#   whole step, state only (9 populations + phi + c read and written)        -> (18, 4)
+VALUES_PER_NODE = {"k_step": (18, 4), "k_wave": (18, 4), "k_lb": (18, 4), "k_fd": (0, 6), "step": (18, 4)}
+# bytes of (a population, a field value) per precision code: FP64, FP32, FP16 population storage
+ELEM_BYTES = {0: (8, 8), 1: (4, 4), 2: (2, 4)}
+PREC_NAMES = {0: "fp64", 1: "fp32", 2: "fp16"}
+
+
+def alg_bytes_per_node(kernel, precision):
+    npop, nfield = VALUES_PER_NODE[kernel]
+    pb, fb = ELEM_BYTES[precision]
+    return npop * pb + nfield * fb
 PATH_NAMES = {0: "fused", 1: "split", 2: "wave"}
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("lbm_kernels_impl.h", "lbm_kernels_f64.hip", "lbm_kernels_f32.hip", "lbm_internal.h"):
+    for f in ("lbm_kernels_impl.h", "lbm_kernels_f64.hip", "lbm_kernels_f32.hip", "lbm_kernels_f16.hip",
+              "lbm_internal.h"):
         with open(os.path.join(ROOT, "paper_1711_10984_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -101,14 +111,13 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     obs = sim.observables(0)
     per_kernel = sim.time_kernels(prof_steps)  # hipEvents around each launch on the library's stream
     sim.close()
-    elem = 8 if precision == lbm.LBM_FP64 else 4
     mlups = nodes * steps / (ms * 1e-3) / 1e6
     dom = max((k for k in per_kernel if k in VALUES_PER_NODE), key=lambda k: per_kernel[k])
-    alg_bytes = VALUES_PER_NODE[dom] * elem * nodes
+    alg_bytes = alg_bytes_per_node(dom, precision) * nodes
     achieved = alg_bytes / (per_kernel[dom] * 1e-3) / 1e9
-    step_bytes = VALUES_PER_NODE["step"] * elem * nodes
+    step_bytes = alg_bytes_per_node("step", precision) * nodes
     step_gbs = step_bytes / (ms * 1e-3 / steps) / 1e9
-    prec = "fp64" if precision == lbm.LBM_FP64 else "fp32"
+    prec = PREC_NAMES[precision]
     traffic = measured_traffic(dom, label, prec, seg_rows)
     return {
         "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
@@ -127,16 +136,17 @@ def _minimg(d, L):
     return (d + 0.5 * L) % L - 0.5 * L
 
 
-def fp32_accuracy(workloads, steps, log_every, graph_steps, path):
-    """FP32 against FP64 on the GPU for the same inputs: largest centre-of-mass deviation over the run
-    (trajectories logged every `log_every` steps), drift of the phi integral in both precisions, and the
-    relative L2 difference of the velocity field at the end (first lattice)."""
+def lowp_accuracy(workloads, steps, log_every, graph_steps, path, low):
+    """A lower precision (`low`: LBM_FP32 or LBM_FP16) against FP64 on the GPU for the same inputs: largest
+    centre-of-mass deviation over the run (trajectories logged every `log_every` steps), drift of the phi
+    integral in both precisions, and the relative L2 difference of the velocity field at the end (first
+    lattice)."""
     import numpy as np
     from paper_1711_10984_amd import lbm
     traj = {}
     end = {}
     phi_sum = {}
-    for prec in (lbm.LBM_FP64, lbm.LBM_FP32):
+    for prec in (lbm.LBM_FP64, low):
         sim = build_sim(workloads, prec, graph_steps, max(path, 0))
         t = []
         s0 = [sim.observables(i)["sum_phi"] for i in range(len(workloads))]
@@ -148,17 +158,17 @@ def fp32_accuracy(workloads, steps, log_every, graph_steps, path):
         phi_sum[prec] = [sim.observables(i)["sum_phi"] - s0[i] for i in range(len(workloads))]
         sim.close()
     dev = 0.0
-    for a, b in zip(traj[lbm.LBM_FP64], traj[lbm.LBM_FP32]):
+    for a, b in zip(traj[lbm.LBM_FP64], traj[low]):
         for i, w in enumerate(workloads):
             for (xa, ya), (xb, yb) in zip(a[i], b[i]):
                 dev = max(dev, float(np.hypot(_minimg(xa - xb, w.nx), _minimg(ya - yb, w.ny))))
-    u64, u32 = end[lbm.LBM_FP64], end[lbm.LBM_FP32]
+    u64, u32 = end[lbm.LBM_FP64], end[low]
     num = np.sqrt(np.sum((u64["ux"] - u32["ux"]) ** 2 + (u64["uy"] - u32["uy"]) ** 2))
     den = np.sqrt(np.sum(u64["ux"] ** 2 + u64["uy"] ** 2))
     return {"steps": steps, "lattices": len(workloads), "log_every": log_every,
             "max_cm_deviation_lu": round(dev, 6),
             "phi_integral_drift_fp64": round(float(max(phi_sum[lbm.LBM_FP64], key=abs)), 6),
-            "phi_integral_drift_fp32": round(float(max(phi_sum[lbm.LBM_FP32], key=abs)), 6),
+            f"phi_integral_drift_{PREC_NAMES[low]}": round(float(max(phi_sum[low], key=abs)), 6),
             "velocity_l2_rel_diff": float(num / den) if den > 0 else None}
 
 
@@ -190,11 +200,11 @@ def main():
                     help="-1: autotuned choice of 0 or 2; 0: fused sweep kernel; 1: split LB + FD kernels; "
                          "2: wavefront-per-strip sweep kernel")
     ap.add_argument("--seg-rows", type=int, default=0, help="fused-kernel strip height (0: autotune)")
-    ap.add_argument("--only", choices=["fp64", "fp32", "c3"], default=None,
+    ap.add_argument("--only", choices=["fp64", "fp32", "fp16", "c3"], default=None,
                     help="run one configuration (for profiling); the JSON line then reports that one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
-    ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-vs-FP64 accuracy runs")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32/FP16-vs-FP64 accuracy runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (reference for rocprofv3 counters)")
     args = ap.parse_args()
@@ -217,8 +227,9 @@ def main():
         torch.cuda.synchronize()
 
     c5 = W.c5_emulsion()
-    if args.only in ("fp32", "c3"):
-        wl, prec, label = ([c5], lbm.LBM_FP32, "c5") if args.only == "fp32" else (W.c3_batch(), lbm.LBM_FP32, "c3")
+    if args.only in ("fp32", "fp16", "c3"):
+        wl, prec, label = {"fp32": ([c5], lbm.LBM_FP32, "c5"), "fp16": ([c5], lbm.LBM_FP16, "c5"),
+                           "c3": (W.c3_batch(), lbm.LBM_FP32, "c3")}[args.only]
         r = measure(wl, prec, args.steps, args.warmup, args.graph_steps, label, args.prof_steps, args.path,
                     args.seg_rows)
         print(json.dumps({"only": args.only, "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
@@ -234,6 +245,8 @@ def main():
                                         args.prof_steps, args.path, args.seg_rows)
         variants["batched_c3_fp32"] = measure(W.c3_batch(), lbm.LBM_FP32, args.steps, args.warmup,
                                               args.graph_steps, "c3", args.prof_steps, args.path, args.seg_rows)
+        variants["fp16_storage_2048"] = measure([c5], lbm.LBM_FP16, args.steps, args.warmup, args.graph_steps,
+                                                "c5", args.prof_steps, args.path, args.seg_rows)
     for v in variants.values():
         v["gain_over_fp64"] = round(v["mlups"] / main_res["mlups"], 3)
     out = {
@@ -266,9 +279,15 @@ def main():
     }
     if not args.no_accuracy and not args.no_variants:
         out["fp32_accuracy"] = {
-            "single_droplet_256": fp32_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
-                                                args.path),
-            "batched_c3": fp32_accuracy(W.c3_batch(), 20000, 100, args.graph_steps, args.path),
+            "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
+                                                args.path, lbm.LBM_FP32),
+            "batched_c3": lowp_accuracy(W.c3_batch(), 20000, 100, args.graph_steps, args.path, lbm.LBM_FP32),
+        }
+        out["fp16_accuracy"] = {
+            "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
+                                                args.path, lbm.LBM_FP16),
+            "emulsion_2048_64_droplets": lowp_accuracy([c5], 5000, 500, args.graph_steps, args.path,
+                                                       lbm.LBM_FP16),
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c5, args.cpu_budget)

@@ -49,6 +49,8 @@ extern "C" {
 
 #define LBM_FP64 0 /* populations, fields and arithmetic in FP64 */
 #define LBM_FP32 1 /* populations, fields and arithmetic in FP32; droplet sums in FP64 */
+#define LBM_FP16 2 /* populations stored as FP16 deviations f_i - w_i n0 from the rest state (round to
+                      nearest even), widened to FP32 on load; fields and arithmetic FP32; sums FP64 */
 
 #define LBM_ADV_PAPER 0 /* advection half-step of Eqs. (16)-(17) as printed */
 #define LBM_ADV_FLUX 1  /* conservative face-upwind flux form of the same half-step */
@@ -63,7 +65,7 @@ extern "C" {
 /* Per-instance model parameters (lattice units). */
 typedef struct lbm_config {
   int32_t nx, ny;     /* periodic lattice, nx, ny >= 3 */
-  int32_t precision;  /* LBM_FP64 or LBM_FP32; equal for every instance of a batch */
+  int32_t precision;  /* LBM_FP64, LBM_FP32 or LBM_FP16; equal for every instance of a batch */
   int32_t advection;  /* LBM_ADV_PAPER or LBM_ADV_FLUX */
   double tau;         /* BGK relaxation time, > 1/2; viscosity (tau - 1/2)/3 (Eq. 15) */
   double n0;          /* initial fluid density (populations w_i n0 when none are given) */

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -62,8 +63,8 @@ int validate(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop) {
     snprintf(where, sizeof where, "instance %d: ", i);
     if (c.nx < 3 || c.ny < 3) return fail(LBM_E_INVAL, std::string(where) + "nx and ny must be >= 3");
     if ((int64_t)c.nx * c.ny > (int64_t)1 << 30) return fail(LBM_E_INVAL, std::string(where) + "lattice too large");
-    if (c.precision != LBM_FP64 && c.precision != LBM_FP32)
-      return fail(LBM_E_INVAL, std::string(where) + "precision must be LBM_FP64 or LBM_FP32");
+    if (c.precision != LBM_FP64 && c.precision != LBM_FP32 && c.precision != LBM_FP16)
+      return fail(LBM_E_INVAL, std::string(where) + "precision must be LBM_FP64, LBM_FP32 or LBM_FP16");
     if (c.precision != cfgs[0].precision) return fail(LBM_E_INVAL, "all instances of a batch need the same precision");
     if (c.advection != LBM_ADV_PAPER && c.advection != LBM_ADV_FLUX)
       return fail(LBM_E_INVAL, std::string(where) + "unknown advection scheme");
@@ -104,9 +105,11 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.drop_base = drop_base;
     const int64_t plane = (int64_t)c.ny * d.pitch;
     d.pstride = plane;
+    // a population buffer holds 9 planes of the storage type (FP16 deviations take half a field plane)
+    const int64_t fbuf = L.prec == LBM_FP16 ? (int64_t)align_up((size_t)(9 * plane / 2), row_align) : 9 * plane;
     int64_t o = pool_elems;
-    d.off_f[0] = o;  o += 9 * plane;
-    d.off_f[1] = o;  o += 9 * plane;
+    d.off_f[0] = o;  o += fbuf;
+    d.off_f[1] = o;  o += fbuf;
     d.off_phi[0] = o; o += plane;
     d.off_phi[1] = o; o += plane;
     d.off_c[0] = o;  o += plane;
@@ -133,6 +136,9 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.coef = 1.0 - 1.0 / (2.0 * c.tau);
     d.A0 = c.A0;
     d.t_star = c.t_star;
+    d.wn[0] = WGT[0] * c.n0;
+    d.wn[1] = WGT[1] * c.n0;
+    d.wn[2] = WGT[5] * c.n0;
     tile_base += d.tiles_x[TILING_SPLIT] * d.tiles_y[TILING_SPLIT];
     seg_base += d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED];
     drop_base += d.ndrop;
@@ -241,28 +247,57 @@ struct lbm_ctx {
 
 namespace {
 
+// Calls f(T{}, P{}) with the arithmetic type T and the population storage type P of a precision code.
+template <class F>
+decltype(auto) with_types(int prec, F&& f) {
+  if (prec == LBM_FP64) return f(double{}, double{});
+  if (prec == LBM_FP32) return f(float{}, float{});
+  return f(float{}, _Float16{});
+}
+
+// Host side of the population storage (the kernels' pop_st / pop_ld): P == T stores the population; a
+// _Float16 store keeps fp16(fp32(f) - fp32(w_i n0)), widened back as fp32(stored) + fp32(w_i n0).
+template <typename T, typename P>
+P host_pop_store(double f, double wn) {
+  if constexpr (std::is_same<T, P>::value) {
+    (void)wn;
+    return (T)f;
+  } else {
+    return (P)((float)f - (float)wn);
+  }
+}
+template <typename T, typename P>
+double host_pop_load(P s, double wn) {
+  if constexpr (std::is_same<T, P>::value) {
+    (void)wn;
+    return (double)s;
+  } else {
+    return (double)((float)s + (float)wn);
+  }
+}
+
 // The sweeping kernel of a strip path (LBM_PATH_FUSED or LBM_PATH_WAVE) over the strip list.
-template <typename T>
+template <typename T, typename P>
 hipError_t launch_sweep(lbm_ctx* c, int parity, double* dbg, int dbg_inst) {
   T* buf = reinterpret_cast<T*>(c->pool());
   if (c->path == LBM_PATH_WAVE)
-    return launch_wave<T>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(),
+    return launch_wave<T, P>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(),
                           c->d_part(), c->d_mask(), c->d_step(), dbg, dbg_inst);
-  return launch_step<T>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(), c->d_part(),
-                        c->d_mask(), c->d_step(), dbg, dbg_inst);
+  return launch_step<T, P>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(),
+                           c->d_part(), c->d_mask(), c->d_step(), dbg, dbg_inst);
 }
 
-template <typename T>
+template <typename T, typename P>
 hipError_t enqueue_step(lbm_ctx* c, int parity) {
   T* buf = reinterpret_cast<T*>(c->pool());
   hipError_t e;
   if (c->path != LBM_PATH_SPLIT) {
-    e = launch_sweep<T>(c, parity, nullptr, -1);
+    e = launch_sweep<T, P>(c, parity, nullptr, -1);
     if (e != hipSuccess) return e;
     return launch_reduce(c->stream, TILING_FUSED, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(),
                          c->d_mask(), c->d_step(), 1);
   }
-  e = launch_lb<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+  e = launch_lb<T, P>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
   if (e != hipSuccess) return e;
   e = launch_fd<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
                    c->d_part(), c->d_mask(), c->d_step(), nullptr, -1);
@@ -272,7 +307,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity) {
 }
 
 hipError_t enqueue_step_any(lbm_ctx* c, int parity) {
-  return c->L.prec == LBM_FP64 ? enqueue_step<double>(c, parity) : enqueue_step<float>(c, parity);
+  return with_types(c->L.prec, [&](auto t, auto p) { return enqueue_step<decltype(t), decltype(p)>(c, parity); });
 }
 
 void destroy_graphs(lbm_ctx* c) {
@@ -306,12 +341,13 @@ void to_device_layout(const double* src, T* dst, int nx, int ny, int pitch) {
     for (int x = 0; x < pitch; ++x) dst[(size_t)y * pitch + x] = x < nx ? (T)src[(size_t)y * nx + x] : T(0);
 }
 
-template <typename T>
+template <typename T, typename P>
 int upload_instance(lbm_ctx* c, int i, const double* phi0, const double* c0, const double* f_pre) {
   const InstDev& d = c->L.inst[i];
   const int nx = d.nx, ny = d.ny, pitch = d.pitch;
   const size_t plane = (size_t)d.pstride;
-  std::vector<T> h(plane * 9);
+  std::vector<T> h(plane);
+  std::vector<P> hf(plane * 9);
   T* base = reinterpret_cast<T*>(c->pool());
   to_device_layout(phi0, h.data(), nx, ny, pitch);
   HIPCHK(hipMemcpyAsync(base + d.off_phi[0], h.data(), plane * sizeof(T), hipMemcpyHostToDevice, c->stream));
@@ -320,7 +356,7 @@ int upload_instance(lbm_ctx* c, int i, const double* phi0, const double* c0, con
   HIPCHK(hipMemcpyAsync(base + d.off_c[0], h.data(), plane * sizeof(T), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   // Stored populations are post-collision values at the emitting node: f*_i(r) = f_i(r + e_i).
-  std::fill(h.begin(), h.end(), T(0));
+  P* fbase = reinterpret_cast<P*>(base + d.off_f[0]);
   for (int k = 0; k < 9; ++k)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
@@ -331,13 +367,13 @@ int upload_instance(lbm_ctx* c, int i, const double* phi0, const double* c0, con
         } else {
           v = WGT[k] * c->cfg[i].n0;
         }
-        h[(size_t)k * plane + (size_t)y * pitch + x] = (T)v;
+        hf[(size_t)k * plane + (size_t)y * pitch + x] = host_pop_store<T, P>(v, WGT[k] * c->cfg[i].n0);
       }
-  HIPCHK(hipMemcpyAsync(base + d.off_f[0], h.data(), 9 * plane * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(fbase, hf.data(), 9 * plane * sizeof(P), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   // velocity / density planes start at zero; the second buffers are fully rewritten by the first step
   HIPCHK(hipMemsetAsync(base + d.off_ux, 0, 3 * plane * sizeof(T), c->stream));
-  HIPCHK(hipMemsetAsync(base + d.off_f[1], 0, 9 * plane * sizeof(T), c->stream));
+  HIPCHK(hipMemsetAsync(base + d.off_f[1], 0, 9 * plane * sizeof(P), c->stream));
   HIPCHK(hipMemsetAsync(base + d.off_phi[1], 0, plane * sizeof(T), c->stream));
   HIPCHK(hipMemsetAsync(base + d.off_c[1], 0, plane * sizeof(T), c->stream));
   return LBM_OK;
@@ -351,13 +387,11 @@ int check_inst(lbm_ctx* c, int32_t inst) {
 
 // n, u planes of every instance from the current state (Eq. 11 with the force of Eq. 14).
 int run_diag(lbm_ctx* c) {
-  hipError_t e;
-  if (c->L.prec == LBM_FP64)
-    e = launch_lb<double>(c->stream, 2, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
-                          reinterpret_cast<double*>(c->pool()), nullptr, -1);
-  else
-    e = launch_lb<float>(c->stream, 2, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
-                         reinterpret_cast<float*>(c->pool()), nullptr, -1);
+  const hipError_t e = with_types(c->L.prec, [&](auto t, auto p) {
+    using T = decltype(t);
+    return launch_lb<T, decltype(p)>(c->stream, 2, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
+                                     reinterpret_cast<T*>(c->pool()), nullptr, -1);
+  });
   if (e != hipSuccess) return fail(LBM_E_HIP, std::string("diagnostic launch: ") + hipGetErrorString(e));
   return LBM_OK;
 }
@@ -374,7 +408,7 @@ int download_plane(lbm_ctx* c, int64_t off, const InstDev& d, double* out) {
   return LBM_OK;
 }
 
-template <typename T>
+template <typename T, typename P>
 int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, double* n, double* ux,
                 double* uy) {
   const InstDev& d = c->L.inst[inst];
@@ -389,9 +423,9 @@ int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, do
   if (uy && (rc = download_plane<T>(c, d.off_uy, d, uy)) != LBM_OK) return rc;
   if (f_pre) {
     const size_t plane = (size_t)d.pstride;
-    std::vector<T> h(9 * plane);
-    HIPCHK(hipMemcpyAsync(h.data(), reinterpret_cast<T*>(c->pool()) + d.off_f[c->parity], 9 * plane * sizeof(T),
-                          hipMemcpyDeviceToHost, c->stream));
+    std::vector<P> h(9 * plane);
+    HIPCHK(hipMemcpyAsync(h.data(), reinterpret_cast<P*>(reinterpret_cast<T*>(c->pool()) + d.off_f[c->parity]),
+                          9 * plane * sizeof(P), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     const int nx = d.nx, ny = d.ny;
     for (int k = 0; k < 9; ++k)
@@ -399,32 +433,33 @@ int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, do
         for (int x = 0; x < nx; ++x) {
           // pre-collision f_k(r) = f*_k(r - e_k)
           const int xs = (x - EX[k] + nx) % nx, ys = (y - EY[k] + ny) % ny;
-          f_pre[(size_t)k * nx * ny + (size_t)y * nx + x] = (double)h[(size_t)k * plane + (size_t)ys * d.pitch + xs];
+          f_pre[(size_t)k * nx * ny + (size_t)y * nx + x] =
+              host_pop_load<T, P>(h[(size_t)k * plane + (size_t)ys * d.pitch + xs], WGT[k] * c->cfg[inst].n0);
         }
   }
   return LBM_OK;
 }
 
 // Stage planes of the next step of instance `inst` from the kernels of the current path.
-template <typename T>
+template <typename T, typename P>
 hipError_t debug_launch(lbm_ctx* c, int inst) {
   T* buf = reinterpret_cast<T*>(c->pool());
-  if (c->path != LBM_PATH_SPLIT) return launch_sweep<T>(c, c->parity, c->d_dbg(), inst);
-  hipError_t e = launch_lb<T>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
+  if (c->path != LBM_PATH_SPLIT) return launch_sweep<T, P>(c, c->parity, c->d_dbg(), inst);
+  hipError_t e = launch_lb<T, P>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
   if (e != hipSuccess) return e;
   return launch_fd<T>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
                       c->d_mask(), c->d_step(), c->d_dbg(), inst);
 }
 
 // One eager step with hipEvents between its kernels: ev[0..nk] bracket nk launches.
-template <typename T>
+template <typename T, typename P>
 hipError_t timed_step(lbm_ctx* c, hipEvent_t* ev, int* nk) {
   T* buf = reinterpret_cast<T*>(c->pool());
   const int p = c->parity;
   hipError_t e;
   (void)hipEventRecord(ev[0], c->stream);
   if (c->path != LBM_PATH_SPLIT) {
-    e = launch_sweep<T>(c, p, nullptr, -1);
+    e = launch_sweep<T, P>(c, p, nullptr, -1);
     (void)hipEventRecord(ev[1], c->stream);
     if (e == hipSuccess)
       e = launch_reduce(c->stream, TILING_FUSED, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
@@ -432,7 +467,7 @@ hipError_t timed_step(lbm_ctx* c, hipEvent_t* ev, int* nk) {
     (void)hipEventRecord(ev[2], c->stream);
     *nk = 2;
   } else {
-    e = launch_lb<T>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+    e = launch_lb<T, P>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
     (void)hipEventRecord(ev[1], c->stream);
     if (e == hipSuccess)
       e = launch_fd<T>(c->stream, 0, p, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
@@ -514,9 +549,10 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
   size_t off_field = 0;
   for (int i = 0; i < ninst; ++i) {
     const size_t n = (size_t)cfgs[i].nx * cfgs[i].ny;
-    rc = c->L.prec == LBM_FP64
-             ? upload_instance<double>(c, i, phi0 + off_field, c0 + off_field, f_pre ? f_pre + 9 * off_field : nullptr)
-             : upload_instance<float>(c, i, phi0 + off_field, c0 + off_field, f_pre ? f_pre + 9 * off_field : nullptr);
+    rc = with_types(c->L.prec, [&](auto t, auto p) {
+      return upload_instance<decltype(t), decltype(p)>(c, i, phi0 + off_field, c0 + off_field,
+                                                       f_pre ? f_pre + 9 * off_field : nullptr);
+    });
     if (rc != LBM_OK) return bail(rc);
     off_field += n;
   }
@@ -543,12 +579,11 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
   INIT_CHK(hipMemsetAsync(c->d_mask(), 0, sizeof(uint64_t) * MASK_WORDS * std::max(c->L.ntiles, c->L.max_segs),
                           c->stream));
   // first centre-of-mass pass on phi0, started from the given centres
-  if (c->L.prec == LBM_FP64)
-    INIT_CHK(launch_cm_partials<double>(c->stream, 0, c->nlaunch(), c->d_tiles(), c->d_inst(),
-                                        reinterpret_cast<double*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask()));
-  else
-    INIT_CHK(launch_cm_partials<float>(c->stream, 0, c->nlaunch(), c->d_tiles(), c->d_inst(),
-                                       reinterpret_cast<float*>(c->pool()), c->d_drops(), c->d_part(), c->d_mask()));
+  INIT_CHK(with_types(c->L.prec, [&](auto t, auto) {
+    using T = decltype(t);
+    return launch_cm_partials<T>(c->stream, 0, c->nlaunch(), c->d_tiles(), c->d_inst(), reinterpret_cast<T*>(c->pool()),
+                                 c->d_drops(), c->d_part(), c->d_mask());
+  }));
   INIT_CHK(launch_reduce(c->stream, TILING_SPLIT, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(),
                          c->d_mask(), c->d_step(), 0));
   INIT_CHK(hipStreamSynchronize(c->stream));
@@ -610,8 +645,9 @@ int lbm_fields(lbm_ctx* c, int32_t inst, double* f_pre, double* phi, double* cc,
   int rc = check_inst(c, inst);
   if (rc != LBM_OK) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
-  return c->L.prec == LBM_FP64 ? fields_impl<double>(c, inst, f_pre, phi, cc, n, ux, uy)
-                               : fields_impl<float>(c, inst, f_pre, phi, cc, n, ux, uy);
+  return with_types(c->L.prec, [&](auto t, auto p) {
+    return fields_impl<decltype(t), decltype(p)>(c, inst, f_pre, phi, cc, n, ux, uy);
+  });
 }
 
 int lbm_droplets(lbm_ctx* c, int32_t inst, lbm_droplet* out) {
@@ -630,13 +666,11 @@ int lbm_observables(lbm_ctx* c, int32_t inst, lbm_obs* obs, double* drop_out) {
   if (rc != LBM_OK) return rc;
   if (!obs) return fail(LBM_E_INVAL, "obs must not be NULL");
   if ((rc = run_diag(c)) != LBM_OK) return rc;
-  hipError_t e = c->L.prec == LBM_FP64
-                     ? launch_obs<double>(c->stream, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
-                                          reinterpret_cast<double*>(c->pool()), c->d_drops(), c->d_obs(),
-                                          c->L.obs_stride)
-                     : launch_obs<float>(c->stream, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
-                                         reinterpret_cast<float*>(c->pool()), c->d_drops(), c->d_obs(),
-                                         c->L.obs_stride);
+  hipError_t e = with_types(c->L.prec, [&](auto t, auto p) {
+    using T = decltype(t);
+    return launch_obs<T, decltype(p)>(c->stream, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(),
+                                      reinterpret_cast<T*>(c->pool()), c->d_drops(), c->d_obs(), c->L.obs_stride);
+  });
   if (e != hipSuccess) return fail(LBM_E_HIP, std::string("observables launch: ") + hipGetErrorString(e));
   const InstDev& d = c->L.inst[inst];
   const int nt = d.tiles_x[TILING_SPLIT] * d.tiles_y[TILING_SPLIT], S = c->L.obs_stride;
@@ -690,7 +724,7 @@ int lbm_debug_stage(lbm_ctx* c, int32_t inst, double* out) {
   if (!out) return fail(LBM_E_INVAL, "out must not be NULL");
   const InstDev& d = c->L.inst[inst];
   if ((int64_t)d.nx * d.ny > DEBUG_MAX_NODES) return fail(LBM_E_INVAL, "stage export is limited to 512 x 512 nodes");
-  hipError_t e = c->L.prec == LBM_FP64 ? debug_launch<double>(c, inst) : debug_launch<float>(c, inst);
+  hipError_t e = with_types(c->L.prec, [&](auto t, auto p) { return debug_launch<decltype(t), decltype(p)>(c, inst); });
   if (e != hipSuccess) return fail(LBM_E_HIP, std::string("stage launch: ") + hipGetErrorString(e));
   const size_t n = (size_t)d.nx * d.ny;
   HIPCHK(hipMemcpyAsync(out, c->d_dbg(), sizeof(double) * LBM_NSTAGE * n, hipMemcpyDeviceToHost, c->stream));
@@ -706,7 +740,8 @@ int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
   hipError_t e = hipSuccess;
   int nk = 0;
   for (int64_t s = 0; s < n && e == hipSuccess; ++s)
-    e = c->L.prec == LBM_FP64 ? timed_step<double>(c, &ev[(size_t)s * 4], &nk) : timed_step<float>(c, &ev[(size_t)s * 4], &nk);
+    e = with_types(c->L.prec,
+                   [&](auto t, auto p) { return timed_step<decltype(t), decltype(p)>(c, &ev[(size_t)s * 4], &nk); });
   hipError_t es = hipStreamSynchronize(c->stream);
   double acc[3] = {0, 0, 0};
   if (e == hipSuccess && es == hipSuccess) {
@@ -782,8 +817,8 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows
   auto trial = [&](int n) -> hipError_t {
     hipError_t e = hipSuccess;
     for (int rep = 0; rep < n && e == hipSuccess; ++rep)
-      e = c->L.prec == LBM_FP64 ? launch_sweep<double>(c, c->parity, nullptr, -1)
-                                : launch_sweep<float>(c, c->parity, nullptr, -1);
+      e = with_types(c->L.prec,
+                     [&](auto t, auto p) { return launch_sweep<decltype(t), decltype(p)>(c, c->parity, nullptr, -1); });
     return e;
   };
   for (int pass = 0; pass < 2 && rc == LBM_OK; ++pass) {

@@ -45,6 +45,7 @@ struct InstDev {
   int32_t advection, pad0;
   // model parameters, derived on the host in double precision
   double a, b, B0, B1, halfB1, D, Gamma, gamma, c0, omega, coef, A0, t_star;
+  double wn[3];  // rest populations w_i n0 of the three weight classes (centre, axis, diagonal)
 };
 
 // Droplet table entry on the device.
@@ -58,9 +59,11 @@ struct TileDev {
   int32_t inst, x0, y0, t;  // t: natural tile index (partials are stored by it)
 };
 
-// Launch helpers implemented in lbm_kernels.hip.  `buf` is the typed base pointer of the field pool,
-// `parity` selects the current buffers.  Modes: 0 step, 1 step + stage export, 2 diagnostics only.
-template <typename T>
+// Launch helpers, instantiated in lbm_kernels_f64.hip, lbm_kernels_f32.hip and lbm_kernels_f16.hip.
+// T is the arithmetic (and field) type, P the population storage type (T itself, or _Float16 deviations
+// from w_i n0 with T = float).  `buf` is the typed base pointer of the field pool, `parity` selects the
+// current buffers.  Modes: 0 step, 1 step + stage export, 2 diagnostics only.
+template <typename T, typename P>
 hipError_t launch_lb(hipStream_t s, int mode, int parity, int ntiles_launch, const TileDev* tiles,
                      const InstDev* inst, T* buf, double* dbg, int dbg_inst);
 template <typename T>
@@ -75,16 +78,16 @@ hipError_t launch_reduce(hipStream_t s, int tiling, int ndrop_total, const InstD
                          const double* part, const uint64_t* mask, int64_t* step, int increment);
 // Fused timestep (one launch per step over the strip list); dbg != nullptr exports stage planes of
 // instance dbg_inst instead of advancing.
-template <typename T>
+template <typename T, typename P>
 hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst,
                        T* buf, const DropDev* drops, double* part, uint64_t* mask, const int64_t* step,
                        double* dbg, int dbg_inst);
 // Same step as launch_step, computed by one 64-lane wavefront per strip segment (no workgroup barriers).
-template <typename T>
+template <typename T, typename P>
 hipError_t launch_wave(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst,
                        T* buf, const DropDev* drops, double* part, uint64_t* mask, const int64_t* step,
                        double* dbg, int dbg_inst);
-template <typename T>
+template <typename T, typename P>
 hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
                       const InstDev* inst, T* buf, const DropDev* drops, double* obs_part,
                       int obs_stride);

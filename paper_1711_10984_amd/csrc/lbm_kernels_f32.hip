@@ -5,6 +5,7 @@
 
 namespace lbm {
 
-LBM_INSTANTIATE(float)
+LBM_INSTANTIATE_FIELDS(float)
+LBM_INSTANTIATE_POPS(float, float)
 
 }  // namespace lbm

@@ -12,6 +12,7 @@ hipError_t launch_reduce(hipStream_t s, int tiling, int ndrop_total, const InstD
   return hipGetLastError();
 }
 
-LBM_INSTANTIATE(double)
+LBM_INSTANTIATE_FIELDS(double)
+LBM_INSTANTIATE_POPS(double, double)
 
 }  // namespace lbm

@@ -25,6 +25,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -34,6 +36,27 @@ namespace {
 template <typename T>
 __device__ __forceinline__ constexpr T cst(double x) {
   return static_cast<T>(x);
+}
+
+// Population storage.  P == T: the populations themselves.  P == _Float16 (with T = float): the deviation
+// f_i - w_i n0 from the rest state, rounded to FP16 (round to nearest even); wn = w_i n0 in T.
+template <typename T, typename P>
+__device__ __forceinline__ T pop_ld(P v, T wn) {
+  if constexpr (std::is_same<T, P>::value) {
+    (void)wn;
+    return v;
+  } else {
+    return T(v) + wn;
+  }
+}
+template <typename P, typename T>
+__device__ __forceinline__ P pop_st(T v, T wn) {
+  if constexpr (std::is_same<T, P>::value) {
+    (void)wn;
+    return v;
+  } else {
+    return P(v - wn);
+  }
 }
 
 __device__ __forceinline__ int wrap_idx(int v, int n) {
@@ -281,7 +304,7 @@ __device__ void tile_cm_sums(const InstDev& I, int t_local, int t_global, const 
 
 // ------------------------------------------------------------------------------------------------
 // k_lb: mu, X, F; pull + moments; collision.  MODE 0: step, 1: step + stage planes, 2: n and u only.
-template <typename T, int MODE>
+template <typename T, typename P, int MODE>
 __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __restrict__ tiles,
                                                  const InstDev* __restrict__ insts, T* __restrict__ buf,
                                                  double* __restrict__ dbg, int dbg_inst) {
@@ -299,8 +322,9 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
   const int64_t plane = I.pstride;
   const T* __restrict__ phi = buf + I.off_phi[parity];
   const T* __restrict__ cc = buf + I.off_c[parity];
-  const T* __restrict__ fin = buf + I.off_f[parity];
-  T* __restrict__ fout = buf + I.off_f[parity ^ 1];
+  const P* __restrict__ fin = reinterpret_cast<const P*>(buf + I.off_f[parity]);
+  P* __restrict__ fout = reinterpret_cast<P*>(buf + I.off_f[parity ^ 1]);
+  const T wr0 = T(I.wn[0]), wr1 = T(I.wn[1]), wr5 = T(I.wn[2]);
 
   for (int i = tid; i < W2; i += NTHREADS) s_col[i] = wrap_idx(td.x0 + i - 2, nx);
   for (int i = tid; i < H2; i += NTHREADS) s_row[i] = wrap_idx(td.y0 + i - 2, ny);
@@ -351,15 +375,15 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const int64_t r0 = (int64_t)y * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
-    const T f0 = fin[r0 + x];
-    const T f1 = fin[plane + r0 + xm];
-    const T f2 = fin[2 * plane + rm + x];
-    const T f3 = fin[3 * plane + r0 + xp];
-    const T f4 = fin[4 * plane + rp + x];
-    const T f5 = fin[5 * plane + rm + xm];
-    const T f6 = fin[6 * plane + rm + xp];
-    const T f7 = fin[7 * plane + rp + xp];
-    const T f8 = fin[8 * plane + rp + xm];
+    const T f0 = pop_ld<T>(fin[r0 + x], wr0);
+    const T f1 = pop_ld<T>(fin[plane + r0 + xm], wr1);
+    const T f2 = pop_ld<T>(fin[2 * plane + rm + x], wr1);
+    const T f3 = pop_ld<T>(fin[3 * plane + r0 + xp], wr1);
+    const T f4 = pop_ld<T>(fin[4 * plane + rp + x], wr1);
+    const T f5 = pop_ld<T>(fin[5 * plane + rm + xm], wr5);
+    const T f6 = pop_ld<T>(fin[6 * plane + rm + xp], wr5);
+    const T f7 = pop_ld<T>(fin[7 * plane + rp + xp], wr5);
+    const T f8 = pop_ld<T>(fin[8 * plane + rp + xm], wr5);
     const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
     const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
     const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
@@ -388,15 +412,15 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
     const T s6 = collide1(f6, wn5, cw5, nux + uy, nFx + Fy, xm1, yp1, Fx, Fy, usq, omega);
     const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
     const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
-    fout[o] = s0;
-    fout[plane + o] = s1;
-    fout[2 * plane + o] = s2;
-    fout[3 * plane + o] = s3;
-    fout[4 * plane + o] = s4;
-    fout[5 * plane + o] = s5;
-    fout[6 * plane + o] = s6;
-    fout[7 * plane + o] = s7;
-    fout[8 * plane + o] = s8;
+    fout[o] = pop_st<P>(s0, wr0);
+    fout[plane + o] = pop_st<P>(s1, wr1);
+    fout[2 * plane + o] = pop_st<P>(s2, wr1);
+    fout[3 * plane + o] = pop_st<P>(s3, wr1);
+    fout[4 * plane + o] = pop_st<P>(s4, wr1);
+    fout[5 * plane + o] = pop_st<P>(s5, wr5);
+    fout[6 * plane + o] = pop_st<P>(s6, wr5);
+    fout[7 * plane + o] = pop_st<P>(s7, wr5);
+    fout[8 * plane + o] = pop_st<P>(s8, wr5);
     if (MODE == 1) {
       const int64_t q = (int64_t)y * nx + x;
       dbg[0 * nplane + q] = (double)s_mu[i1];
@@ -612,7 +636,7 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(int tiling, int ndrop_total
 
 // Observables of the current state from the n, u planes written by k_lb<MODE 2>:
 // per-tile {mass, sum phi, sum c, min B, max |u|, nonfinite, per droplet (phi, phi ux, phi uy)}.
-template <typename T>
+template <typename T, typename P>
 __global__ __launch_bounds__(NTHREADS) void k_obs(int parity, const TileDev* __restrict__ tiles,
                                                   const InstDev* __restrict__ insts, const T* __restrict__ buf,
                                                   const DropDev* __restrict__ drops,
@@ -632,7 +656,7 @@ __global__ __launch_bounds__(NTHREADS) void k_obs(int parity, const TileDev* __r
   }
   const T* __restrict__ phi = buf + I.off_phi[parity];
   const T* __restrict__ cc = buf + I.off_c[parity];
-  const T* __restrict__ fst = buf + I.off_f[parity];
+  const P* __restrict__ fst = reinterpret_cast<const P*>(buf + I.off_f[parity]);
   double m = 0.0, sp = 0.0, sc = 0.0, mb = 1e300, mu = 0.0, nf = 0.0;
   int kd[NPT];
   double vv[NPT], vx[NPT], vy[NPT];
@@ -797,7 +821,7 @@ __device__ __forceinline__ void block_reduce3(double& a, double& b, double& c, d
   __syncthreads();
 }
 
-template <typename T, bool DBG>
+template <typename T, typename P, bool DBG>
 __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __restrict__ segs,
                                                    const InstDev* __restrict__ insts, T* __restrict__ buf,
                                                    const DropDev* __restrict__ drops, double* __restrict__ part,
@@ -824,8 +848,9 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   const int64_t plane = I.pstride;
   const T* __restrict__ phi_in = buf + I.off_phi[parity];
   const T* __restrict__ c_in = buf + I.off_c[parity];
-  const T* __restrict__ fin = buf + I.off_f[parity];
-  T* __restrict__ fout = buf + I.off_f[parity ^ 1];
+  const P* __restrict__ fin = reinterpret_cast<const P*>(buf + I.off_f[parity]);
+  P* __restrict__ fout = reinterpret_cast<P*>(buf + I.off_f[parity ^ 1]);
+  const T wr0 = T(I.wn[0]), wr1 = T(I.wn[1]), wr5 = T(I.wn[2]);
   T* __restrict__ phi_out = buf + I.off_phi[parity ^ 1];
   T* __restrict__ c_out = buf + I.off_c[parity ^ 1];
   const int64_t nplane = (int64_t)nx * ny;
@@ -885,8 +910,8 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
 
   // prefetch registers: phi, c of the stage-0 row and the pulled populations of the stage-2 row
   T pf_phi = T(0), pf_c = T(0);
-  T pf[9];
-  for (int i = 0; i < 9; ++i) pf[i] = T(0);
+  P pf[9];
+  for (int i = 0; i < 9; ++i) pf[i] = P(0);
   auto load_s0 = [&](int it) {
     const int r = y0 - 5 + it * FUSED_R + wv;
     if (r < yend + 5) {
@@ -963,8 +988,9 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
         const T ph = r_phi[sm][lane], cv = r_c[sm][lane];
         const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
         const T Fy = (-(ph * gmy) - gcy) - cv * gXy;
-        const T f0 = pf[0], f1 = pf[1], f2 = pf[2], f3 = pf[3], f4 = pf[4], f5 = pf[5], f6 = pf[6], f7 = pf[7],
-                f8 = pf[8];
+        const T f0 = pop_ld<T>(pf[0], wr0), f1 = pop_ld<T>(pf[1], wr1), f2 = pop_ld<T>(pf[2], wr1),
+                f3 = pop_ld<T>(pf[3], wr1), f4 = pop_ld<T>(pf[4], wr1), f5 = pop_ld<T>(pf[5], wr5),
+                f6 = pop_ld<T>(pf[6], wr5), f7 = pop_ld<T>(pf[7], wr5), f8 = pop_ld<T>(pf[8], wr5);
         const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
         const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
         const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
@@ -987,15 +1013,15 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
           const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
           const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
           const int64_t o = (int64_t)r * pitch + gx;
-          fout[o] = s0;
-          fout[plane + o] = s1;
-          fout[2 * plane + o] = s2;
-          fout[3 * plane + o] = s3;
-          fout[4 * plane + o] = s4;
-          fout[5 * plane + o] = s5;
-          fout[6 * plane + o] = s6;
-          fout[7 * plane + o] = s7;
-          fout[8 * plane + o] = s8;
+          fout[o] = pop_st<P>(s0, wr0);
+          fout[plane + o] = pop_st<P>(s1, wr1);
+          fout[2 * plane + o] = pop_st<P>(s2, wr1);
+          fout[3 * plane + o] = pop_st<P>(s3, wr1);
+          fout[4 * plane + o] = pop_st<P>(s4, wr1);
+          fout[5 * plane + o] = pop_st<P>(s5, wr5);
+          fout[6 * plane + o] = pop_st<P>(s6, wr5);
+          fout[7 * plane + o] = pop_st<P>(s7, wr5);
+          fout[8 * plane + o] = pop_st<P>(s8, wr5);
           if (DBG) {
             const int64_t q = (int64_t)r * nx + (x0 + col);
             dbg[2 * nplane + q] = (double)Fx;
@@ -1320,7 +1346,7 @@ __device__ __forceinline__ T advect_n(T gc, T ge, T gw, T gn, T gs, T uc, T ue, 
   return gc - ((Fr - Fl) + (Ft - Fb));
 }
 
-template <typename T, bool DBG>
+template <typename T, typename P, bool DBG>
 // Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD;
 // FP32 fits three.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
@@ -1346,8 +1372,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int64_t plane = I.pstride;
   const T* __restrict__ phi_in = buf + I.off_phi[parity];
   const T* __restrict__ c_in = buf + I.off_c[parity];
-  const T* __restrict__ fin = buf + I.off_f[parity];
-  T* __restrict__ fout = buf + I.off_f[parity ^ 1];
+  const P* __restrict__ fin = reinterpret_cast<const P*>(buf + I.off_f[parity]);
+  P* __restrict__ fout = reinterpret_cast<P*>(buf + I.off_f[parity ^ 1]);
+  const T wr0 = T(I.wn[0]), wr1 = T(I.wn[1]), wr5 = T(I.wn[2]);
   T* __restrict__ phi_out = buf + I.off_phi[parity ^ 1];
   T* __restrict__ c_out = buf + I.off_c[parity ^ 1];
   const int64_t nplane = (int64_t)nx * ny;
@@ -1420,11 +1447,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   // register holding an outstanding load is ever copied.
   constexpr int PFD = sizeof(T) == 8 ? 2 : 1;
   struct Pref {
-    T phi, c, f[9];
+    T phi, c;
+    P f[9];
   };
   Pref pfs[PFD];
   // Addresses: a wave-uniform row pointer (scalar registers) plus a per-lane 32-bit column byte offset.
-  const unsigned bx = (unsigned)gx * sizeof(T), bxm = (unsigned)gxm * sizeof(T), bxp = (unsigned)gxp * sizeof(T);
+  const unsigned bx = (unsigned)gx * sizeof(T);
+  const unsigned fx = (unsigned)gx * sizeof(P), fxm = (unsigned)gxm * sizeof(P), fxp = (unsigned)gxp * sizeof(P);
   auto load_s0 = [&](Pref& p, int r) {
     const int64_t ro = (int64_t)wrap_near(r, ny) * pitch;
     p.phi = ld_col(phi_in + ro, bx);
@@ -1434,15 +1463,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int gy = wrap_near(r, ny);
     const int gym = gy == 0 ? ny - 1 : gy - 1, gyp = gy == ny - 1 ? 0 : gy + 1;
     const int64_t r0 = (int64_t)gy * pitch, rm = (int64_t)gym * pitch, rp = (int64_t)gyp * pitch;
-    p.f[0] = ld_col(fin + r0, bx);
-    p.f[1] = ld_col(fin + plane + r0, bxm);
-    p.f[2] = ld_col(fin + 2 * plane + rm, bx);
-    p.f[3] = ld_col(fin + 3 * plane + r0, bxp);
-    p.f[4] = ld_col(fin + 4 * plane + rp, bx);
-    p.f[5] = ld_col(fin + 5 * plane + rm, bxm);
-    p.f[6] = ld_col(fin + 6 * plane + rm, bxp);
-    p.f[7] = ld_col(fin + 7 * plane + rp, bxp);
-    p.f[8] = ld_col(fin + 8 * plane + rp, bxm);
+    p.f[0] = ld_col(fin + r0, fx);
+    p.f[1] = ld_col(fin + plane + r0, fxm);
+    p.f[2] = ld_col(fin + 2 * plane + rm, fx);
+    p.f[3] = ld_col(fin + 3 * plane + r0, fxp);
+    p.f[4] = ld_col(fin + 4 * plane + rp, fx);
+    p.f[5] = ld_col(fin + 5 * plane + rm, fxm);
+    p.f[6] = ld_col(fin + 6 * plane + rm, fxp);
+    p.f[7] = ld_col(fin + 7 * plane + rp, fxp);
+    p.f[8] = ld_col(fin + 8 * plane + rp, fxm);
   };
   // Set j serves the iterations it = j (mod PFD): stage-0 row y0 - 5 + it, stage-2 row y0 - 7 + it, whose
   // first valid row y0 - 3 comes at it = 4.
@@ -1490,8 +1519,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       const T ph = P2, cv = C2;
       const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
       const T Fy = (-(ph * gmy) - gcy) - cv * gXy;
-      const T f0 = pf.f[0], f1 = pf.f[1], f2 = pf.f[2], f3 = pf.f[3], f4 = pf.f[4], f5 = pf.f[5], f6 = pf.f[6],
-              f7 = pf.f[7], f8 = pf.f[8];
+      const T f0 = pop_ld<T>(pf.f[0], wr0), f1 = pop_ld<T>(pf.f[1], wr1), f2 = pop_ld<T>(pf.f[2], wr1),
+              f3 = pop_ld<T>(pf.f[3], wr1), f4 = pop_ld<T>(pf.f[4], wr1), f5 = pop_ld<T>(pf.f[5], wr5),
+              f6 = pop_ld<T>(pf.f[6], wr5), f7 = pop_ld<T>(pf.f[7], wr5), f8 = pop_ld<T>(pf.f[8], wr5);
       const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
       const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
       const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
@@ -1513,16 +1543,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         const T s6 = collide1(f6, wn5, cw5, nux + uy, nFx + Fy, xm1, yp1, Fx, Fy, usq, omega);
         const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
         const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
-        T* const o = fout + (int64_t)r * pitch;
-        st_col(o, bx, s0);
-        st_col(o + plane, bx, s1);
-        st_col(o + 2 * plane, bx, s2);
-        st_col(o + 3 * plane, bx, s3);
-        st_col(o + 4 * plane, bx, s4);
-        st_col(o + 5 * plane, bx, s5);
-        st_col(o + 6 * plane, bx, s6);
-        st_col(o + 7 * plane, bx, s7);
-        st_col(o + 8 * plane, bx, s8);
+        P* const o = fout + (int64_t)r * pitch;
+        st_col(o, fx, pop_st<P>(s0, wr0));
+        st_col(o + plane, fx, pop_st<P>(s1, wr1));
+        st_col(o + 2 * plane, fx, pop_st<P>(s2, wr1));
+        st_col(o + 3 * plane, fx, pop_st<P>(s3, wr1));
+        st_col(o + 4 * plane, fx, pop_st<P>(s4, wr1));
+        st_col(o + 5 * plane, fx, pop_st<P>(s5, wr5));
+        st_col(o + 6 * plane, fx, pop_st<P>(s6, wr5));
+        st_col(o + 7 * plane, fx, pop_st<P>(s7, wr5));
+        st_col(o + 8 * plane, fx, pop_st<P>(s8, wr5));
         if (DBG) {
           const int64_t qq = (int64_t)r * nx + (x0 + col);
           dbg[2 * nplane + qq] = (double)Fx;
@@ -1687,17 +1717,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 }  // namespace
 
 // ------------------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename P>
 hipError_t launch_lb(hipStream_t s, int mode, int parity, int ntiles_launch, const TileDev* tiles,
                      const InstDev* inst, T* buf, double* dbg, int dbg_inst) {
   if (ntiles_launch <= 0) return hipSuccess;
   dim3 grid(ntiles_launch), block(NTHREADS);
   if (mode == 0)
-    hipLaunchKernelGGL((k_lb<T, 0>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
+    hipLaunchKernelGGL((k_lb<T, P, 0>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_lb<T, 1>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
+    hipLaunchKernelGGL((k_lb<T, P, 1>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
   else
-    hipLaunchKernelGGL((k_lb<T, 2>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
+    hipLaunchKernelGGL((k_lb<T, P, 2>), grid, block, 0, s, parity, tiles, inst, buf, dbg, dbg_inst);
   return hipGetLastError();
 }
 
@@ -1726,56 +1756,58 @@ hipError_t launch_cm_partials(hipStream_t s, int parity, int ntiles_launch, cons
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename P>
 hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
                       const InstDev* inst, T* buf, const DropDev* drops, double* obs_part, int obs_stride) {
   if (ntiles_launch <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_obs<T>), dim3(ntiles_launch), dim3(NTHREADS), 0, s, parity, tiles, inst, buf, drops,
+  hipLaunchKernelGGL((k_obs<T, P>), dim3(ntiles_launch), dim3(NTHREADS), 0, s, parity, tiles, inst, buf, drops,
                      obs_part, obs_stride);
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename P>
 hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst, T* buf,
                        const DropDev* drops, double* part, uint64_t* mask, const int64_t* step, double* dbg,
                        int dbg_inst) {
   if (nseg_launch <= 0) return hipSuccess;
   if (dbg)
-    hipLaunchKernelGGL((k_step<T, true>), dim3(nseg_launch), dim3(NTHREADS), 0, s, parity, segs, inst, buf, drops,
-                       part, mask, step, dbg, dbg_inst);
+    hipLaunchKernelGGL((k_step<T, P, true>), dim3(nseg_launch), dim3(NTHREADS), 0, s, parity, segs, inst, buf,
+                       drops, part, mask, step, dbg, dbg_inst);
   else
-    hipLaunchKernelGGL((k_step<T, false>), dim3(nseg_launch), dim3(NTHREADS), 0, s, parity, segs, inst, buf, drops,
-                       part, mask, step, dbg, dbg_inst);
+    hipLaunchKernelGGL((k_step<T, P, false>), dim3(nseg_launch), dim3(NTHREADS), 0, s, parity, segs, inst, buf,
+                       drops, part, mask, step, dbg, dbg_inst);
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename P>
 hipError_t launch_wave(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst, T* buf,
                        const DropDev* drops, double* part, uint64_t* mask, const int64_t* step, double* dbg,
                        int dbg_inst) {
   if (nseg_launch <= 0) return hipSuccess;
   if (dbg)
-    hipLaunchKernelGGL((k_wave<T, true>), dim3(nseg_launch), dim3(64), 0, s, parity, segs, inst, buf, drops, part,
-                       mask, step, dbg, dbg_inst);
+    hipLaunchKernelGGL((k_wave<T, P, true>), dim3(nseg_launch), dim3(64), 0, s, parity, segs, inst, buf, drops,
+                       part, mask, step, dbg, dbg_inst);
   else
-    hipLaunchKernelGGL((k_wave<T, false>), dim3(nseg_launch), dim3(64), 0, s, parity, segs, inst, buf, drops, part,
-                       mask, step, dbg, dbg_inst);
+    hipLaunchKernelGGL((k_wave<T, P, false>), dim3(nseg_launch), dim3(64), 0, s, parity, segs, inst, buf, drops,
+                       part, mask, step, dbg, dbg_inst);
   return hipGetLastError();
 }
 
-#define LBM_INSTANTIATE(T)                                                                                \
-  template hipError_t launch_lb<T>(hipStream_t, int, int, int, const TileDev*, const InstDev*, T*,        \
-                                   double*, int);                                                         \
+// Launchers of the kernels that touch only the FP fields (instantiated once per arithmetic type T) and of
+// those that also touch the populations (once per pair T, P of arithmetic and population storage type).
+#define LBM_INSTANTIATE_FIELDS(T)                                                                         \
   template hipError_t launch_fd<T>(hipStream_t, int, int, int, const TileDev*, const InstDev*, T*,        \
                                    const DropDev*, double*, uint64_t*, const int64_t*, double*, int);     \
   template hipError_t launch_cm_partials<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,    \
-                                            const DropDev*, double*, uint64_t*);                          \
-  template hipError_t launch_obs<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,            \
-                                    const DropDev*, double*, int);                                        \
-  template hipError_t launch_step<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*, const DropDev*,  \
-                                     double*, uint64_t*, const int64_t*, double*, int); \
-  template hipError_t launch_wave<T>(hipStream_t, int, int, const TileDev*, const InstDev*, T*, const DropDev*,  \
-                                     double*, uint64_t*, const int64_t*, double*, int);
-
+                                            const DropDev*, double*, uint64_t*);
+#define LBM_INSTANTIATE_POPS(T, P)                                                                        \
+  template hipError_t launch_lb<T, P>(hipStream_t, int, int, int, const TileDev*, const InstDev*, T*,     \
+                                      double*, int);                                                      \
+  template hipError_t launch_obs<T, P>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,         \
+                                       const DropDev*, double*, int);                                     \
+  template hipError_t launch_step<T, P>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,        \
+                                        const DropDev*, double*, uint64_t*, const int64_t*, double*, int); \
+  template hipError_t launch_wave<T, P>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,        \
+                                        const DropDev*, double*, uint64_t*, const int64_t*, double*, int);
 
 }  // namespace lbm

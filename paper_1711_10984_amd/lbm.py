@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBM_LIBRARY", os.path.join(_HERE, "liblbm.so"))
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
-LBM_FP64, LBM_FP32 = 0, 1
+LBM_FP64, LBM_FP32, LBM_FP16 = 0, 1, 2
 LBM_ADV_PAPER, LBM_ADV_FLUX = 0, 1
 LBM_PATH_FUSED, LBM_PATH_SPLIT, LBM_PATH_WAVE = 0, 1, 2
 LBM_MAXDROP = 256

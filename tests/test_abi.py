@@ -64,6 +64,9 @@ def test_workspace_bytes_scales_with_lattice():
     b64 = lbm.lbm_workspace_bytes([lbm.make_config(dict(nx=2048, ny=2048), lbm.LBM_FP64)], [64])
     b32 = lbm.lbm_workspace_bytes([lbm.make_config(dict(nx=2048, ny=2048), lbm.LBM_FP32)], [64])
     assert 0.5 < b32 / b64 < 0.6
+    # FP16 population storage: 9 x 2 B + 7 x 4 B per node in the pool instead of 25 x 4 B
+    b16 = lbm.lbm_workspace_bytes([lbm.make_config(dict(nx=2048, ny=2048), lbm.LBM_FP16)], [64])
+    assert 0.6 < b16 / b32 < 0.75
     # a batch needs the sum
     bb = lbm.lbm_workspace_bytes([_cfg(nx=256, ny=256), _cfg(nx=100, ny=37)], [2, 0])
     assert bb > b1
@@ -113,3 +116,9 @@ def test_kernel_names():
     lbm = _lbm()
     assert [lbm.lbm_kernel_name(lbm.LBM_PATH_SPLIT, i) for i in range(3)] == ["k_lb", "k_fd", "k_reduce"]
     assert [lbm.lbm_kernel_name(lbm.LBM_PATH_FUSED, i) for i in range(3)] == ["k_step", "k_reduce", ""]
+
+
+def test_unknown_precision_rejected():
+    lbm = _lbm()
+    with pytest.raises(lbm.LBMError, match="precision must be"):
+        lbm.lbm_workspace_bytes([lbm.make_config(dict(nx=16, ny=16), 3)], [0])
