@@ -52,6 +52,16 @@ extern "C" {
 #define LBM_FP16 2 /* populations stored as FP16 deviations f_i - w_i n0 from the rest state (round to
                       nearest even), widened to FP32 on load; fields and arithmetic FP32; sums FP64 */
 
+/* Boundaries in y (Sec. 2.2 names bounding walls, Sec. 2.3 neutral wetting at them).  LBM_WALLS_Y:
+ * solid plates halfway between node rows, at y = -1/2 and y = ny - 1/2, x periodic.  Populations that
+ * stream into a plate return to their node in the opposite direction (halfway bounce-back, no-slip);
+ * every scalar field entering a stencil is continued across a plate by its mirror image (neutral
+ * wetting, n.grad phi = 0, and no diffusive flux through the plate, n.grad mu_phi = n.grad mu_c = 0);
+ * the advection stencil sees the mirrored velocity with u_y reversed (no flow through the plate);
+ * droplet distances and centres are not periodic in y. */
+#define LBM_WALLS_NONE 0
+#define LBM_WALLS_Y 1
+
 #define LBM_ADV_PAPER 0 /* advection half-step of Eqs. (16)-(17) as printed */
 #define LBM_ADV_FLUX 1  /* conservative face-upwind flux form of the same half-step */
 
@@ -64,9 +74,11 @@ extern "C" {
 
 /* Per-instance model parameters (lattice units). */
 typedef struct lbm_config {
-  int32_t nx, ny;     /* periodic lattice, nx, ny >= 3 */
+  int32_t nx, ny;     /* lattice, nx, ny >= 3; periodic in x, and in y without walls */
   int32_t precision;  /* LBM_FP64, LBM_FP32 or LBM_FP16; equal for every instance of a batch */
   int32_t advection;  /* LBM_ADV_PAPER or LBM_ADV_FLUX */
+  int32_t walls;      /* LBM_WALLS_NONE or LBM_WALLS_Y */
+  int32_t reserved;   /* 0 */
   double tau;         /* BGK relaxation time, > 1/2; viscosity (tau - 1/2)/3 (Eq. 15) */
   double n0;          /* initial fluid density (populations w_i n0 when none are given) */
   double a, b;        /* bulk free energy a phi^2/2 + b phi^4/4, b > 0 (Eq. 1) */

@@ -38,6 +38,18 @@
  *    distance; consumption -gamma (c^{n+1/2} - c0) with constant c0.
  *  - Centre of mass (Sec. 4): over nodes with phi >= 0, each node assigned to
  *    the nearest previous centre (minimum image), offsets unwrapped about it.
+ *  - Bounding walls (optional, walls = 1; Sec. 2.2 defers their implementation
+ *    to a reference not reproduced, Sec. 2.3 fixes neutral wetting): solid
+ *    plates halfway between node rows, at y = -1/2 and y = ny - 1/2; x stays
+ *    periodic.  Populations: halfway bounce-back, a population streamed into a
+ *    plate returns to its node in the opposite direction.  Every scalar field
+ *    that enters a stencil (phi, c, mu, X and their half-step counterparts, M)
+ *    is continued across a plate by its mirror image, g(x, -1) = g(x, 0) and
+ *    g(x, ny) = g(x, ny - 1): this is n.grad(phi) = 0 (neutral wetting) and,
+ *    link by link, zero diffusive flux through the plate (n.grad mu_phi =
+ *    n.grad mu_c = 0).  In the advection stencil the ghost velocity is the
+ *    mirror image with u_y reversed (no flow through the plate).  Droplet
+ *    distances and centres are not periodic in y.
  */
 #include <math.h>
 #include <stdint.h>
@@ -49,7 +61,7 @@
 typedef struct {
   int32_t nx, ny;
   int32_t advection; /* 0: Eqs. (16)-(17) as printed; 1: conservative face-upwind flux form */
-  int32_t reserved;
+  int32_t walls;     /* 0: periodic in y; 1: plates at y = -1/2 and y = ny - 1/2 */
   double tau, n0;
   double a, b, B0, B1, D, Gamma;
   double gamma, A0, t_star, c0;
@@ -72,6 +84,7 @@ typedef struct {
 /* D2Q9 links: rest, E, N, W, S, NE, NW, SW, SE (Sec. 2.2). */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6}; /* e_OPP[i] = -e_i */
 static const double W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
@@ -100,6 +113,17 @@ static inline int wrapi(int i, int n) {
 static inline size_t idx(const orc_params* p, int x, int y) {
   return (size_t)wrapi(y, p->ny) * (size_t)p->nx + (size_t)wrapi(x, p->nx);
 }
+/* Neighbour of a scalar field in a stencil: periodic in x; in y periodic, or with walls the mirror
+   image across the plate (row -1 reads row 0, row ny reads row ny - 1). */
+static inline size_t idxs(const orc_params* p, int x, int y) {
+  if (p->walls) {
+    if (y < 0) y = -1 - y;
+    if (y >= p->ny) y = 2 * p->ny - 1 - y;
+  }
+  return idx(p, x, y);
+}
+/* Period of the y coordinate for droplet distances and centres (none with walls). */
+static inline double yperiod(const orc_params* p) { return p->walls ? INFINITY : (double)p->ny; }
 
 /* Minimum-image offset for a coordinate difference on a ring of length L. */
 static double minimg(double d, double L) {
@@ -108,6 +132,7 @@ static double minimg(double d, double L) {
   return d;
 }
 static double wrapd(double v, double L) {
+  if (isinf(L)) return v;
   double r = fmod(v, L);
   if (r < 0.0) r += L;
   if (r >= L) r -= L;
@@ -120,11 +145,11 @@ static void grad9(const orc_params* p, const double* g, double* gx, double* gy) 
 #pragma omp parallel for schedule(static) if (PAR(p))
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
-      double E = g[idx(p, x + 1, y)], Wv = g[idx(p, x - 1, y)];
-      double N = g[idx(p, x, y + 1)], S = g[idx(p, x, y - 1)];
-      double NE = g[idx(p, x + 1, y + 1)], NW = g[idx(p, x - 1, y + 1)];
-      double SW = g[idx(p, x - 1, y - 1)], SE = g[idx(p, x + 1, y - 1)];
-      size_t k = idx(p, x, y);
+      double E = g[idxs(p, x + 1, y)], Wv = g[idxs(p, x - 1, y)];
+      double N = g[idxs(p, x, y + 1)], S = g[idxs(p, x, y - 1)];
+      double NE = g[idxs(p, x + 1, y + 1)], NW = g[idxs(p, x - 1, y + 1)];
+      double SW = g[idxs(p, x - 1, y - 1)], SE = g[idxs(p, x + 1, y - 1)];
+      size_t k = idxs(p, x, y);
       gx[k] = (4.0 * (E - Wv) + ((NE - NW) + (SE - SW))) * (1.0 / 12.0);
       gy[k] = (4.0 * (N - S) + ((NE - SE) + (NW - SW))) * (1.0 / 12.0);
     }
@@ -135,11 +160,11 @@ static void lap9(const orc_params* p, const double* g, double* out) {
 #pragma omp parallel for schedule(static) if (PAR(p))
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
-      double E = g[idx(p, x + 1, y)], Wv = g[idx(p, x - 1, y)];
-      double N = g[idx(p, x, y + 1)], S = g[idx(p, x, y - 1)];
-      double NE = g[idx(p, x + 1, y + 1)], NW = g[idx(p, x - 1, y + 1)];
-      double SW = g[idx(p, x - 1, y - 1)], SE = g[idx(p, x + 1, y - 1)];
-      size_t k = idx(p, x, y);
+      double E = g[idxs(p, x + 1, y)], Wv = g[idxs(p, x - 1, y)];
+      double N = g[idxs(p, x, y + 1)], S = g[idxs(p, x, y - 1)];
+      double NE = g[idxs(p, x + 1, y + 1)], NW = g[idxs(p, x - 1, y + 1)];
+      double SW = g[idxs(p, x - 1, y - 1)], SE = g[idxs(p, x + 1, y - 1)];
+      size_t k = idxs(p, x, y);
       out[k] = (4.0 * ((E + Wv) + (N + S)) + ((NE + NW) + (SE + SW)) - 20.0 * g[k]) * (1.0 / 6.0);
     }
 }
@@ -150,11 +175,11 @@ static void div9(const orc_params* p, const double* kf, const double* X, double*
 #pragma omp parallel for schedule(static) if (PAR(p))
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
-      size_t k0 = idx(p, x, y);
+      size_t k0 = idxs(p, x, y);
       double kc = kf[k0], Xc = X[k0];
       double t[9];
       for (int i = 1; i < 9; ++i) {
-        size_t ki = idx(p, x + EX[i], y + EY[i]);
+        size_t ki = idxs(p, x + EX[i], y + EY[i]);
         t[i] = (kc + kf[ki]) * (X[ki] - Xc);
       }
       /* axis links weigh 4/12, diagonal links 1/12 */
@@ -168,7 +193,7 @@ static int nearest_drop(const orc_sim* s, double x, double y) {
   double bd = 0.0;
   for (int k = 0; k < s->ndrop; ++k) {
     double dx = minimg(x - s->drop[k].x, (double)s->p.nx);
-    double dy = minimg(y - s->drop[k].y, (double)s->p.ny);
+    double dy = minimg(y - s->drop[k].y, yperiod(&s->p));
     double d2 = dx * dx + dy * dy;
     if (best < 0 || d2 < bd) {
       best = k;
@@ -190,7 +215,7 @@ static void update_centres(orc_sim* s, const double* phi) {
       int k = nearest_drop(s, (double)x, (double)y);
       if (k < 0) continue;
       double dx = minimg((double)x - s->drop[k].x, (double)p->nx);
-      double dy = minimg((double)y - s->drop[k].y, (double)p->ny);
+      double dy = minimg((double)y - s->drop[k].y, yperiod(p));
       sw[k] += v;
       sx[k] += v * dx;
       sy[k] += v * dy;
@@ -198,7 +223,7 @@ static void update_centres(orc_sim* s, const double* phi) {
   for (int k = 0; k < s->ndrop; ++k) {
     if (sw[k] > 0.0) {
       s->drop[k].x = wrapd(s->drop[k].x + sx[k] / sw[k], (double)p->nx);
-      s->drop[k].y = wrapd(s->drop[k].y + sy[k] / sw[k], (double)p->ny);
+      s->drop[k].y = wrapd(s->drop[k].y + sy[k] / sw[k], yperiod(p));
     }
   }
 }
@@ -212,7 +237,7 @@ static int source_count(const orc_sim* s, int x, int y) {
     double px = d->x + (d->R - d->Rs) * d->ex;
     double py = d->y + (d->R - d->Rs) * d->ey;
     double dx = minimg((double)x - px, (double)s->p.nx);
-    double dy = minimg((double)y - py, (double)s->p.ny);
+    double dy = minimg((double)y - py, yperiod(&s->p));
     if (dx * dx + dy * dy <= d->Rs * d->Rs) ++cnt;
   }
   return cnt;
@@ -281,19 +306,22 @@ static void advect(const orc_params* p, const double* g, const double* ux, const
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x) {
       size_t k = idx(p, x, y);
-      size_t kE = idx(p, x + 1, y), kW = idx(p, x - 1, y);
-      size_t kN = idx(p, x, y + 1), kS = idx(p, x, y - 1);
+      size_t kE = idxs(p, x + 1, y), kW = idxs(p, x - 1, y);
+      size_t kN = idxs(p, x, y + 1), kS = idxs(p, x, y - 1);
       double gc = g[k];
+      /* y-velocity of the neighbours; across a plate the mirror image with the sign reversed */
+      double uyN = (p->walls && y == p->ny - 1) ? -uy[kN] : uy[kN];
+      double uyS = (p->walls && y == 0) ? -uy[kS] : uy[kS];
       if (p->advection == 0) {
         /* centred velocity divergence, upwind concentration gradient */
-        double divu = 0.5 * (ux[kE] - ux[kW]) + 0.5 * (uy[kN] - uy[kS]);
+        double divu = 0.5 * (ux[kE] - ux[kW]) + 0.5 * (uyN - uyS);
         double dgx = ux[k] > 0.0 ? gc - g[kW] : g[kE] - gc;
         double dgy = uy[k] > 0.0 ? gc - g[kS] : g[kN] - gc;
         out[k] = gc - ((gc * divu + ux[k] * dgx) + uy[k] * dgy);
       } else {
         /* conservative form: face velocity = mean of the two nodes, upwind face value */
         double uxr = 0.5 * (ux[k] + ux[kE]), uxl = 0.5 * (ux[kW] + ux[k]);
-        double uyt = 0.5 * (uy[k] + uy[kN]), uyb = 0.5 * (uy[kS] + uy[k]);
+        double uyt = 0.5 * (uy[k] + uyN), uyb = 0.5 * (uyS + uy[k]);
         double Fr = uxr * (uxr >= 0.0 ? gc : g[kE]);
         double Fl = uxl * (uxl >= 0.0 ? g[kW] : gc);
         double Ft = uyt * (uyt >= 0.0 ? gc : g[kN]);
@@ -352,12 +380,18 @@ static void do_step(orc_sim* s, double* st) {
       fstar[(size_t)i * N + k] = (fi - omega * (fi - feq)) + Fi;
     }
   }
-  /* S6: streaming f_i(r + e_i, n + 1) = f*_i(r) (Eq. 10) */
+  /* S6: streaming f_i(r + e_i, n + 1) = f*_i(r) (Eq. 10); with walls, a population that would enter a
+     plate is bounced back: f_OPP[i](r, n + 1) = f*_i(r) */
 #pragma omp parallel for schedule(static) if (PAR(p))
   for (int y = 0; y < p->ny; ++y)
     for (int x = 0; x < p->nx; ++x)
-      for (int i = 0; i < 9; ++i)
-        fnew[(size_t)i * N + idx(p, x + EX[i], y + EY[i])] = fstar[(size_t)i * N + idx(p, x, y)];
+      for (int i = 0; i < 9; ++i) {
+        int yy = y + EY[i];
+        if (p->walls && (yy < 0 || yy >= p->ny))
+          fnew[(size_t)OPP[i] * N + idx(p, x, y)] = fstar[(size_t)i * N + idx(p, x, y)];
+        else
+          fnew[(size_t)i * N + idx(p, x + EX[i], yy)] = fstar[(size_t)i * N + idx(p, x, y)];
+      }
 
   /* S7: Euler advection half-step with u^n (Eqs. 16-17) */
   advect(p, s->phi, ux, uy, ph);

@@ -27,7 +27,7 @@ STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "p
 
 
 class _Params(C.Structure):
-    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("advection", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("advection", C.c_int32), ("walls", C.c_int32),
                 ("tau", C.c_double), ("n0", C.c_double),
                 ("a", C.c_double), ("b", C.c_double), ("B0", C.c_double), ("B1", C.c_double),
                 ("D", C.c_double), ("Gamma", C.c_double),
@@ -62,6 +62,7 @@ class Params:
     t_star: float = 2.0e6
     c0: float = 0.0
     advection: int = 0  # 0: Eqs. (16)-(17) as printed, 1: conservative flux form
+    walls: int = 0  # 0: periodic in y, 1: plates at y = -1/2 and y = ny - 1/2
 
 
 @dataclass
@@ -110,13 +111,13 @@ def _ptr(a: Optional[np.ndarray]):
 
 def _c_params(p: Params) -> _Params:
     d = asdict(p)
-    return _Params(nx=d["nx"], ny=d["ny"], advection=d["advection"], reserved=0, tau=d["tau"], n0=d["n0"],
+    return _Params(nx=d["nx"], ny=d["ny"], advection=d["advection"], walls=d["walls"], tau=d["tau"], n0=d["n0"],
                    a=d["a"], b=d["b"], B0=d["B0"], B1=d["B1"], D=d["D"], Gamma=d["Gamma"], gamma=d["gamma"],
                    A0=d["A0"], t_star=d["t_star"], c0=d["c0"])
 
 
 class OracleSim:
-    """One periodic lattice advanced by the oracle."""
+    """One lattice (periodic, or bounded by plates in y) advanced by the oracle."""
 
     def __init__(self, p: Params, phi0: np.ndarray, c0: np.ndarray, drops: Sequence[Drop] = (),
                  f_pre: Optional[np.ndarray] = None, step: int = 0):

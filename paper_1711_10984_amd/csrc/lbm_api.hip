@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -38,6 +39,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // D2Q9 directions in the public order rest, E, N, W, S, NE, NW, SW, SE.
 constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};  // e_OPP[k] = -e_k
 constexpr double WGT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
@@ -68,6 +70,8 @@ int validate(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop) {
     if (c.precision != cfgs[0].precision) return fail(LBM_E_INVAL, "all instances of a batch need the same precision");
     if (c.advection != LBM_ADV_PAPER && c.advection != LBM_ADV_FLUX)
       return fail(LBM_E_INVAL, std::string(where) + "unknown advection scheme");
+    if (c.walls != LBM_WALLS_NONE && c.walls != LBM_WALLS_Y)
+      return fail(LBM_E_INVAL, std::string(where) + "walls must be LBM_WALLS_NONE or LBM_WALLS_Y");
     if (!(c.tau > 0.5)) return fail(LBM_E_INVAL, std::string(where) + "tau must exceed 1/2");
     if (!(c.b > 0.0)) return fail(LBM_E_INVAL, std::string(where) + "b must be positive");
     if (!(c.n0 > 0.0)) return fail(LBM_E_INVAL, std::string(where) + "n0 must be positive");
@@ -123,6 +127,8 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.part_base[TILING_FUSED] = part_elems1;
     part_elems1 += (int64_t)d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED] * d.ndrop * 3;
     d.advection = c.advection;
+    d.walls = c.walls;
+    d.yper = c.walls ? std::numeric_limits<double>::infinity() : (double)c.ny;
     d.a = c.a;
     d.b = c.b;
     d.B0 = c.B0;
@@ -355,15 +361,22 @@ int upload_instance(lbm_ctx* c, int i, const double* phi0, const double* c0, con
   to_device_layout(c0, h.data(), nx, ny, pitch);
   HIPCHK(hipMemcpyAsync(base + d.off_c[0], h.data(), plane * sizeof(T), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  // Stored populations are post-collision values at the emitting node: f*_i(r) = f_i(r + e_i).
+  // Stored populations are post-collision values at the emitting node: f*_i(r) = f_i(r + e_i); with walls,
+  // a population streamed into a plate comes back to r reversed: f*_i(r) = f_OPP[i](r).
   P* fbase = reinterpret_cast<P*>(base + d.off_f[0]);
+  const bool walls = c->cfg[i].walls != 0;
   for (int k = 0; k < 9; ++k)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         double v;
         if (f_pre) {
-          const int xs = (x + EX[k] + nx) % nx, ys = (y + EY[k] + ny) % ny;
-          v = f_pre[(size_t)k * nx * ny + (size_t)ys * nx + xs];
+          const int yt = y + EY[k];
+          if (walls && (yt < 0 || yt >= ny)) {
+            v = f_pre[(size_t)OPP[k] * nx * ny + (size_t)y * nx + x];
+          } else {
+            const int xs = (x + EX[k] + nx) % nx, ys = (yt + ny) % ny;
+            v = f_pre[(size_t)k * nx * ny + (size_t)ys * nx + xs];
+          }
         } else {
           v = WGT[k] * c->cfg[i].n0;
         }
@@ -428,13 +441,20 @@ int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, do
                           9 * plane * sizeof(P), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     const int nx = d.nx, ny = d.ny;
+    const bool walls = d.walls != 0;
     for (int k = 0; k < 9; ++k)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
-          // pre-collision f_k(r) = f*_k(r - e_k)
-          const int xs = (x - EX[k] + nx) % nx, ys = (y - EY[k] + ny) % ny;
-          f_pre[(size_t)k * nx * ny + (size_t)y * nx + x] =
-              host_pop_load<T, P>(h[(size_t)k * plane + (size_t)ys * d.pitch + xs], WGT[k] * c->cfg[inst].n0);
+          // pre-collision f_k(r) = f*_k(r - e_k), or with walls f*_OPP[k](r) when r - e_k is behind a plate
+          const int yf = y - EY[k];
+          size_t src;
+          if (walls && (yf < 0 || yf >= ny)) {
+            src = (size_t)OPP[k] * plane + (size_t)y * d.pitch + x;
+          } else {
+            const int xs = (x - EX[k] + nx) % nx, ys = (yf + ny) % ny;
+            src = (size_t)k * plane + (size_t)ys * d.pitch + xs;
+          }
+          f_pre[(size_t)k * nx * ny + (size_t)y * nx + x] = host_pop_load<T, P>(h[src], WGT[k] * c->cfg[inst].n0);
         }
   }
   return LBM_OK;

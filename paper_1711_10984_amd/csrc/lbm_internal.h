@@ -42,7 +42,8 @@ struct InstDev {
   int64_t off_c[2];    // the two c buffers
   int64_t off_ux, off_uy, off_n;  // velocity planes written by the LB kernel; density (diagnostics)
   int64_t part_base[2];  // per tiling: offset (doubles) of the centre-of-mass partials [tiles][ndrop][3]
-  int32_t advection, pad0;
+  int32_t advection, walls;  // walls: LBM_WALLS_NONE or LBM_WALLS_Y
+  double yper;                // period of y in droplet distances and centres: ny, or infinite with walls
   // model parameters, derived on the host in double precision
   double a, b, B0, B1, halfB1, D, Gamma, gamma, c0, omega, coef, A0, t_star;
   double wn[3];  // rest populations w_i n0 of the three weight classes (centre, axis, diagonal)

@@ -70,6 +70,16 @@ __device__ __forceinline__ int wrap_near(int v, int n) {
   return wrap_idx(v, n);
 }
 
+// Row read for row index r (within one lattice height of [0, ny)): periodic wrap, or with walls the
+// mirror image across the plates at y = -1/2 and y = ny - 1/2 (row -1 reads row 0, row ny reads ny - 1).
+__device__ __forceinline__ int row_of(int r, int ny, int walls) {
+  if (!walls) return wrap_near(r, ny);
+  const int p = 2 * ny;
+  int m = r % p;
+  if (m < 0) m += p;
+  return m < ny ? m : p - 1 - m;
+}
+
 __device__ __forceinline__ double minimg(double d, double L) {
   if (d >= 0.5 * L) return d - L;
   if (d < -0.5 * L) return d + L;
@@ -77,6 +87,7 @@ __device__ __forceinline__ double minimg(double d, double L) {
 }
 
 __device__ __forceinline__ double wrapd(double v, double L) {
+  if (isinf(L)) return v;  // not periodic (y with walls)
   double r = fmod(v, L);
   if (r < 0.0) r += L;
   if (r >= L) r -= L;
@@ -192,7 +203,7 @@ __device__ void cull_droplets(const InstDev& I, const DropDev* __restrict__ drop
                               int by0, int by1, DropShared& sh) {
   const int tid = threadIdx.x;
   const int nd = I.ndrop;
-  const double Lx = I.nx, Ly = I.ny;
+  const double Lx = I.nx, Ly = I.yper;
   const double xm = 0.5 * (bx0 + bx1), ym = 0.5 * (by0 + by1);
   const double hx = 0.5 * (bx1 - bx0), hy = 0.5 * (by1 - by0);
   double my_min_max = 1e300;
@@ -236,7 +247,7 @@ __device__ __forceinline__ int nearest_drop(const InstDev& I, const DropDev* __r
     const int k = sh.near_list[j];
     const DropDev d = drops[I.drop_base + k];
     const double dx = minimg(x - d.x, (double)I.nx);
-    const double dy = minimg(y - d.y, (double)I.ny);
+    const double dy = minimg(y - d.y, I.yper);
     const double d2 = dx * dx + dy * dy;
     if (best < 0 || d2 < bd) {
       best = k;
@@ -255,7 +266,7 @@ __device__ __forceinline__ int source_count(const InstDev& I, const DropDev* __r
     const double px = d.x + (d.R - d.Rs) * d.ex;
     const double py = d.y + (d.R - d.Rs) * d.ey;
     const double dx = minimg(x - px, (double)I.nx);
-    const double dy = minimg(y - py, (double)I.ny);
+    const double dy = minimg(y - py, I.yper);
     if (dx * dx + dy * dy <= d.Rs * d.Rs) ++cnt;
   }
   return cnt;
@@ -327,7 +338,7 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
   const T wr0 = T(I.wn[0]), wr1 = T(I.wn[1]), wr5 = T(I.wn[2]);
 
   for (int i = tid; i < W2; i += NTHREADS) s_col[i] = wrap_idx(td.x0 + i - 2, nx);
-  for (int i = tid; i < H2; i += NTHREADS) s_row[i] = wrap_idx(td.y0 + i - 2, ny);
+  for (int i = tid; i < H2; i += NTHREADS) s_row[i] = row_of(td.y0 + i - 2, ny, I.walls);
   __syncthreads();
   for (int idx = tid; idx < W2 * H2; idx += NTHREADS) {
     const int ly = idx / W2, lx = idx - ly * W2;
@@ -375,15 +386,17 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const int64_t r0 = (int64_t)y * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
+    // with walls, the populations that would come from behind a plate are the node's own, bounced back
+    const bool bb0 = I.walls && y == 0, bbn = I.walls && y == ny - 1;
     const T f0 = pop_ld<T>(fin[r0 + x], wr0);
     const T f1 = pop_ld<T>(fin[plane + r0 + xm], wr1);
-    const T f2 = pop_ld<T>(fin[2 * plane + rm + x], wr1);
+    const T f2 = pop_ld<T>(bb0 ? fin[4 * plane + r0 + x] : fin[2 * plane + rm + x], wr1);
     const T f3 = pop_ld<T>(fin[3 * plane + r0 + xp], wr1);
-    const T f4 = pop_ld<T>(fin[4 * plane + rp + x], wr1);
-    const T f5 = pop_ld<T>(fin[5 * plane + rm + xm], wr5);
-    const T f6 = pop_ld<T>(fin[6 * plane + rm + xp], wr5);
-    const T f7 = pop_ld<T>(fin[7 * plane + rp + xp], wr5);
-    const T f8 = pop_ld<T>(fin[8 * plane + rp + xm], wr5);
+    const T f4 = pop_ld<T>(bbn ? fin[2 * plane + r0 + x] : fin[4 * plane + rp + x], wr1);
+    const T f5 = pop_ld<T>(bb0 ? fin[7 * plane + r0 + x] : fin[5 * plane + rm + xm], wr5);
+    const T f6 = pop_ld<T>(bb0 ? fin[8 * plane + r0 + x] : fin[6 * plane + rm + xp], wr5);
+    const T f7 = pop_ld<T>(bbn ? fin[5 * plane + r0 + x] : fin[7 * plane + rp + xp], wr5);
+    const T f8 = pop_ld<T>(bbn ? fin[6 * plane + r0 + x] : fin[8 * plane + rp + xm], wr5);
     const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
     const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
     const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
@@ -466,7 +479,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fd(int parity, const TileDev* __re
   T* __restrict__ c_out = buf + I.off_c[parity ^ 1];
 
   for (int i = tid; i < W3; i += NTHREADS) s_col[i] = wrap_idx(td.x0 + i - 3, nx);
-  for (int i = tid; i < H3; i += NTHREADS) s_row[i] = wrap_idx(td.y0 + i - 3, ny);
+  for (int i = tid; i < H3; i += NTHREADS) s_row[i] = row_of(td.y0 + i - 3, ny, I.walls);
   __syncthreads();
   for (int idx = tid; idx < W3 * H3; idx += NTHREADS) {
     const int ly = idx / W3, lx = idx - ly * W3;
@@ -474,7 +487,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fd(int parity, const TileDev* __re
     s_phi[idx] = phi[g];
     s_c[idx] = cc[g];
     s_ux[idx] = gux[g];
-    s_uy[idx] = guy[g];
+    // across a plate the ghost velocity is the mirror image with u_y reversed
+    const int ry = td.y0 + ly - 3;
+    s_uy[idx] = (I.walls && (ry < 0 || ry >= ny)) ? -guy[g] : guy[g];
   }
   __syncthreads();
 
@@ -543,7 +558,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fd(int parity, const TileDev* __re
       kd[j] = k;
       vv[j] = v;
       vx[j] = v * minimg((double)x - d.x, (double)nx);
-      vy[j] = v * minimg((double)y - d.y, (double)ny);
+      vy[j] = v * minimg((double)y - d.y, I.yper);
     }
     if (MODE == 1) {
       const int64_t q = (int64_t)y * nx + x;
@@ -592,7 +607,7 @@ __global__ __launch_bounds__(NTHREADS) void k_cm_partials(int parity, const Tile
       kd[j] = k;
       vv[j] = v;
       vx[j] = v * minimg((double)x - d.x, (double)nx);
-      vy[j] = v * minimg((double)y - d.y, (double)ny);
+      vy[j] = v * minimg((double)y - d.y, I.yper);
     }
   }
   tile_cm_sums(I, td.t - I.tile_base[TILING_SPLIT], td.t, kd, vv, vx, vy, sh, part, mask);
@@ -630,7 +645,7 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(int tiling, int ndrop_total
   const double s2 = block_reduce(a2, red, OpAdd());
   if (threadIdx.x == 0 && s0 > 0.0) {
     drops[g].x = wrapd(d.x + s1 / s0, (double)I.nx);
-    drops[g].y = wrapd(d.y + s2 / s0, (double)I.ny);
+    drops[g].y = wrapd(d.y + s2 / s0, I.yper);
   }
 }
 
@@ -774,24 +789,23 @@ __device__ __forceinline__ T div9r(const T* cu, const T* cm, const T* cd, T D, c
   return (T(4) * ((t1 + t3) + (t2 + t4)) + ((t5 + t6) + (t7 + t8))) * cst<T>(1.0 / 12.0);
 }
 
+// Advection half-step of Eqs. (16)-(17) at one lane: scalar g (centre, east, west, north, south),
+// velocity x-component at the centre and its east/west neighbours, y-component at the centre and its
+// north/south neighbours.
 template <typename T>
-__device__ __forceinline__ T advect_r(const T* gu, const T* gm, const T* gd, const T* xu, const T* xm,
-                                      const T* xd, const T* yu, const T* ym, const T* yd, int l, int mode) {
-  // xm/ym: velocity rows (x and y components) at row r; xu.. at r+1, xd.. at r-1
-  const T gc = gm[l];
+__device__ __forceinline__ T advect_n(T gc, T ge, T gw, T gn, T gs, T uc, T ue, T uw, T vc, T vn, T vs, int mode) {
   if (mode == 0) {
-    const T divu = T(0.5) * (xm[l + 1] - xm[l - 1]) + T(0.5) * (yu[l] - yd[l]);
-    const T u = xm[l], v = ym[l];
-    const T dgx = u > T(0) ? gc - gm[l - 1] : gm[l + 1] - gc;
-    const T dgy = v > T(0) ? gc - gd[l] : gu[l] - gc;
-    return gc - ((gc * divu + u * dgx) + v * dgy);
+    const T divu = T(0.5) * (ue - uw) + T(0.5) * (vn - vs);
+    const T dgx = uc > T(0) ? gc - gw : ge - gc;
+    const T dgy = vc > T(0) ? gc - gs : gn - gc;
+    return gc - ((gc * divu + uc * dgx) + vc * dgy);
   }
-  const T uxr = T(0.5) * (xm[l] + xm[l + 1]), uxl = T(0.5) * (xm[l - 1] + xm[l]);
-  const T uyt = T(0.5) * (ym[l] + yu[l]), uyb = T(0.5) * (yd[l] + ym[l]);
-  const T Fr = uxr * (uxr >= T(0) ? gc : gm[l + 1]);
-  const T Fl = uxl * (uxl >= T(0) ? gm[l - 1] : gc);
-  const T Ft = uyt * (uyt >= T(0) ? gc : gu[l]);
-  const T Fb = uyb * (uyb >= T(0) ? gd[l] : gc);
+  const T uxr = T(0.5) * (uc + ue), uxl = T(0.5) * (uw + uc);
+  const T uyt = T(0.5) * (vc + vn), uyb = T(0.5) * (vs + vc);
+  const T Fr = uxr * (uxr >= T(0) ? gc : ge);
+  const T Fl = uxl * (uxl >= T(0) ? gw : gc);
+  const T Ft = uyt * (uyt >= T(0) ? gc : gn);
+  const T Fb = uyb * (uyb >= T(0) ? gs : gc);
   return gc - ((Fr - Fl) + (Ft - Fb));
 }
 
@@ -857,7 +871,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
 
   // --- droplet culling for the owned box [x0, xend) x [y0, yend); thread k handles droplet k
   if (nd > 0) {
-    const double Lx = nx, Ly = ny;
+    const double Lx = nx, Ly = I.yper;
     const double xm = 0.5 * (x0 + xend - 1), ym = 0.5 * (y0 + yend - 1);
     const double hx = 0.5 * (xend - 1 - x0), hy = 0.5 * (yend - 1 - y0);
     double maxd2 = 1e300, mind2 = 1e300;
@@ -912,10 +926,11 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   T pf_phi = T(0), pf_c = T(0);
   P pf[9];
   for (int i = 0; i < 9; ++i) pf[i] = P(0);
+  const int walls = I.walls;
   auto load_s0 = [&](int it) {
     const int r = y0 - 5 + it * FUSED_R + wv;
     if (r < yend + 5) {
-      const int gy = wrap_near(r, ny);
+      const int gy = row_of(r, ny, walls);
       const int64_t o = (int64_t)gy * pitch + gx;
       pf_phi = phi_in[o];
       pf_c = c_in[o];
@@ -924,18 +939,19 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   auto load_s2 = [&](int it) {
     const int r = y0 - 5 + it * FUSED_R + wv - 2;
     if (l2 && r >= y0 - 3 && r < yend + 3) {
-      const int gy = wrap_near(r, ny);
-      const int gym = gy == 0 ? ny - 1 : gy - 1, gyp = gy == ny - 1 ? 0 : gy + 1;
+      const int gy = row_of(r, ny, walls), gym = row_of(r - 1, ny, walls), gyp = row_of(r + 1, ny, walls);
       const int64_t r0 = (int64_t)gy * pitch, rm = (int64_t)gym * pitch, rp = (int64_t)gyp * pitch;
+      // behind a plate: the node's own opposite population (halfway bounce-back)
+      const bool bb0 = walls && r == 0, bbn = walls && r == ny - 1;
       pf[0] = fin[r0 + gx];
       pf[1] = fin[plane + r0 + gxm];
-      pf[2] = fin[2 * plane + rm + gx];
+      pf[2] = bb0 ? fin[4 * plane + r0 + gx] : fin[2 * plane + rm + gx];
       pf[3] = fin[3 * plane + r0 + gxp];
-      pf[4] = fin[4 * plane + rp + gx];
-      pf[5] = fin[5 * plane + rm + gxm];
-      pf[6] = fin[6 * plane + rm + gxp];
-      pf[7] = fin[7 * plane + rp + gxp];
-      pf[8] = fin[8 * plane + rp + gxm];
+      pf[4] = bbn ? fin[2 * plane + r0 + gx] : fin[4 * plane + rp + gx];
+      pf[5] = bb0 ? fin[7 * plane + r0 + gx] : fin[5 * plane + rm + gxm];
+      pf[6] = bb0 ? fin[8 * plane + r0 + gx] : fin[6 * plane + rm + gxp];
+      pf[7] = bbn ? fin[5 * plane + r0 + gx] : fin[7 * plane + rp + gxp];
+      pf[8] = bbn ? fin[6 * plane + r0 + gx] : fin[8 * plane + rp + gxm];
     }
   };
   load_s0(0);
@@ -1042,10 +1058,14 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
       const int r = q0 - 3 + wv;
       if (l3 && r >= y0 - 2 && r < yend + 2) {
         const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
-        const T ph = advect_r(r_phi[su], r_phi[sm], r_phi[sdn], r_ux[su], r_ux[sm], r_ux[sdn], r_uy[su], r_uy[sm],
-                              r_uy[sdn], lane, adv);
-        const T ch = advect_r(r_c[su], r_c[sm], r_c[sdn], r_ux[su], r_ux[sm], r_ux[sdn], r_uy[su], r_uy[sm],
-                              r_uy[sdn], lane, adv);
+        // u^n beyond a plate is not computed: its mirror image with u_y reversed
+        const T uc = r_ux[sm][lane], ue = r_ux[sm][lane + 1], uw = r_ux[sm][lane - 1], vc = r_uy[sm][lane];
+        const T vn = (walls && r == ny - 1) ? -vc : r_uy[su][lane];
+        const T vs = (walls && r == 0) ? -vc : r_uy[sdn][lane];
+        const T ph = advect_n(r_phi[sm][lane], r_phi[sm][lane + 1], r_phi[sm][lane - 1], r_phi[su][lane],
+                              r_phi[sdn][lane], uc, ue, uw, vc, vn, vs, adv);
+        const T ch = advect_n(r_c[sm][lane], r_c[sm][lane + 1], r_c[sm][lane - 1], r_c[su][lane], r_c[sdn][lane], uc,
+                              ue, uw, vc, vn, vs, adv);
         r_ph[sm][lane] = ph;
         r_ch[sm][lane] = ch;
         if (DBG && own_col && r >= y0 && r < yend) {
@@ -1060,7 +1080,10 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
     {
       const int r = q0 - 4 + wv;
       if (l4 && r >= y0 - 1 && r < yend + 1) {
-        const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
+        // half-step fields beyond a plate: the mirror image of the boundary row
+        const int sm = r & (RING - 1);
+        const int su = (walls && r == ny - 1) ? sm : (r + 1) & (RING - 1);
+        const int sdn = (walls && r == 0) ? sm : (r - 1) & (RING - 1);
         T gphx, gphy, gchx, gchy;
         grad9r(r_ph[su], r_ph[sm], r_ph[sdn], lane, gphx, gphy);
         grad9r(r_ch[su], r_ch[sm], r_ch[sdn], lane, gchx, gchy);
@@ -1085,7 +1108,9 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
     {
       const int r = q0 - 5 + wv;
       if (own_col && r >= y0 && r < yend) {
-        const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
+        const int sm = r & (RING - 1);
+        const int su = (walls && r == ny - 1) ? sm : (r + 1) & (RING - 1);
+        const int sdn = (walls && r == 0) ? sm : (r - 1) & (RING - 1);
         const T phn = r_ph[sm][lane] + Gamma * lap9r(r_M[su], r_M[sm], r_M[sdn], lane);
         const T ch = r_ch[sm][lane];
         const T lch = lap9r(r_ch[su], r_ch[sm], r_ch[sdn], lane);
@@ -1100,7 +1125,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
               m &= m - 1;
               const DropDev d = drops[I.drop_base + k];
               const double px = d.x + (d.R - d.Rs) * d.ex, py = d.y + (d.R - d.Rs) * d.ey;
-              const double dx = minimg(xd - px, (double)nx), dy = minimg(yd - py, (double)ny);
+              const double dx = minimg(xd - px, (double)nx), dy = minimg(yd - py, I.yper);
               if (dx * dx + dy * dy <= d.Rs * d.Rs) ++cnt;
             }
           }
@@ -1126,7 +1151,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
               const int k = w * 64 + __ffsll(m) - 1;
               m &= m - 1;
               const DropDev d = drops[I.drop_base + k];
-              const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, (double)ny);
+              const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, I.yper);
               const double d2 = dx * dx + dy * dy;
               if (best < 0 || d2 < bd) {
                 best = k;
@@ -1138,7 +1163,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
           kd = best;
           cv0 = v;
           cv1 = v * minimg(xd - d.x, (double)nx);
-          cv2 = v * minimg(yd - d.y, (double)ny);
+          cv2 = v * minimg(yd - d.y, I.yper);
         }
       }
     }
@@ -1326,25 +1351,6 @@ __device__ __forceinline__ T div9n(const Nbr<T>& c, const Nbr<T>& X, T D) {
   return (T(4) * ((t1 + t3) + (t2 + t4)) + ((t5 + t6) + (t7 + t8))) * cst<T>(1.0 / 12.0);
 }
 
-// Advection half-step of Eqs. (16)-(17) at one lane: scalar g (centre, east, west, north, south),
-// velocity x-component at the centre and its east/west neighbours, y-component at the centre and its
-// north/south neighbours.
-template <typename T>
-__device__ __forceinline__ T advect_n(T gc, T ge, T gw, T gn, T gs, T uc, T ue, T uw, T vc, T vn, T vs, int mode) {
-  if (mode == 0) {
-    const T divu = T(0.5) * (ue - uw) + T(0.5) * (vn - vs);
-    const T dgx = uc > T(0) ? gc - gw : ge - gc;
-    const T dgy = vc > T(0) ? gc - gs : gn - gc;
-    return gc - ((gc * divu + uc * dgx) + vc * dgy);
-  }
-  const T uxr = T(0.5) * (uc + ue), uxl = T(0.5) * (uw + uc);
-  const T uyt = T(0.5) * (vc + vn), uyb = T(0.5) * (vs + vc);
-  const T Fr = uxr * (uxr >= T(0) ? gc : ge);
-  const T Fl = uxl * (uxl >= T(0) ? gw : gc);
-  const T Ft = uyt * (uyt >= T(0) ? gc : gn);
-  const T Fb = uyb * (uyb >= T(0) ? gs : gc);
-  return gc - ((Fr - Fl) + (Ft - Fb));
-}
 
 template <typename T, typename P, bool DBG>
 // Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD;
@@ -1384,7 +1390,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   unsigned long long near_v = 0ull, src_v = 0ull, seg_v = 0ull;
   bool any_src = false;
   if (nd > 0) {
-    const double Lx = nx, Ly = ny;
+    const double Lx = nx, Ly = I.yper;
     const double xm = 0.5 * (x0 + xend - 1), ym = 0.5 * (y0 + yend - 1);
     const double hx = 0.5 * (xend - 1 - x0), hy = 0.5 * (yend - 1 - y0);
     double mind2[MASK_WORDS];
@@ -1454,24 +1460,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   // Addresses: a wave-uniform row pointer (scalar registers) plus a per-lane 32-bit column byte offset.
   const unsigned bx = (unsigned)gx * sizeof(T);
   const unsigned fx = (unsigned)gx * sizeof(P), fxm = (unsigned)gxm * sizeof(P), fxp = (unsigned)gxp * sizeof(P);
+  const int walls = I.walls;
   auto load_s0 = [&](Pref& p, int r) {
-    const int64_t ro = (int64_t)wrap_near(r, ny) * pitch;
+    const int64_t ro = (int64_t)row_of(r, ny, walls) * pitch;
     p.phi = ld_col(phi_in + ro, bx);
     p.c = ld_col(c_in + ro, bx);
   };
   auto load_s2 = [&](Pref& p, int r) {
-    const int gy = wrap_near(r, ny);
-    const int gym = gy == 0 ? ny - 1 : gy - 1, gyp = gy == ny - 1 ? 0 : gy + 1;
+    const int gy = row_of(r, ny, walls), gym = row_of(r - 1, ny, walls), gyp = row_of(r + 1, ny, walls);
     const int64_t r0 = (int64_t)gy * pitch, rm = (int64_t)gym * pitch, rp = (int64_t)gyp * pitch;
+    // behind a plate: the node's own opposite population (halfway bounce-back)
+    const bool bb0 = walls && r == 0, bbn = walls && r == ny - 1;
     p.f[0] = ld_col(fin + r0, fx);
     p.f[1] = ld_col(fin + plane + r0, fxm);
-    p.f[2] = ld_col(fin + 2 * plane + rm, fx);
+    p.f[2] = bb0 ? ld_col(fin + 4 * plane + r0, fx) : ld_col(fin + 2 * plane + rm, fx);
     p.f[3] = ld_col(fin + 3 * plane + r0, fxp);
-    p.f[4] = ld_col(fin + 4 * plane + rp, fx);
-    p.f[5] = ld_col(fin + 5 * plane + rm, fxm);
-    p.f[6] = ld_col(fin + 6 * plane + rm, fxp);
-    p.f[7] = ld_col(fin + 7 * plane + rp, fxp);
-    p.f[8] = ld_col(fin + 8 * plane + rp, fxm);
+    p.f[4] = bbn ? ld_col(fin + 2 * plane + r0, fx) : ld_col(fin + 4 * plane + rp, fx);
+    p.f[5] = bb0 ? ld_col(fin + 7 * plane + r0, fx) : ld_col(fin + 5 * plane + rm, fxm);
+    p.f[6] = bb0 ? ld_col(fin + 8 * plane + r0, fx) : ld_col(fin + 6 * plane + rm, fxp);
+    p.f[7] = bbn ? ld_col(fin + 5 * plane + r0, fx) : ld_col(fin + 7 * plane + rp, fxp);
+    p.f[8] = bbn ? ld_col(fin + 6 * plane + r0, fx) : ld_col(fin + 8 * plane + rp, fxm);
   };
   // Set j serves the iterations it = j (mod PFD): stage-0 row y0 - 5 + it, stage-2 row y0 - 7 + it, whose
   // first valid row y0 - 3 comes at it = 4.
@@ -1572,8 +1580,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       shift_ew(UX3, ue, uw);
       shift_ew(P3, pe, pw);
       shift_ew(C3, ce, cw);
-      PH3 = advect_n(P3, pe, pw, P2, P4, UX3, ue, uw, UY3, UY2, UY4, adv);
-      CH3 = advect_n(C3, ce, cw, C2, C4, UX3, ue, uw, UY3, UY2, UY4, adv);
+      // u^n beyond a plate is not computed: its mirror image with u_y reversed
+      const T vn = (walls && q - 3 == ny - 1) ? -UY3 : UY2, vs = (walls && q - 3 == 0) ? -UY3 : UY4;
+      PH3 = advect_n(P3, pe, pw, P2, P4, UX3, ue, uw, UY3, vn, vs, adv);
+      CH3 = advect_n(C3, ce, cw, C2, C4, UX3, ue, uw, UY3, vn, vs, adv);
       if (DBG && own_col && q - 3 >= y0 && q - 3 < yend) {
         const int64_t qq = (int64_t)(q - 3) * nx + (x0 + col);
         dbg[7 * nplane + qq] = (double)PH3;
@@ -1582,7 +1592,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     // ---- s4: bracket M of Eq. (18) and X^{n+1/2} at row q - 4
     if (q - 4 >= y0 - 1 && q - 4 < yend + 1) {
-      const Nbr<T> gph = nbr(PH3, PH4, PH5), gch = nbr(CH3, CH4, CH5);
+      // half-step fields beyond a plate: the mirror image of the boundary row
+      const bool top = walls && q - 4 == ny - 1, bot = walls && q - 4 == 0;
+      const Nbr<T> gph = nbr(top ? PH4 : PH3, PH4, bot ? PH4 : PH5), gch = nbr(top ? CH4 : CH3, CH4, bot ? CH4 : CH5);
       T gphx, gphy, gchx, gchy;
       grad9n(gph, gphx, gphy);
       grad9n(gch, gchx, gchy);
@@ -1600,7 +1612,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     // ---- s5: phi^{n+1}, c^{n+1} (Eqs. 18, 19) at row q - 5 and centre-of-mass contributions
     if (q - 5 >= y0) {
       const int r = q - 5;
-      const Nbr<T> gM = nbr(M4, M5, M6), gch = nbr(CH4, CH5, CH6), gXh = nbr(XH4, XH5, XH6);
+      const bool top = walls && r == ny - 1, bot = walls && r == 0;
+      const Nbr<T> gM = nbr(top ? M5 : M4, M5, bot ? M5 : M6), gch = nbr(top ? CH5 : CH4, CH5, bot ? CH5 : CH6),
+                   gXh = nbr(top ? XH5 : XH4, XH5, bot ? XH5 : XH6);
       const T phn = PH5 + Gamma * lap9n(gM);
       const T ch = CH5;
       const T lch = lap9n(gch);
@@ -1614,7 +1628,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           m &= m - 1;
           const DropDev d = drops[I.drop_base + k];
           const double px = d.x + (d.R - d.Rs) * d.ex, py = d.y + (d.R - d.Rs) * d.ey;
-          const double dx = minimg(xd - px, (double)nx), dy = minimg(yd - py, (double)ny);
+          const double dx = minimg(xd - px, (double)nx), dy = minimg(yd - py, I.yper);
           if (dx * dx + dy * dy <= d.Rs * d.Rs) ++cnt;
         }
       }
@@ -1641,7 +1655,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
               const int k = w * 64 + __ffsll(m) - 1;
               m &= m - 1;
               const DropDev d = drops[I.drop_base + k];
-              const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, (double)ny);
+              const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, I.yper);
               const double d2 = dx * dx + dy * dy;
               if (best < 0 || d2 < bd) {
                 best = k;
@@ -1653,7 +1667,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           kd = best;
           cv0 = v;
           cv1 = v * minimg(xd - d.x, (double)nx);
-          cv2 = v * minimg(yd - d.y, (double)ny);
+          cv2 = v * minimg(yd - d.y, I.yper);
         }
       }
       // per-row wave sums of the centre-of-mass contributions, one droplet at a time (fixed butterfly order)

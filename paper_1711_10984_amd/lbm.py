@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("LBM_LIBRARY", os.path.join(_HERE, "liblbm.so"))
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_HIP, LBM_E_UNSTABLE, LBM_E_STATE = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16 = 0, 1, 2
+LBM_WALLS_NONE, LBM_WALLS_Y = 0, 1
 LBM_ADV_PAPER, LBM_ADV_FLUX = 0, 1
 LBM_PATH_FUSED, LBM_PATH_SPLIT, LBM_PATH_WAVE = 0, 1, 2
 LBM_MAXDROP = 256
@@ -42,7 +43,7 @@ class LBMError(RuntimeError):
 
 class lbm_config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32), ("advection", C.c_int32),
-                ("tau", C.c_double), ("n0", C.c_double), ("a", C.c_double), ("b", C.c_double),
+                ("walls", C.c_int32), ("reserved", C.c_int32), ("tau", C.c_double), ("n0", C.c_double), ("a", C.c_double), ("b", C.c_double),
                 ("B0", C.c_double), ("B1", C.c_double), ("D", C.c_double), ("Gamma", C.c_double),
                 ("gamma", C.c_double), ("A0", C.c_double), ("t_star", C.c_double), ("c0", C.c_double)]
 
@@ -121,7 +122,8 @@ def _dptr(a: Optional[np.ndarray]):
 def make_config(p: dict, precision: int = LBM_FP64) -> lbm_config:
     """lbm_config from a parameter dict (keys as in include/lbm.h; nx, ny required)."""
     return lbm_config(nx=int(p["nx"]), ny=int(p["ny"]), precision=int(precision),
-                      advection=int(p.get("advection", 0)), tau=p.get("tau", 1.0), n0=p.get("n0", 1.0),
+                      advection=int(p.get("advection", 0)), walls=int(p.get("walls", 0)), reserved=0,
+                      tau=p.get("tau", 1.0), n0=p.get("n0", 1.0),
                       a=p.get("a", -0.001), b=p.get("b", 0.001), B0=p.get("B0", 0.006), B1=p.get("B1", -0.05),
                       D=p.get("D", 0.1), Gamma=p.get("Gamma", 1.0), gamma=p.get("gamma", 0.0),
                       A0=p.get("A0", 0.0), t_star=p.get("t_star", 2.0e6), c0=p.get("c0", 0.0))

@@ -114,6 +114,17 @@ def c2_single_active(seed: int = 1002, n: int = 256) -> Workload:
     return Workload(f"c2_{n}x{n}_single_active_droplet", n, n, dict(ACTIVE), phi, psi, [d], steps=50000)
 
 
+def plates_single_active(seed: int = 1006, nx: int = 512, ny: int = 256, R: float = 32.0) -> Workload:
+    """The plate geometry of Sec. 4: a droplet of radius R at the centre of an nx x ny box between two plates
+    (walls at y = -1/2 and y = ny - 1/2, x periodic), surfactant initially 0.1 everywhere, B0 = 0.006,
+    B1 = -0.05, tau = 0.6, consumption 1.5e-3 and production A0 = 1.5e-10 in a disk of radius R/4 touching
+    the interface from inside on the +x side."""
+    d = DropSpec(x=nx / 2.0, y=ny / 2.0, R=R, Rs=R / 4.0, ex=1.0, ey=0.0, active=1, psi_front=0.1, psi_back=0.1)
+    phi, psi = droplet_fields(nx, ny, [d], psi_out=0.1, seed=seed)
+    params = dict(PAPER_EQUILIBRIUM, tau=0.6, gamma=1.5e-3, A0=1.5e-10, walls=1)
+    return Workload(f"plates_{nx}x{ny}_single_active_droplet", nx, ny, params, phi, psi, [d], steps=100000)
+
+
 def c3_batch(seed: int = 1003) -> List[Workload]:
     """32 two-droplet instances (R = 24, Ly = 256) of uneven widths: head-on separations
     d in {2.5, 3, 4, 6} R (Lx = 256, 256, 384, 512), vertical offsets {0, R/2, R}, active-active and

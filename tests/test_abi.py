@@ -41,7 +41,7 @@ def test_header_constants_match_binding():
 
 def test_struct_layouts():
     lbm = _lbm()
-    assert C.sizeof(lbm.lbm_config) == 4 * 4 + 12 * 8
+    assert C.sizeof(lbm.lbm_config) == 6 * 4 + 12 * 8
     assert C.sizeof(lbm.lbm_droplet) == 6 * 8 + 8
     assert C.sizeof(lbm.lbm_obs) == 8 + 5 * 8 + 8
 

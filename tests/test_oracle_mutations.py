@@ -16,7 +16,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
 PINS = ["tests/test_oracle_thermo.py", "tests/test_oracle_stencils.py", "tests/test_oracle_lb.py",
-        "tests/test_oracle_fd.py", "tests/test_oracle_equilibrium.py"]
+        "tests/test_oracle_fd.py", "tests/test_oracle_equilibrium.py", "tests/test_oracle_walls.py"]
 
 MUTATIONS = [
     ("equilibrium without the 1/2", "4.5 * eu * eu", "9.0 * eu * eu"),
@@ -30,7 +30,7 @@ MUTATIONS = [
     ("cubic term at the half step", "p->b * (pn * pn * pn)", "p->b * (ph[k] * ph[k] * ph[k])"),
     ("gradient axes mixed", "gy[k] = (4.0 * (N - S)", "gy[k] = (4.0 * (E - Wv)"),
     ("Laplacian centre weight", "- 20.0 * g[k]", "- 16.0 * g[k]"),
-    ("streaming reversed", "idx(p, x + EX[i], y + EY[i])] = fstar", "idx(p, x - EX[i], y - EY[i])] = fstar"),
+    ("streaming reversed", "idx(p, x + EX[i], yy)] = fstar", "idx(p, x - EX[i], y - EY[i])] = fstar"),
     ("source disk radius", "<= d->Rs * d->Rs", "< d->Rs * d->Rs * 0.5"),
     ("consumption sign", "- p->gamma * (ch[k] - p->c0)", "+ p->gamma * (ch[k] - p->c0)"),
     ("link mobility from one end", "(kc + kf[ki])", "(2.0 * kc)"),
@@ -48,6 +48,13 @@ MUTATIONS = [
      "double my = (fi[2] + (fi[5] + fi[8])) - (fi[4] + (fi[7] + fi[6]));"),
     ("centre of mass unweighted", "sx[k] += v * dx;", "sx[k] += dx;"),
     ("relaxation rate", "double omega = 1.0 / p->tau;", "double omega = 1.0 / (p->tau + 0.1);"),
+    ("walls: bounce-back to the mirror diagonal", "OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6}",
+     "OPP[9] = {0, 3, 4, 1, 2, 8, 7, 6, 5}"),
+    ("walls: mirror ghost one row off", "if (y < 0) y = -1 - y;", "if (y < 0) y = -y;"),
+    ("walls: top plate mirrored off by one", "if (y >= p->ny) y = 2 * p->ny - 1 - y;",
+     "if (y >= p->ny) y = 2 * p->ny - 2 - y;"),
+    ("walls: ghost velocity not reversed", "(p->walls && y == 0) ? -uy[kS] : uy[kS]",
+     "(p->walls && y == 0) ? uy[kS] : uy[kS]"),
 ]
 
 
