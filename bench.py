@@ -63,10 +63,8 @@ def measured_traffic(kernel: str, workload: str, precision: str, seg_rows):
         return None
     if data.get("kernel_source_hash") != kernel_source_hash():
         return None
-    ent = data.get("entries", {}).get(f"{kernel}:{workload}:{precision}")
-    if ent is None or ent.get("seg_rows") != seg_rows:
-        return None
-    return ent.get("bytes_per_launch")
+    ent = data.get("entries", {}).get(f"{kernel}:{workload}:{precision}:{seg_rows}")
+    return None if ent is None else ent.get("bytes_per_launch")
 
 
 def build_sim(workloads, precision, graph_steps, path):
