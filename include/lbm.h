@@ -207,6 +207,28 @@ int lbm_autotune(lbm_ctx* ctx, int32_t launches, int32_t both_paths, int32_t* ro
  * wave path: {k_wave, k_reduce, 0}; split path: {k_lb, k_fd, k_reduce}.  Advances the state by n steps.  Synchronous. */
 int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
 
+/* ---- Reverse mode (the derivative of a droplet's displacement; Sec. 4 centre of mass) ----
+ * The loss is J = x_CM(n0 + nsteps) - x_CM(n0) of droplet `drop` (minimum image in x, so |J| < nx/2), and the
+ * derivatives are with respect to the production rate A0 of Sec. 4 (A(n) = A0 min(n, t_star)) and to the
+ * surfactant field c at the start of the run, n0.  The adjoint is the exact transpose of the discrete step
+ * (Eqs. 3, 5, 10-19) with these held fixed: the nodes inside each production disk, the upwind side chosen by
+ * the sign of u in Eqs. (16)-(17) and the droplet masks (phi >= 0, nearest centre); none of them is
+ * differentiable.  Contexts of one periodic lattice, LBM_FP64 or LBM_FP32, LBM_ADV_PAPER (LBM_E_INVAL
+ * otherwise).
+ * Memory: checkpoints of the state every `every` steps, the states of one interval and the planes of one
+ * backward step live in a caller-owned device workspace of lbm_adjoint_bytes bytes (the library allocates
+ * nothing); it must stay untouched between the forward and the backward call. */
+int lbm_adjoint_bytes(const lbm_ctx* ctx, int64_t nsteps, int32_t every, size_t* bytes);
+/* Forward pass: advances the context by nsteps steps (as lbm_step) from its current state n0, keeping a
+ * checkpoint every `every` steps in ws.  J (may be NULL) receives the loss.  Synchronous. */
+int lbm_adjoint_forward(lbm_ctx* ctx, void* ws, size_t bytes, int32_t drop, int64_t nsteps, int32_t every,
+                        double* J);
+/* Backward pass of the last lbm_adjoint_forward on this context (LBM_E_STATE if the context has stepped
+ * since): recomputes each checkpoint interval, then runs the adjoint kernels from n0 + nsteps back to n0.
+ * dJ_dA0 (may be NULL) receives dJ/dA0; dJ_dc0 (may be NULL, host [ny][nx], x fastest) receives dJ/dc(n0).
+ * The context is left at n0 + nsteps.  May be called again.  Synchronous. */
+int lbm_adjoint_backward(lbm_ctx* ctx, void* ws, size_t bytes, double* dJ_dA0, double* dJ_dc0);
+
 /* Name of kernel `which` (0..2) of lbm_time_kernels for a path (static string, "" if none). */
 const char* lbm_kernel_name(int32_t path, int32_t which);
 

@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 # (source, floating-point contraction)
 SRC = [("lbm_kernels_f64.hip", "off"), ("lbm_kernels_f32.hip", "fast"), ("lbm_kernels_f16.hip", "fast"),
+       ("lbm_adjoint_f64.hip", "off"), ("lbm_adjoint_f32.hip", "fast"),
        ("lbm_api.hip", "off")]
 LIB = os.path.join(HERE, "liblbm.so")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")

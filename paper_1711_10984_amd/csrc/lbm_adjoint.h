@@ -1,0 +1,52 @@
+// Launchers of the reverse-mode (adjoint) kernels of one timestep; internal to the library.
+// Planes are dense [ny][nx]; the state planes phi^n, c^n are read from the field pool (row pitch `pitch`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// Forward intermediates of step n, as exported by the stage-export kernels (doubles, dense planes).
+struct AdjFwd {
+  const double *mu, *X, *Fx, *Fy, *n, *ux, *uy, *ph, *ch, *M, *Xh;
+};
+
+// Every plane an adjoint step reads or writes (T = arithmetic type, dense planes of nx * ny).
+template <typename T>
+struct AdjPlanes {
+  const T *phi, *c;  // state at n in the pool (pitched)
+  int pitch;
+  const T *fb1, *pb1, *cb1;  // adjoint of f (9 planes), phi, c at n + 1
+  T *fb, *pb, *cb;           // adjoint at n (outputs)
+  // gradient planes of the forward fields
+  T *gpx, *gpy, *gcx, *gcy, *lp, *gphx, *gphy, *gchx, *gchy, *lph, *gmx, *gmy, *gXx, *gXy;
+  // intermediate adjoints
+  T *Mb, *Xhb, *phb, *chb, *uxb, *uyb, *Fxb, *Fyb, *mub, *Xb;
+};
+
+struct AdjModel {
+  int nx, ny;
+  double a, b, B0, B1, D, Gamma, gamma, omega, coef, ramp;  // ramp = min(n, t*): dA(n)/dA0
+  double yper;
+};
+
+// One backward step: the adjoint at n + 1 -> the adjoint at n.  part receives per-block partial sums of
+// sum_r cb1(r) * ramp * count_n(r) (the step's contribution to d/dA0), at most adj_blocks(nx * ny) values.
+template <typename T>
+hipError_t launch_adjoint_step(hipStream_t s, const AdjModel& m, const AdjFwd& f, const AdjPlanes<T>& p,
+                               const DropDev* drops_n, int ndrop, double* part);
+
+// Seed of the loss x_CM^N of droplet `drop`: pass 0 writes per-block partial sums of phi over the droplet's
+// nodes (phi^N >= 0, nearest centre of step N - 1) into part; pass 1 writes pb = (dx - delta) / sw on those
+// nodes and 0 elsewhere, and clears fb, cb.
+template <typename T>
+hipError_t launch_adjoint_seed(hipStream_t s, int pass, const AdjModel& m, const T* phi, int pitch,
+                               const DropDev* drops_prev, int ndrop, int drop, double delta, double sw, T* fb,
+                               T* pb, T* cb, double* part);
+
+inline int adj_blocks(int64_t nodes) { return (int)((nodes + 255) / 256); }
+
+}  // namespace lbm

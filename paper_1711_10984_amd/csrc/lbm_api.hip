@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "lbm_adjoint.h"
 #include "lbm_internal.h"
 
 using namespace lbm;
@@ -236,6 +237,12 @@ struct lbm_ctx {
   int path = LBM_PATH_FUSED;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   hipGraph_t graph[2] = {nullptr, nullptr};
+  // the last recorded forward pass of lbm_adjoint_forward (see lbm_adjoint_backward)
+  struct {
+    bool valid = false;
+    int64_t n0 = 0, nsteps = 0;
+    int every = 0, drop = 0;
+  } adj;
 
   void* pool() const { return ws + L.off_pool; }
   InstDev* d_inst() const { return reinterpret_cast<InstDev*>(ws + L.off_inst); }
@@ -462,13 +469,13 @@ int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, do
 
 // Stage planes of the next step of instance `inst` from the kernels of the current path.
 template <typename T, typename P>
-hipError_t debug_launch(lbm_ctx* c, int inst) {
+hipError_t debug_launch(lbm_ctx* c, int inst, double* dbg) {
   T* buf = reinterpret_cast<T*>(c->pool());
-  if (c->path != LBM_PATH_SPLIT) return launch_sweep<T, P>(c, c->parity, c->d_dbg(), inst);
-  hipError_t e = launch_lb<T, P>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_dbg(), inst);
+  if (c->path != LBM_PATH_SPLIT) return launch_sweep<T, P>(c, c->parity, dbg, inst);
+  hipError_t e = launch_lb<T, P>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, dbg, inst);
   if (e != hipSuccess) return e;
   return launch_fd<T>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
-                      c->d_mask(), c->d_step(), c->d_dbg(), inst);
+                      c->d_mask(), c->d_step(), dbg, inst);
 }
 
 // One eager step with hipEvents between its kernels: ev[0..nk] bracket nk launches.
@@ -744,7 +751,8 @@ int lbm_debug_stage(lbm_ctx* c, int32_t inst, double* out) {
   if (!out) return fail(LBM_E_INVAL, "out must not be NULL");
   const InstDev& d = c->L.inst[inst];
   if ((int64_t)d.nx * d.ny > DEBUG_MAX_NODES) return fail(LBM_E_INVAL, "stage export is limited to 512 x 512 nodes");
-  hipError_t e = with_types(c->L.prec, [&](auto t, auto p) { return debug_launch<decltype(t), decltype(p)>(c, inst); });
+  hipError_t e = with_types(c->L.prec,
+                            [&](auto t, auto p) { return debug_launch<decltype(t), decltype(p)>(c, inst, c->d_dbg()); });
   if (e != hipSuccess) return fail(LBM_E_HIP, std::string("stage launch: ") + hipGetErrorString(e));
   const size_t n = (size_t)d.nx * d.ny;
   HIPCHK(hipMemcpyAsync(out, c->d_dbg(), sizeof(double) * LBM_NSTAGE * n, hipMemcpyDeviceToHost, c->stream));
@@ -911,5 +919,265 @@ void lbm_destroy(lbm_ctx* c) {
 }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Reverse mode: checkpointed forward pass and backward sweep of the adjoint kernels.
+namespace {
+
+struct AdjLayout {
+  size_t pop = 0, field = 0, dropb = 0, slot = 0;  // bytes of a saved state and of its parts
+  int64_t ncp = 0, nodes = 0;
+  int every = 0, nb = 0;
+  size_t off_cp = 0, off_seg = 0, off_final = 0, off_fwd = 0, off_adj = 0, off_part = 0, total = 0;
+};
+
+constexpr int ADJ_TMP_PLANES = 24;  // gradient planes and intermediate adjoints of one backward step
+
+int adj_check(const lbm_ctx* c, int32_t drop, int64_t nsteps, int32_t every) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  if (c->L.inst.size() != 1) return fail(LBM_E_INVAL, "the adjoint takes a context of one lattice");
+  const lbm_config& g = c->cfg[0];
+  if (g.precision != LBM_FP64 && g.precision != LBM_FP32)
+    return fail(LBM_E_INVAL, "the adjoint runs in LBM_FP64 or LBM_FP32");
+  if (g.walls != LBM_WALLS_NONE) return fail(LBM_E_INVAL, "the adjoint is implemented for periodic lattices");
+  if (g.advection != LBM_ADV_PAPER) return fail(LBM_E_INVAL, "the adjoint is implemented for LBM_ADV_PAPER");
+  if (drop < 0 || drop >= c->L.inst[0].ndrop) return fail(LBM_E_INVAL, "droplet index out of range");
+  if (nsteps < 1 || every < 1) return fail(LBM_E_INVAL, "nsteps and checkpoint interval must be >= 1");
+  return LBM_OK;
+}
+
+AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int every) {
+  AdjLayout A;
+  const InstDev& d = c->L.inst[0];
+  A.nodes = (int64_t)d.nx * d.ny;
+  A.nb = adj_blocks(A.nodes);
+  A.every = every;
+  A.ncp = (nsteps + every - 1) / every;
+  A.pop = (size_t)9 * d.pstride * c->L.elem;
+  A.field = (size_t)d.pstride * c->L.elem;
+  A.dropb = sizeof(DropDev) * (size_t)std::max(1, (int)d.ndrop);
+  A.slot = align_up(A.pop + 2 * A.field + A.dropb + sizeof(int64_t), ALIGN);
+  size_t off = 0;
+  A.off_cp = off;    off += A.slot * (size_t)A.ncp;
+  A.off_seg = off;   off += A.slot * (size_t)every;
+  A.off_final = off; off += A.slot;
+  A.off_fwd = off;   off = align_up(off + sizeof(double) * LBM_NSTAGE * (size_t)A.nodes, ALIGN);
+  A.off_adj = off;   off = align_up(off + c->L.elem * (size_t)(22 + ADJ_TMP_PLANES) * A.nodes, ALIGN);
+  A.off_part = off;  off = align_up(off + sizeof(double) * (size_t)A.nb * (size_t)(nsteps + 1), ALIGN);
+  A.total = off;
+  return A;
+}
+
+// Copy the state of the single lattice (current buffers, droplet table, step counter) to or from a slot.
+int adj_save(lbm_ctx* c, const AdjLayout& A, char* slot) {
+  const InstDev& d = c->L.inst[0];
+  char* pool = static_cast<char*>(c->pool());
+  const size_t e = c->L.elem;
+  HIPCHK(hipMemcpyAsync(slot, pool + d.off_f[c->parity] * e, A.pop, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(slot + A.pop, pool + d.off_phi[c->parity] * e, A.field, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(slot + A.pop + A.field, pool + d.off_c[c->parity] * e, A.field, hipMemcpyDeviceToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(slot + A.pop + 2 * A.field, c->d_drops(), sizeof(DropDev) * d.ndrop, hipMemcpyDeviceToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(slot + A.pop + 2 * A.field + A.dropb, c->d_step(), sizeof(int64_t), hipMemcpyDeviceToDevice,
+                        c->stream));
+  return LBM_OK;
+}
+
+int adj_load(lbm_ctx* c, const AdjLayout& A, const char* slot, int64_t step) {
+  const InstDev& d = c->L.inst[0];
+  char* pool = static_cast<char*>(c->pool());
+  const size_t e = c->L.elem;
+  HIPCHK(hipMemcpyAsync(pool + d.off_f[c->parity] * e, slot, A.pop, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(pool + d.off_phi[c->parity] * e, slot + A.pop, A.field, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(pool + d.off_c[c->parity] * e, slot + A.pop + A.field, A.field, hipMemcpyDeviceToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_drops(), slot + A.pop + 2 * A.field, sizeof(DropDev) * d.ndrop, hipMemcpyDeviceToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_step(), slot + A.pop + 2 * A.field + A.dropb, sizeof(int64_t), hipMemcpyDeviceToDevice,
+                        c->stream));
+  c->step = step;
+  return LBM_OK;
+}
+
+const DropDev* adj_slot_drops(const AdjLayout& A, const char* slot) {
+  return reinterpret_cast<const DropDev*>(slot + A.pop + 2 * A.field);
+}
+
+template <typename T>
+int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* dc0) {
+  const InstDev& d = c->L.inst[0];
+  const lbm_config& g = c->cfg[0];
+  const int64_t n0 = c->adj.n0, N = c->adj.nsteps, M = A.nodes;
+  const int every = c->adj.every, drop = c->adj.drop, nd = d.ndrop;
+  int rc;
+  if ((rc = adj_save(c, A, w + A.off_final)) != LBM_OK) return rc;
+  double* fwd = reinterpret_cast<double*>(w + A.off_fwd);
+  const AdjFwd F{fwd + 0 * M, fwd + 1 * M, fwd + 2 * M, fwd + 3 * M, fwd + 4 * M, fwd + 5 * M,
+                 fwd + 6 * M, fwd + 7 * M, fwd + 8 * M, fwd + 9 * M, fwd + 10 * M};
+  T* adj = reinterpret_cast<T*>(w + A.off_adj);
+  T* lam[2] = {adj, adj + 11 * M};  // adjoint state (f 9 planes, phi, c) at n and at n + 1
+  T* tmp = adj + 22 * M;
+  double* part = reinterpret_cast<double*>(w + A.off_part);
+  AdjModel m;
+  m.nx = d.nx;
+  m.ny = d.ny;
+  m.a = g.a;
+  m.b = g.b;
+  m.B0 = g.B0;
+  m.B1 = g.B1;
+  m.D = g.D;
+  m.Gamma = g.Gamma;
+  m.gamma = g.gamma;
+  m.omega = d.omega;
+  m.coef = d.coef;
+  m.yper = d.yper;
+  m.ramp = 0.0;
+  auto planes = [&](T* in, T* out) {
+    AdjPlanes<T> p;
+    T* base = reinterpret_cast<T*>(c->pool());
+    p.phi = base + d.off_phi[c->parity];
+    p.c = base + d.off_c[c->parity];
+    p.pitch = d.pitch;
+    p.fb1 = in;
+    p.pb1 = in + 9 * M;
+    p.cb1 = in + 10 * M;
+    p.fb = out;
+    p.pb = out + 9 * M;
+    p.cb = out + 10 * M;
+    T** t[] = {&p.gpx, &p.gpy, &p.gcx, &p.gcy, &p.lp, &p.gphx, &p.gphy, &p.gchx, &p.gchy, &p.lph, &p.gmx, &p.gmy,
+               &p.gXx, &p.gXy, &p.Mb, &p.Xhb, &p.phb, &p.chb, &p.uxb, &p.uyb, &p.Fxb, &p.Fyb, &p.mub, &p.Xb};
+    static_assert(sizeof(t) / sizeof(t[0]) == ADJ_TMP_PLANES, "temporary planes");
+    for (int i = 0; i < ADJ_TMP_PLANES; ++i) *t[i] = tmp + (size_t)i * M;
+    return p;
+  };
+  int cur = 1;  // lam[cur] holds the adjoint of the latest state
+  bool seeded = false;
+  for (int64_t s = A.ncp - 1; s >= 0; --s) {
+    const int64_t k0 = s * every, k1 = std::min<int64_t>(N, k0 + every);
+    // recompute the states of the segment from its checkpoint, keeping each one
+    if ((rc = adj_load(c, A, w + A.off_cp + (size_t)s * A.slot, n0 + k0)) != LBM_OK) return rc;
+    for (int64_t k = k0; k < k1; ++k) {
+      if ((rc = adj_save(c, A, w + A.off_seg + (size_t)(k - k0) * A.slot)) != LBM_OK) return rc;
+      hipError_t e = enqueue_step_any(c, c->parity);
+      if (e != hipSuccess) return fail(LBM_E_HIP, std::string("adjoint recompute: ") + hipGetErrorString(e));
+      c->parity ^= 1;
+      c->step += 1;
+    }
+    if (!seeded) {
+      // loss x_CM^N - x_CM^{n0}: seed d/d phi^N over the droplet's nodes (centres of step N - 1)
+      const char* last = w + A.off_seg + (size_t)(k1 - 1 - k0) * A.slot;
+      std::vector<DropDev> prev(nd), now(nd);
+      HIPCHK(hipMemcpyAsync(prev.data(), adj_slot_drops(A, last), sizeof(DropDev) * nd, hipMemcpyDeviceToHost,
+                            c->stream));
+      HIPCHK(hipMemcpyAsync(now.data(), c->d_drops(), sizeof(DropDev) * nd, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      double dx = now[drop].x - prev[drop].x;
+      if (dx >= 0.5 * d.nx) dx -= d.nx;
+      if (dx < -0.5 * d.nx) dx += d.nx;
+      const T* phiN = reinterpret_cast<const T*>(c->pool()) + d.off_phi[c->parity];
+      HIPCHK(launch_adjoint_seed<T>(c->stream, 0, m, phiN, d.pitch, adj_slot_drops(A, last), nd, drop, 0.0, 1.0,
+                                    lam[cur], lam[cur] + 9 * M, lam[cur] + 10 * M, part));
+      std::vector<double> hp(A.nb);
+      HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * A.nb, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      double sw = 0.0;
+      for (double v : hp) sw += v;
+      if (!(sw > 0.0)) return fail(LBM_E_STATE, "the droplet has no nodes with phi >= 0 at the end of the run");
+      HIPCHK(launch_adjoint_seed<T>(c->stream, 1, m, phiN, d.pitch, adj_slot_drops(A, last), nd, drop, dx, sw,
+                                    lam[cur], lam[cur] + 9 * M, lam[cur] + 10 * M, part));
+      seeded = true;
+    }
+    // backward through the segment, latest step first
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      const char* slot = w + A.off_seg + (size_t)(k - k0) * A.slot;
+      if ((rc = adj_load(c, A, slot, n0 + k)) != LBM_OK) return rc;
+      HIPCHK((debug_launch<T, T>(c, 0, fwd)));
+      const double tn = (double)(n0 + k);
+      m.ramp = tn < g.t_star ? tn : g.t_star;
+      const AdjPlanes<T> p = planes(lam[cur], lam[cur ^ 1]);
+      HIPCHK(launch_adjoint_step<T>(c->stream, m, F, p, adj_slot_drops(A, slot), nd, part + (size_t)(k + 1) * A.nb));
+      cur ^= 1;
+    }
+  }
+  // results: d/d c^{n0} and the production-rate derivative summed in a fixed order
+  if (dc0) {
+    std::vector<T> h((size_t)M);
+    HIPCHK(hipMemcpyAsync(h.data(), lam[cur] + 10 * M, sizeof(T) * M, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < M; ++i) dc0[i] = (double)h[(size_t)i];
+  }
+  if (dA0) {
+    std::vector<double> hp((size_t)A.nb * (size_t)(N + 1));
+    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double s = 0.0;
+    for (size_t i = (size_t)A.nb; i < hp.size(); ++i) s += hp[i];
+    *dA0 = s;
+  }
+  // back to the state at the end of the forward pass
+  if ((rc = adj_load(c, A, w + A.off_final, n0 + N)) != LBM_OK) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_adjoint_bytes(const lbm_ctx* c, int64_t nsteps, int32_t every, size_t* bytes) {
+  if (!c || !bytes) return fail(LBM_E_INVAL, "null argument");
+  if (nsteps < 1 || every < 1) return fail(LBM_E_INVAL, "nsteps and checkpoint interval must be >= 1");
+  if (c->L.inst.size() != 1) return fail(LBM_E_INVAL, "the adjoint takes a context of one lattice");
+  *bytes = adj_layout(c, nsteps, every).total;
+  return LBM_OK;
+}
+
+int lbm_adjoint_forward(lbm_ctx* c, void* ws, size_t bytes, int32_t drop, int64_t nsteps, int32_t every,
+                        double* J) {
+  int rc = adj_check(c, drop, nsteps, every);
+  if (rc != LBM_OK) return rc;
+  if (!ws) return fail(LBM_E_INVAL, "adjoint workspace must not be NULL");
+  const AdjLayout A = adj_layout(c, nsteps, every);
+  if (bytes < A.total) return fail(LBM_E_NOMEM, "adjoint workspace too small (see lbm_adjoint_bytes)");
+  char* w = static_cast<char*>(ws);
+  const InstDev& d = c->L.inst[0];
+  std::vector<DropDev> dd(d.ndrop);
+  HIPCHK(hipMemcpyAsync(dd.data(), c->d_drops(), sizeof(DropDev) * d.ndrop, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double x0 = dd[drop].x;
+  c->adj.valid = false;
+  c->adj.n0 = c->step;
+  c->adj.nsteps = nsteps;
+  c->adj.every = every;
+  c->adj.drop = drop;
+  for (int64_t k = 0; k < nsteps; k += every) {
+    if ((rc = adj_save(c, A, w + A.off_cp + (size_t)(k / every) * A.slot)) != LBM_OK) return rc;
+    if ((rc = lbm_step(c, std::min<int64_t>(every, nsteps - k))) != LBM_OK) return rc;
+  }
+  HIPCHK(hipMemcpyAsync(dd.data(), c->d_drops(), sizeof(DropDev) * d.ndrop, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double dx = dd[drop].x - x0;
+  if (dx >= 0.5 * d.nx) dx -= d.nx;
+  if (dx < -0.5 * d.nx) dx += d.nx;
+  if (J) *J = dx;
+  c->adj.valid = true;
+  return LBM_OK;
+}
+
+int lbm_adjoint_backward(lbm_ctx* c, void* ws, size_t bytes, double* dJ_dA0, double* dJ_dc0) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  if (!c->adj.valid) return fail(LBM_E_STATE, "no forward pass recorded (lbm_adjoint_forward)");
+  if (c->step != c->adj.n0 + c->adj.nsteps)
+    return fail(LBM_E_STATE, "the context has moved since the recorded forward pass");
+  if (!ws) return fail(LBM_E_INVAL, "adjoint workspace must not be NULL");
+  const AdjLayout A = adj_layout(c, c->adj.nsteps, c->adj.every);
+  if (bytes < A.total) return fail(LBM_E_NOMEM, "adjoint workspace too small (see lbm_adjoint_bytes)");
+  char* w = static_cast<char*>(ws);
+  return c->L.prec == LBM_FP64 ? adj_backward<double>(c, A, w, dJ_dA0, dJ_dc0)
+                               : adj_backward<float>(c, A, w, dJ_dA0, dJ_dc0);
+}
 
 }  // extern "C"

@@ -30,7 +30,8 @@ STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "p
 EXPORTED = ["lbm_workspace_bytes", "lbm_init_batch", "lbm_init", "lbm_step", "lbm_set_graph", "lbm_sync",
             "lbm_get_step", "lbm_fields", "lbm_observables", "lbm_droplets", "lbm_debug_stage",
             "lbm_time_kernels", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_set_seg_rows",
-            "lbm_get_seg_rows", "lbm_tune_rows", "lbm_autotune", "lbm_destroy", "lbm_last_error"]
+            "lbm_get_seg_rows", "lbm_tune_rows", "lbm_autotune", "lbm_adjoint_bytes", "lbm_adjoint_forward",
+            "lbm_adjoint_backward", "lbm_destroy", "lbm_last_error"]
 LBM_SEG_ROWS_MIN, LBM_SEG_ROWS_MAX, LBM_TUNE_NROWS = 16, 4096, 16
 PATH_NAMES = {LBM_PATH_FUSED: "fused", LBM_PATH_SPLIT: "split", LBM_PATH_WAVE: "wave"}
 
@@ -98,6 +99,9 @@ def load_library(path: Optional[str] = None):
     lib.lbm_tune_rows.argtypes = []
     lib.lbm_tune_rows.restype = C.POINTER(C.c_int32)
     lib.lbm_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
+    lib.lbm_adjoint_bytes.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.lbm_adjoint_forward.argtypes = [vp, vp, C.c_size_t, C.c_int32, C.c_int64, C.c_int32, dp]
+    lib.lbm_adjoint_backward.argtypes = [vp, vp, C.c_size_t, dp, dp]
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.restype = C.c_char_p
@@ -202,6 +206,26 @@ def lbm_time_kernels(ctx: int, n: int) -> np.ndarray:
     out = np.zeros(3)
     _check(load_library().lbm_time_kernels(C.c_void_p(ctx), int(n), _dptr(out)))
     return out
+
+
+def lbm_adjoint_bytes(ctx: int, nsteps: int, every: int) -> int:
+    n = C.c_size_t(0)
+    _check(load_library().lbm_adjoint_bytes(C.c_void_p(ctx), int(nsteps), int(every), C.byref(n)))
+    return int(n.value)
+
+
+def lbm_adjoint_forward(ctx: int, ws: int, nbytes: int, drop: int, nsteps: int, every: int) -> float:
+    J = np.zeros(1)
+    _check(load_library().lbm_adjoint_forward(C.c_void_p(ctx), C.c_void_p(ws), nbytes, int(drop), int(nsteps),
+                                              int(every), _dptr(J)))
+    return float(J[0])
+
+
+def lbm_adjoint_backward(ctx: int, ws: int, nbytes: int, shape):
+    dA0 = np.zeros(1)
+    dc0 = np.zeros(shape)
+    _check(load_library().lbm_adjoint_backward(C.c_void_p(ctx), C.c_void_p(ws), nbytes, _dptr(dA0), _dptr(dc0)))
+    return float(dA0[0]), dc0
 
 
 def lbm_kernel_name(path: int, which: int) -> str:
@@ -361,3 +385,62 @@ class Sim:
         ms = lbm_time_kernels(self.ctx, n)
         path = lbm_get_path(self.ctx)
         return {lbm_kernel_name(path, i): float(ms[i]) for i in range(3) if lbm_kernel_name(path, i)}
+
+    def adjoint_forward(self, drop: int, nsteps: int, every: int = 100) -> float:
+        """Advance nsteps steps keeping checkpoints every `every` steps (the adjoint workspace is a torch
+        uint8 tensor held by this object) and return J = x_CM(end) - x_CM(start) of droplet `drop`."""
+        nbytes = lbm_adjoint_bytes(self.ctx, nsteps, every)
+        with self.torch.cuda.device(self.device):
+            self.adj_ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        return lbm_adjoint_forward(self.ctx, self.adj_ws.data_ptr(), nbytes, drop, nsteps, every)
+
+    def adjoint_backward(self):
+        """(dJ/dA0, dJ/dc at the start) of the last adjoint_forward (the library's adjoint kernels)."""
+        return lbm_adjoint_backward(self.ctx, self.adj_ws.data_ptr(), self.adj_ws.numel(), self.shapes[0])
+
+
+def com_displacement(A0, psi0, params: dict, phi0: np.ndarray, drops: List[dict], nsteps: int, every: int = 100,
+                     drop: int = 0, precision: int = LBM_FP64, path: int = LBM_PATH_FUSED):
+    """J = x-displacement of droplet `drop`'s centre of mass over nsteps steps as a differentiable function of the
+    production rate A0 (0-d tensor) and the initial surfactant field psi0 ([ny][nx] tensor); the gradient comes
+    from the library's adjoint (lbm_adjoint_backward)."""
+    return _ComDisplacement.apply(A0, psi0, params, phi0, drops, nsteps, every, drop, precision, path)
+
+
+def _make_com_displacement():
+    import torch
+
+    class ComDisplacement(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, A0, psi0, params, phi0, drops, nsteps, every, drop, precision, path):
+            p = dict(params, A0=float(A0.detach().cpu()))
+            c0 = np.ascontiguousarray(psi0.detach().cpu().numpy(), dtype=np.float64)
+            sim = Sim([p], [phi0], [c0], [drops], precision=precision, graph_steps=20, path=path)
+            J = sim.adjoint_forward(drop, nsteps, every)
+            ctx.sim = sim
+            ctx.psi_device, ctx.psi_dtype = psi0.device, psi0.dtype
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            dA0, dc0 = ctx.sim.adjoint_backward()
+            ctx.sim.close()
+            g = gJ.detach().cpu().double()
+            gA0 = (g * dA0).to(torch.float64)
+            gpsi = (g * torch.from_numpy(dc0)).to(device=ctx.psi_device, dtype=ctx.psi_dtype)
+            return gA0, gpsi, None, None, None, None, None, None, None, None
+
+    return ComDisplacement
+
+
+class _LazyFunction:
+    def __init__(self):
+        self.fn = None
+
+    def apply(self, *args):
+        if self.fn is None:
+            self.fn = _make_com_displacement()
+        return self.fn.apply(*args)
+
+
+_ComDisplacement = _LazyFunction()
