@@ -91,13 +91,15 @@ def time_steps(sim, steps, warmup):
 
 
 def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=-1, seg_rows=0):
-    """path -1: the autotuner picks the sweeping kernel (fused or wave) and its strip height."""
+    """path -1: the autotuner picks the kernel path (fused or wave sweep with its strip height, or split)."""
     from paper_1711_10984_amd import lbm
     sim = build_sim(workloads, precision, graph_steps, 0 if path < 0 else path)
     tune_ms = {}
     if path != 1 and seg_rows == 0:
         # state-preserving: the trial launches write scratch only
         seg_rows, path, tune_ms = sim.autotune(10, both_paths=path < 0)
+        if path == 1:
+            seg_rows = None
     elif path != 1:
         if path < 0:
             path = 0
@@ -170,6 +172,30 @@ def lowp_accuracy(workloads, steps, log_every, graph_steps, path, low):
             "velocity_l2_rel_diff": float(num / den) if den > 0 else None}
 
 
+def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
+    """Reverse mode on the 256^2 single-active-droplet workload: wall time of the checkpointed forward pass and
+    of the backward sweep (both synchronous library calls), best of `repeats`, on the autotuned kernel path."""
+    from paper_1711_10984_amd import lbm, workloads as W
+    w = W.c2_single_active()
+    best_f, best_b = 1e300, 1e300
+    for _ in range(repeats):
+        sim = lbm.Sim([w.param_dict()], [w.phi0], [w.c0], [w.drop_dicts()], precision=precision, graph_steps=20)
+        rows, path, _ = sim.autotune(10, both_paths=True)
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.adjoint_forward(0, nsteps, every)
+        t1 = time.perf_counter()
+        sim.adjoint_backward()
+        t2 = time.perf_counter()
+        sim.close()
+        best_f, best_b = min(best_f, t1 - t0), min(best_b, t2 - t1)
+    return {"workload": f"{w.name}, {nsteps} steps, checkpoint every {every}", "nodes": w.nodes,
+            "path": PATH_NAMES[path], "seg_rows": rows if path != 1 else None,
+            "forward_ms_per_step": round(best_f / nsteps * 1e3, 5), "backward_ms_per_step": round(best_b / nsteps * 1e3, 5),
+            "backward_mlups": round(w.nodes * nsteps / best_b / 1e6, 1),
+            "backward_over_forward": round(best_b / best_f, 2)}
+
+
 def cpu_baseline(w, budget_s):
     """The FP64 oracle as it stands on this host's cores, on a bounded sample of the same workload."""
     from oracle import OracleSim, Params, Drop
@@ -195,10 +221,10 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=50, help="steps timed per kernel with hipEvents")
     ap.add_argument("--no-variants", action="store_true", help="FP64 2048^2 only")
     ap.add_argument("--path", type=int, default=-1, choices=[-1] + sorted(PATH_NAMES),
-                    help="-1: autotuned choice of 0 or 2; 0: fused sweep kernel; 1: split LB + FD kernels; "
+                    help="-1: autotuned choice of 0, 1 or 2; 0: fused sweep kernel; 1: split LB + FD kernels; "
                          "2: wavefront-per-strip sweep kernel")
     ap.add_argument("--seg-rows", type=int, default=0, help="fused-kernel strip height (0: autotune)")
-    ap.add_argument("--only", choices=["fp64", "fp32", "fp16", "c3"], default=None,
+    ap.add_argument("--only", choices=["fp64", "fp32", "fp16", "c3", "adjoint"], default=None,
                     help="run one configuration (for profiling); the JSON line then reports that one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
@@ -225,6 +251,9 @@ def main():
         torch.cuda.synchronize()
 
     c5 = W.c5_emulsion()
+    if args.only == "adjoint":
+        print(json.dumps({"only": "adjoint", "fp64": adjoint_measure(lbm.LBM_FP64, repeats=1)}), flush=True)
+        return
     if args.only in ("fp32", "fp16", "c3"):
         wl, prec, label = {"fp32": ([c5], lbm.LBM_FP32, "c5"), "fp16": ([c5], lbm.LBM_FP16, "c5"),
                            "c3": (W.c3_batch(), lbm.LBM_FP32, "c3")}[args.only]
@@ -287,6 +316,8 @@ def main():
             "emulsion_2048_64_droplets": lowp_accuracy([c5], 5000, 500, args.graph_steps, args.path,
                                                        lbm.LBM_FP16),
         }
+    if not args.no_variants:
+        out["adjoint"] = {"fp64": adjoint_measure(lbm.LBM_FP64), "fp32": adjoint_measure(lbm.LBM_FP32)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c5, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -192,13 +192,14 @@ const int32_t* lbm_tune_rows(void);
 
 /* Autotuner: time `launches` back-to-back launches of the sweeping kernel for each candidate height
  * (heights giving the same number of segments as a smaller one are skipped) -- for both sweeping
- * kernels (LBM_PATH_FUSED, LBM_PATH_WAVE) when both_paths != 0, else for the current path only -- and
- * set the path and height of the fastest.  The trial launches read the current state and write only
- * scratch (the inactive halves of the ping-pong buffers and the centre-of-mass partials): the state,
- * the droplet table and the step counter are unchanged.  On the split path nothing is tried.
- * rows_out, path_out (may be NULL) receive the choice; ms_out (may be NULL, 2 * LBM_TUNE_NROWS entries,
- * [fused heights..., wave heights...]) the average ms per launch of each candidate (-1 if not tried).
- * Synchronous. */
+ * kernels (LBM_PATH_FUSED, LBM_PATH_WAVE) and the split pair (LBM_PATH_SPLIT, no height) when
+ * both_paths != 0, else for the current sweeping path only -- and set the path and height of the fastest.
+ * The trial launches read the current state and write only scratch (the inactive halves of the ping-pong
+ * buffers, the velocity planes and the centre-of-mass partials): the state, the droplet table and the step
+ * counter are unchanged.  Called on the split path with both_paths == 0, nothing is tried.
+ * rows_out, path_out (may be NULL) receive the choice; ms_out (may be NULL, 2 * LBM_TUNE_NROWS + 1 entries,
+ * [fused heights..., wave heights..., split]) the average ms per launch (per step pair for the split
+ * path) of each candidate (-1 if not tried).  Synchronous. */
 int lbm_autotune(lbm_ctx* ctx, int32_t launches, int32_t both_paths, int32_t* rows_out, int32_t* path_out,
                  double* ms_out);
 
@@ -215,9 +216,10 @@ int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
  * the sign of u in Eqs. (16)-(17) and the droplet masks (phi >= 0, nearest centre); none of them is
  * differentiable.  Contexts of one periodic lattice, LBM_FP64 or LBM_FP32, LBM_ADV_PAPER (LBM_E_INVAL
  * otherwise).
- * Memory: checkpoints of the state every `every` steps, the states of one interval and the planes of one
- * backward step live in a caller-owned device workspace of lbm_adjoint_bytes bytes (the library allocates
- * nothing); it must stay untouched between the forward and the backward call. */
+ * Memory: a checkpoint of the state every `every` steps (9 population planes, phi, c), and for the interval
+ * being reversed phi, c and 11 FP64 stage planes of each step, plus about 24 planes of one backward step, live
+ * in a caller-owned device workspace of lbm_adjoint_bytes bytes (the library allocates nothing); it must stay
+ * untouched between the forward and the backward call.  An interval near sqrt(nsteps) keeps it smallest. */
 int lbm_adjoint_bytes(const lbm_ctx* ctx, int64_t nsteps, int32_t every, size_t* bytes);
 /* Forward pass: advances the context by nsteps steps (as lbm_step) from its current state n0, keeping a
  * checkpoint every `every` steps in ws.  J (may be NULL) receives the loss.  Synchronous. */

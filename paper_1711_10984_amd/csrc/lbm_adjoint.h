@@ -17,7 +17,7 @@ struct AdjFwd {
 // Every plane an adjoint step reads or writes (T = arithmetic type, dense planes of nx * ny).
 template <typename T>
 struct AdjPlanes {
-  const T *phi, *c;  // state at n in the pool (pitched)
+  const T *phi, *c;  // state at n (pitched rows)
   int pitch;
   const T *fb1, *pb1, *cb1;  // adjoint of f (9 planes), phi, c at n + 1
   T *fb, *pb, *cb;           // adjoint at n (outputs)

@@ -300,9 +300,18 @@ hipError_t launch_sweep(lbm_ctx* c, int parity, double* dbg, int dbg_inst) {
                            c->d_part(), c->d_mask(), c->d_step(), dbg, dbg_inst);
 }
 
+// The two tile kernels of the split path.
+template <typename T, typename P>
+hipError_t launch_split(lbm_ctx* c, int parity) {
+  T* buf = reinterpret_cast<T*>(c->pool());
+  hipError_t e = launch_lb<T, P>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+  if (e != hipSuccess) return e;
+  return launch_fd<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
+                      c->d_mask(), c->d_step(), nullptr, -1);
+}
+
 template <typename T, typename P>
 hipError_t enqueue_step(lbm_ctx* c, int parity) {
-  T* buf = reinterpret_cast<T*>(c->pool());
   hipError_t e;
   if (c->path != LBM_PATH_SPLIT) {
     e = launch_sweep<T, P>(c, parity, nullptr, -1);
@@ -310,10 +319,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity) {
     return launch_reduce(c->stream, TILING_FUSED, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(),
                          c->d_mask(), c->d_step(), 1);
   }
-  e = launch_lb<T, P>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
-  if (e != hipSuccess) return e;
-  e = launch_fd<T>(c->stream, 0, parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
-                   c->d_part(), c->d_mask(), c->d_step(), nullptr, -1);
+  e = launch_split<T, P>(c, parity);
   if (e != hipSuccess) return e;
   return launch_reduce(c->stream, TILING_SPLIT, c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(),
                        c->d_mask(), c->d_step(), 1);
@@ -812,8 +818,8 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows
   if (!c) return fail(LBM_E_INVAL, "null context");
   if (launches <= 0) return fail(LBM_E_INVAL, "launches must be > 0");
   if (ms_out)
-    for (int k = 0; k < 2 * LBM_TUNE_NROWS; ++k) ms_out[k] = -1.0;
-  if (c->path == LBM_PATH_SPLIT) {
+    for (int k = 0; k < 2 * LBM_TUNE_NROWS + 1; ++k) ms_out[k] = -1.0;
+  if (c->path == LBM_PATH_SPLIT && !both_paths) {
     if (rows_out) *rows_out = c->L.seg_rows;
     if (path_out) *path_out = c->path;
     return LBM_OK;
@@ -882,6 +888,35 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows
         best_path = paths[pi];
       }
     }
+  // the split path (two tile kernels, no strip height) competes with the step time of the sweeping kernels
+  if (both_paths && rc == LBM_OK) {
+    c->path = LBM_PATH_SPLIT;
+    double split_ms = 1e300;
+    for (int pass = 0; pass < 2 && rc == LBM_OK; ++pass) {
+      hipError_t e = hipSuccess;
+      auto one = [&]() {
+        return with_types(c->L.prec,
+                          [&](auto t, auto p) { return launch_split<decltype(t), decltype(p)>(c, c->parity); });
+      };
+      e = one();
+      (void)hipEventRecord(e0, c->stream);
+      for (int rep = 0; rep < launches && e == hipSuccess; ++rep) e = one();
+      (void)hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e != hipSuccess) {
+        rc = fail(LBM_E_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      split_ms = std::min(split_ms, (double)ms / launches);
+    }
+    if (ms_out && split_ms < 1e299) ms_out[2 * LBM_TUNE_NROWS] = split_ms;
+    if (split_ms < best_ms) {
+      best_ms = split_ms;
+      best_path = LBM_PATH_SPLIT;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->path = start_path;
@@ -927,13 +962,52 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 namespace {
 
 struct AdjLayout {
-  size_t pop = 0, field = 0, dropb = 0, slot = 0;  // bytes of a saved state and of its parts
+  size_t pop = 0, field = 0, dropb = 0;  // bytes of the parts of a saved state
+  size_t slot = 0;   // a whole state: populations, phi, c, droplet table, step counter
+  size_t sslot = 0;  // what the adjoint step reads of a recomputed state: phi, c, droplet table
   int64_t ncp = 0, nodes = 0;
   int every = 0, nb = 0;
   size_t off_cp = 0, off_seg = 0, off_final = 0, off_fwd = 0, off_adj = 0, off_part = 0, total = 0;
 };
 
 constexpr int ADJ_TMP_PLANES = 24;  // gradient planes and intermediate adjoints of one backward step
+// The adjoint step reads the first ADJ_FWD_PLANES stage planes of the forward step (mu .. X^{n+1/2}).  The
+// stage export writes twice as many, so the exports of the steps of an interval are laid out
+// ADJ_FWD_PLANES planes apart: the later step's export overwrites only the unread second half of the earlier.
+constexpr int ADJ_FWD_PLANES = 11;
+static_assert(2 * ADJ_FWD_PLANES == LBM_NSTAGE, "stage planes of the adjoint's forward record");
+
+// Up to five byte ranges (multiples of 8 bytes) copied by one launch.
+struct CopyList {
+  const uint64_t* src[5];
+  uint64_t* dst[5];
+  int64_t n[5];  // 8-byte words
+  int nseg;
+};
+
+__global__ void __launch_bounds__(256) k_copy_list(CopyList L) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int s = 0; s < L.nseg; ++s)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n[s]; i += stride)
+      L.dst[s][i] = L.src[s][i];
+}
+
+struct CopyBuilder {
+  CopyList L{};
+  int64_t most = 0;
+  void add(const void* src, void* dst, size_t bytes) {
+    L.src[L.nseg] = static_cast<const uint64_t*>(src);
+    L.dst[L.nseg] = static_cast<uint64_t*>(dst);
+    L.n[L.nseg] = (int64_t)(bytes / 8);
+    most = std::max(most, L.n[L.nseg]);
+    ++L.nseg;
+  }
+  hipError_t launch(hipStream_t s) const {
+    const int blocks = (int)std::min<int64_t>(std::max<int64_t>((most + 255) / 256, 1), 2048);
+    hipLaunchKernelGGL(k_copy_list, dim3(blocks), dim3(256), 0, s, L);
+    return hipGetLastError();
+  }
+};
 
 int adj_check(const lbm_ctx* c, int32_t drop, int64_t nsteps, int32_t every) {
   if (!c) return fail(LBM_E_INVAL, "null context");
@@ -959,30 +1033,32 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int every) {
   A.field = (size_t)d.pstride * c->L.elem;
   A.dropb = sizeof(DropDev) * (size_t)std::max(1, (int)d.ndrop);
   A.slot = align_up(A.pop + 2 * A.field + A.dropb + sizeof(int64_t), ALIGN);
+  A.sslot = align_up(2 * A.field + A.dropb, ALIGN);
   size_t off = 0;
   A.off_cp = off;    off += A.slot * (size_t)A.ncp;
-  A.off_seg = off;   off += A.slot * (size_t)every;
+  A.off_seg = off;   off += A.sslot * (size_t)every;
   A.off_final = off; off += A.slot;
-  A.off_fwd = off;   off = align_up(off + sizeof(double) * LBM_NSTAGE * (size_t)A.nodes, ALIGN);
+  A.off_fwd = off;
+  off = align_up(off + sizeof(double) * ADJ_FWD_PLANES * (size_t)(every + 1) * (size_t)A.nodes, ALIGN);
   A.off_adj = off;   off = align_up(off + c->L.elem * (size_t)(22 + ADJ_TMP_PLANES) * A.nodes, ALIGN);
   A.off_part = off;  off = align_up(off + sizeof(double) * (size_t)A.nb * (size_t)(nsteps + 1), ALIGN);
   A.total = off;
   return A;
 }
 
-// Copy the state of the single lattice (current buffers, droplet table, step counter) to or from a slot.
+// Copy the state of the single lattice (current buffers, droplet table, step counter) to or from a whole
+// slot, in one launch.
 int adj_save(lbm_ctx* c, const AdjLayout& A, char* slot) {
   const InstDev& d = c->L.inst[0];
   char* pool = static_cast<char*>(c->pool());
   const size_t e = c->L.elem;
-  HIPCHK(hipMemcpyAsync(slot, pool + d.off_f[c->parity] * e, A.pop, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(slot + A.pop, pool + d.off_phi[c->parity] * e, A.field, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(slot + A.pop + A.field, pool + d.off_c[c->parity] * e, A.field, hipMemcpyDeviceToDevice,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(slot + A.pop + 2 * A.field, c->d_drops(), sizeof(DropDev) * d.ndrop, hipMemcpyDeviceToDevice,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(slot + A.pop + 2 * A.field + A.dropb, c->d_step(), sizeof(int64_t), hipMemcpyDeviceToDevice,
-                        c->stream));
+  CopyBuilder b;
+  b.add(pool + d.off_f[c->parity] * e, slot, A.pop);
+  b.add(pool + d.off_phi[c->parity] * e, slot + A.pop, A.field);
+  b.add(pool + d.off_c[c->parity] * e, slot + A.pop + A.field, A.field);
+  b.add(c->d_drops(), slot + A.pop + 2 * A.field, sizeof(DropDev) * d.ndrop);
+  b.add(c->d_step(), slot + A.pop + 2 * A.field + A.dropb, sizeof(int64_t));
+  HIPCHK(b.launch(c->stream));
   return LBM_OK;
 }
 
@@ -990,20 +1066,32 @@ int adj_load(lbm_ctx* c, const AdjLayout& A, const char* slot, int64_t step) {
   const InstDev& d = c->L.inst[0];
   char* pool = static_cast<char*>(c->pool());
   const size_t e = c->L.elem;
-  HIPCHK(hipMemcpyAsync(pool + d.off_f[c->parity] * e, slot, A.pop, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(pool + d.off_phi[c->parity] * e, slot + A.pop, A.field, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(pool + d.off_c[c->parity] * e, slot + A.pop + A.field, A.field, hipMemcpyDeviceToDevice,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(c->d_drops(), slot + A.pop + 2 * A.field, sizeof(DropDev) * d.ndrop, hipMemcpyDeviceToDevice,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(c->d_step(), slot + A.pop + 2 * A.field + A.dropb, sizeof(int64_t), hipMemcpyDeviceToDevice,
-                        c->stream));
+  CopyBuilder b;
+  b.add(slot, pool + d.off_f[c->parity] * e, A.pop);
+  b.add(slot + A.pop, pool + d.off_phi[c->parity] * e, A.field);
+  b.add(slot + A.pop + A.field, pool + d.off_c[c->parity] * e, A.field);
+  b.add(slot + A.pop + 2 * A.field, c->d_drops(), sizeof(DropDev) * d.ndrop);
+  b.add(slot + A.pop + 2 * A.field + A.dropb, c->d_step(), sizeof(int64_t));
+  HIPCHK(b.launch(c->stream));
   c->step = step;
   return LBM_OK;
 }
 
-const DropDev* adj_slot_drops(const AdjLayout& A, const char* slot) {
-  return reinterpret_cast<const DropDev*>(slot + A.pop + 2 * A.field);
+// phi, c and the droplet table of the current state into a segment slot (what the adjoint step reads).
+int adj_save_seg(lbm_ctx* c, const AdjLayout& A, char* sslot) {
+  const InstDev& d = c->L.inst[0];
+  char* pool = static_cast<char*>(c->pool());
+  const size_t e = c->L.elem;
+  CopyBuilder b;
+  b.add(pool + d.off_phi[c->parity] * e, sslot, A.field);
+  b.add(pool + d.off_c[c->parity] * e, sslot + A.field, A.field);
+  b.add(c->d_drops(), sslot + 2 * A.field, sizeof(DropDev) * d.ndrop);
+  HIPCHK(b.launch(c->stream));
+  return LBM_OK;
+}
+
+const DropDev* adj_seg_drops(const AdjLayout& A, const char* sslot) {
+  return reinterpret_cast<const DropDev*>(sslot + 2 * A.field);
 }
 
 template <typename T>
@@ -1014,9 +1102,14 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
   const int every = c->adj.every, drop = c->adj.drop, nd = d.ndrop;
   int rc;
   if ((rc = adj_save(c, A, w + A.off_final)) != LBM_OK) return rc;
+  // stage planes of step k0 + j of the current interval start ADJ_FWD_PLANES * j planes into the record
   double* fwd = reinterpret_cast<double*>(w + A.off_fwd);
-  const AdjFwd F{fwd + 0 * M, fwd + 1 * M, fwd + 2 * M, fwd + 3 * M, fwd + 4 * M, fwd + 5 * M,
-                 fwd + 6 * M, fwd + 7 * M, fwd + 8 * M, fwd + 9 * M, fwd + 10 * M};
+  auto fwd_rec = [&](int64_t j) { return fwd + (size_t)ADJ_FWD_PLANES * (size_t)j * (size_t)M; };
+  auto fwd_at = [&](int64_t j) {
+    const double* f = fwd_rec(j);
+    return AdjFwd{f + 0 * M, f + 1 * M, f + 2 * M, f + 3 * M, f + 4 * M,  f + 5 * M,
+                  f + 6 * M, f + 7 * M, f + 8 * M, f + 9 * M, f + 10 * M};
+  };
   T* adj = reinterpret_cast<T*>(w + A.off_adj);
   T* lam[2] = {adj, adj + 11 * M};  // adjoint state (f 9 planes, phi, c) at n and at n + 1
   T* tmp = adj + 22 * M;
@@ -1035,11 +1128,10 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
   m.coef = d.coef;
   m.yper = d.yper;
   m.ramp = 0.0;
-  auto planes = [&](T* in, T* out) {
+  auto planes = [&](const char* sslot, T* in, T* out) {
     AdjPlanes<T> p;
-    T* base = reinterpret_cast<T*>(c->pool());
-    p.phi = base + d.off_phi[c->parity];
-    p.c = base + d.off_c[c->parity];
+    p.phi = reinterpret_cast<const T*>(sslot);
+    p.c = reinterpret_cast<const T*>(sslot + A.field);
     p.pitch = d.pitch;
     p.fb1 = in;
     p.pb1 = in + 9 * M;
@@ -1057,10 +1149,12 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
   bool seeded = false;
   for (int64_t s = A.ncp - 1; s >= 0; --s) {
     const int64_t k0 = s * every, k1 = std::min<int64_t>(N, k0 + every);
-    // recompute the states of the segment from its checkpoint, keeping each one
+    // recompute the interval from its checkpoint, keeping phi, c, the droplet table and the stage planes
+    // of every step
     if ((rc = adj_load(c, A, w + A.off_cp + (size_t)s * A.slot, n0 + k0)) != LBM_OK) return rc;
     for (int64_t k = k0; k < k1; ++k) {
-      if ((rc = adj_save(c, A, w + A.off_seg + (size_t)(k - k0) * A.slot)) != LBM_OK) return rc;
+      if ((rc = adj_save_seg(c, A, w + A.off_seg + (size_t)(k - k0) * A.sslot)) != LBM_OK) return rc;
+      HIPCHK((debug_launch<T, T>(c, 0, fwd_rec(k - k0))));
       hipError_t e = enqueue_step_any(c, c->parity);
       if (e != hipSuccess) return fail(LBM_E_HIP, std::string("adjoint recompute: ") + hipGetErrorString(e));
       c->parity ^= 1;
@@ -1068,9 +1162,9 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
     }
     if (!seeded) {
       // loss x_CM^N - x_CM^{n0}: seed d/d phi^N over the droplet's nodes (centres of step N - 1)
-      const char* last = w + A.off_seg + (size_t)(k1 - 1 - k0) * A.slot;
+      const char* last = w + A.off_seg + (size_t)(k1 - 1 - k0) * A.sslot;
       std::vector<DropDev> prev(nd), now(nd);
-      HIPCHK(hipMemcpyAsync(prev.data(), adj_slot_drops(A, last), sizeof(DropDev) * nd, hipMemcpyDeviceToHost,
+      HIPCHK(hipMemcpyAsync(prev.data(), adj_seg_drops(A, last), sizeof(DropDev) * nd, hipMemcpyDeviceToHost,
                             c->stream));
       HIPCHK(hipMemcpyAsync(now.data(), c->d_drops(), sizeof(DropDev) * nd, hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -1078,7 +1172,7 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
       if (dx >= 0.5 * d.nx) dx -= d.nx;
       if (dx < -0.5 * d.nx) dx += d.nx;
       const T* phiN = reinterpret_cast<const T*>(c->pool()) + d.off_phi[c->parity];
-      HIPCHK(launch_adjoint_seed<T>(c->stream, 0, m, phiN, d.pitch, adj_slot_drops(A, last), nd, drop, 0.0, 1.0,
+      HIPCHK(launch_adjoint_seed<T>(c->stream, 0, m, phiN, d.pitch, adj_seg_drops(A, last), nd, drop, 0.0, 1.0,
                                     lam[cur], lam[cur] + 9 * M, lam[cur] + 10 * M, part));
       std::vector<double> hp(A.nb);
       HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * A.nb, hipMemcpyDeviceToHost, c->stream));
@@ -1086,19 +1180,18 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
       double sw = 0.0;
       for (double v : hp) sw += v;
       if (!(sw > 0.0)) return fail(LBM_E_STATE, "the droplet has no nodes with phi >= 0 at the end of the run");
-      HIPCHK(launch_adjoint_seed<T>(c->stream, 1, m, phiN, d.pitch, adj_slot_drops(A, last), nd, drop, dx, sw,
+      HIPCHK(launch_adjoint_seed<T>(c->stream, 1, m, phiN, d.pitch, adj_seg_drops(A, last), nd, drop, dx, sw,
                                     lam[cur], lam[cur] + 9 * M, lam[cur] + 10 * M, part));
       seeded = true;
     }
     // backward through the segment, latest step first
     for (int64_t k = k1 - 1; k >= k0; --k) {
-      const char* slot = w + A.off_seg + (size_t)(k - k0) * A.slot;
-      if ((rc = adj_load(c, A, slot, n0 + k)) != LBM_OK) return rc;
-      HIPCHK((debug_launch<T, T>(c, 0, fwd)));
+      const char* sslot = w + A.off_seg + (size_t)(k - k0) * A.sslot;
       const double tn = (double)(n0 + k);
       m.ramp = tn < g.t_star ? tn : g.t_star;
-      const AdjPlanes<T> p = planes(lam[cur], lam[cur ^ 1]);
-      HIPCHK(launch_adjoint_step<T>(c->stream, m, F, p, adj_slot_drops(A, slot), nd, part + (size_t)(k + 1) * A.nb));
+      const AdjPlanes<T> p = planes(sslot, lam[cur], lam[cur ^ 1]);
+      HIPCHK(launch_adjoint_step<T>(c->stream, m, fwd_at(k - k0), p, adj_seg_drops(A, sslot), nd,
+                                    part + (size_t)(k + 1) * A.nb));
       cur ^= 1;
     }
   }

@@ -256,7 +256,7 @@ def lbm_tune_rows():
 def lbm_autotune(ctx: int, launches: int, both_paths: bool = True):
     """Returns (rows, path, {"fused:rows" / "wave:rows": ms per launch}) for the candidates tried."""
     rows, path = C.c_int32(0), C.c_int32(0)
-    ms = np.zeros(2 * LBM_TUNE_NROWS)
+    ms = np.zeros(2 * LBM_TUNE_NROWS + 1)
     _check(load_library().lbm_autotune(C.c_void_p(ctx), int(launches), int(bool(both_paths)), C.byref(rows),
                                        C.byref(path), _dptr(ms)))
     cand = lbm_tune_rows()
@@ -265,6 +265,8 @@ def lbm_autotune(ctx: int, launches: int, both_paths: bool = True):
         for k, r in enumerate(cand):
             if ms[pi * LBM_TUNE_NROWS + k] >= 0:
                 times[f"{name}:{r}"] = float(ms[pi * LBM_TUNE_NROWS + k])
+    if ms[2 * LBM_TUNE_NROWS] >= 0:
+        times["split"] = float(ms[2 * LBM_TUNE_NROWS])
     return int(rows.value), int(path.value), times
 
 
@@ -376,8 +378,8 @@ class Sim:
         lbm_set_seg_rows(self.ctx, rows)
 
     def autotune(self, launches: int = 5, both_paths: bool = True):
-        """Pick the sweeping kernel (fused or wave) and its segment height by timing each candidate (the
-        state is unchanged).  Returns (rows, path, times)."""
+        """Pick the kernel path (fused or wave sweep with its segment height, or the split pair) by timing each
+        candidate (the state is unchanged).  Returns (rows, path, times)."""
         return lbm_autotune(self.ctx, launches, both_paths)
 
     def time_kernels(self, n: int) -> Dict[str, float]:
@@ -400,10 +402,10 @@ class Sim:
 
 
 def com_displacement(A0, psi0, params: dict, phi0: np.ndarray, drops: List[dict], nsteps: int, every: int = 100,
-                     drop: int = 0, precision: int = LBM_FP64, path: int = LBM_PATH_FUSED):
+                     drop: int = 0, precision: int = LBM_FP64, path: int = -1):
     """J = x-displacement of droplet `drop`'s centre of mass over nsteps steps as a differentiable function of the
     production rate A0 (0-d tensor) and the initial surfactant field psi0 ([ny][nx] tensor); the gradient comes
-    from the library's adjoint (lbm_adjoint_backward)."""
+    from the library's adjoint (lbm_adjoint_backward).  path -1 picks the kernel path with the autotuner."""
     return _ComDisplacement.apply(A0, psi0, params, phi0, drops, nsteps, every, drop, precision, path)
 
 
@@ -415,7 +417,10 @@ def _make_com_displacement():
         def forward(ctx, A0, psi0, params, phi0, drops, nsteps, every, drop, precision, path):
             p = dict(params, A0=float(A0.detach().cpu()))
             c0 = np.ascontiguousarray(psi0.detach().cpu().numpy(), dtype=np.float64)
-            sim = Sim([p], [phi0], [c0], [drops], precision=precision, graph_steps=20, path=path)
+            sim = Sim([p], [phi0], [c0], [drops], precision=precision, graph_steps=20,
+                      path=LBM_PATH_FUSED if path < 0 else path)
+            if path < 0:
+                sim.autotune(10, both_paths=True)
             J = sim.adjoint_forward(drop, nsteps, every)
             ctx.sim = sim
             ctx.psi_device, ctx.psi_dtype = psi0.device, psi0.dtype

@@ -12,7 +12,8 @@ membership, the upwind sides and the droplet masks fixed; a perturbation of 1e-6
   adjoint only erratically, 1e-4 .. 1e-2 at h = 1e-4 .. 1e-7 for such directions, against 2e-6 at h = 1e-6
   for directions near the droplet);
 * FP32 adjoint against the FP64 one; the torch.autograd wrapper; the state is restored and a second
-  backward pass repeats the first bit for bit.
+  backward pass repeats the first bit for bit; the checkpoint interval and the kernel path leave the gradients
+  unchanged bit for bit.
 """
 import numpy as np
 import pytest
@@ -145,6 +146,19 @@ def test_state_restored_and_backward_repeatable():
     ref = gpu_J(w, w.c0, nsteps=120)
     assert J == ref
     s.close()
+
+
+@pytest.mark.parametrize("every,path", [(1, 1), (7, 2), (100, 0)])
+def test_interval_and_path_leave_gradients_unchanged(every, path):
+    """The checkpoint interval (dividing the run or not, longer than it) and the kernel path only change the
+    schedule of the recompute: the gradients are bit for bit those of a run with interval 20 on the fused path."""
+    w = W.c2_single_active(n=64, seed=49)
+    w.params["A0"] = 2e-6
+    s0, J0, dA0_0, dc0_0 = adjoint(w, 60, 20, path=0)
+    s0.close()
+    s, J, dA0, dc0 = adjoint(w, 60, every, path=path)
+    s.close()
+    assert J == J0 and dA0 == dA0_0 and np.array_equal(dc0, dc0_0)
 
 
 def test_torch_autograd_wrapper():

@@ -296,6 +296,31 @@ def test_segment_heights_agree_bitwise_and_autotune_keeps_state(path):
     s.close()
 
 
+def test_autotune_over_all_paths_keeps_state():
+    """With both_paths the autotuner also times the split pair; whatever it picks, the state, droplets and
+    step counter are untouched and the run continues bit for bit (the paths agree bitwise)."""
+    w = W.c5_emulsion(n=200, ndrop=3, R=12.0, seed=32)
+    ref = gpu_sim(w, graph_steps=0, path=0)
+    ref.step(24)
+    want = ref.fields()
+    ref.close()
+    s = gpu_sim(w, graph_steps=0, path=1)
+    s.step(5)
+    before, drops_before, step_before = s.fields(), s.droplets(), s.step_count
+    rows, path, times = s.autotune(3, both_paths=True)
+    assert path in (0, 1, 2) and "split" in times and any(k.startswith("wave:") for k in times)
+    assert s.path == path and (path == 1 or rows in s.tune_rows())
+    after = s.fields()
+    for k in FIELDS:
+        assert np.array_equal(before[k], after[k]), k
+    assert s.droplets() == drops_before and s.step_count == step_before
+    s.step(19)
+    f = s.fields()
+    for k in FIELDS:
+        assert np.array_equal(f[k], want[k]), k
+    s.close()
+
+
 def test_fp32_batched_instances_match_single_runs():
     """Batching does not change any instance's arithmetic (FP32, uneven sizes)."""
     lbm = _lbm()
