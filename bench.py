@@ -52,7 +52,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, precision: str, seg_rows):
+def measured_traffic(kernel: str, workload: str, precision: str, strip_w, seg_rows):
     """HBM bytes per launch from the committed rocprofv3 counter summary (profiles/traffic.json), if it
     was taken on the current kernel source and the same strip height (null otherwise)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -63,7 +63,7 @@ def measured_traffic(kernel: str, workload: str, precision: str, seg_rows):
         return None
     if data.get("kernel_source_hash") != kernel_source_hash():
         return None
-    ent = data.get("entries", {}).get(f"{kernel}:{workload}:{precision}:{seg_rows}")
+    ent = data.get("entries", {}).get(f"{kernel}:{workload}:{precision}:{strip_w}x{seg_rows}")
     return None if ent is None else ent.get("bytes_per_launch")
 
 
@@ -90,8 +90,9 @@ def time_steps(sim, steps, warmup):
     return ms, wall
 
 
-def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=-1, seg_rows=0):
-    """path -1: the autotuner picks the kernel path (fused or wave sweep with its strip height, or split)."""
+def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=-1, seg_rows=0, strip_w=0):
+    """path -1: the autotuner picks the kernel path (fused or wave sweep with its strip width and height, or
+    split).  seg_rows / strip_w 0: autotuned (with a given height, width 0 keeps the default)."""
     from paper_1711_10984_amd import lbm
     sim = build_sim(workloads, precision, graph_steps, 0 if path < 0 else path)
     tune_ms = {}
@@ -104,8 +105,11 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
         if path < 0:
             path = 0
         sim.set_seg_rows(seg_rows)
+        if strip_w:
+            sim.set_strip_width(strip_w)
     else:
         seg_rows = None
+    strip_w = sim.strip_width if seg_rows is not None else None
     nodes = sum(w.nodes for w in workloads)
     ms, wall = time_steps(sim, steps, warmup)
     obs = sim.observables(0)
@@ -118,10 +122,11 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     step_bytes = alg_bytes_per_node("step", precision) * nodes
     step_gbs = step_bytes / (ms * 1e-3 / steps) / 1e9
     prec = PREC_NAMES[precision]
-    traffic = measured_traffic(dom, label, prec, seg_rows)
+    traffic = measured_traffic(dom, label, prec, strip_w, seg_rows)
     return {
         "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
-        "kernel_ms": per_kernel, "seg_rows": seg_rows, "autotune_ms": tune_ms, "path": PATH_NAMES[path],
+        "kernel_ms": per_kernel, "seg_rows": seg_rows, "strip_width": strip_w, "autotune_ms": tune_ms,
+        "path": PATH_NAMES[path],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": per_kernel[dom]},
@@ -181,6 +186,7 @@ def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
     for _ in range(repeats):
         sim = lbm.Sim([w.param_dict()], [w.phi0], [w.c0], [w.drop_dicts()], precision=precision, graph_steps=20)
         rows, path, _ = sim.autotune(10, both_paths=True)
+        width = sim.strip_width
         sim.sync()
         t0 = time.perf_counter()
         sim.adjoint_forward(0, nsteps, every)
@@ -191,6 +197,7 @@ def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
         best_f, best_b = min(best_f, t1 - t0), min(best_b, t2 - t1)
     return {"workload": f"{w.name}, {nsteps} steps, checkpoint every {every}", "nodes": w.nodes,
             "path": PATH_NAMES[path], "seg_rows": rows if path != 1 else None,
+            "strip_width": width if path != 1 else None,
             "forward_ms_per_step": round(best_f / nsteps * 1e3, 5), "backward_ms_per_step": round(best_b / nsteps * 1e3, 5),
             "backward_mlups": round(w.nodes * nsteps / best_b / 1e6, 1),
             "backward_over_forward": round(best_b / best_f, 2)}
@@ -223,7 +230,9 @@ def main():
     ap.add_argument("--path", type=int, default=-1, choices=[-1] + sorted(PATH_NAMES),
                     help="-1: autotuned choice of 0, 1 or 2; 0: fused sweep kernel; 1: split LB + FD kernels; "
                          "2: wavefront-per-strip sweep kernel")
-    ap.add_argument("--seg-rows", type=int, default=0, help="fused-kernel strip height (0: autotune)")
+    ap.add_argument("--seg-rows", type=int, default=0, help="sweeping-kernel strip height (0: autotune)")
+    ap.add_argument("--strip-width", type=int, default=0,
+                    help="sweeping-kernel strip width with --seg-rows (0: the library default)")
     ap.add_argument("--only", choices=["fp64", "fp32", "fp16", "c3", "adjoint"], default=None,
                     help="run one configuration (for profiling); the JSON line then reports that one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -258,22 +267,23 @@ def main():
         wl, prec, label = {"fp32": ([c5], lbm.LBM_FP32, "c5"), "fp16": ([c5], lbm.LBM_FP16, "c5"),
                            "c3": (W.c3_batch(), lbm.LBM_FP32, "c3")}[args.only]
         r = measure(wl, prec, args.steps, args.warmup, args.graph_steps, label, args.prof_steps, args.path,
-                    args.seg_rows)
+                    args.seg_rows, args.strip_width)
         print(json.dumps({"only": args.only, "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
                           "roofline": r["roofline"], "kernel_ms": r["kernel_ms"], "seg_rows": r["seg_rows"],
-                          "path": r["path"]}),
+                          "strip_width": r["strip_width"], "path": r["path"]}),
               flush=True)
         return
     main_res = measure([c5], lbm.LBM_FP64, args.steps, args.warmup, args.graph_steps, "c5", args.prof_steps,
-                       args.path, args.seg_rows)
+                       args.path, args.seg_rows, args.strip_width)
     variants = {}
     if not args.no_variants and args.only is None:
         variants["fp32_2048"] = measure([c5], lbm.LBM_FP32, args.steps, args.warmup, args.graph_steps, "c5",
-                                        args.prof_steps, args.path, args.seg_rows)
+                                        args.prof_steps, args.path, args.seg_rows, args.strip_width)
         variants["batched_c3_fp32"] = measure(W.c3_batch(), lbm.LBM_FP32, args.steps, args.warmup,
-                                              args.graph_steps, "c3", args.prof_steps, args.path, args.seg_rows)
+                                              args.graph_steps, "c3", args.prof_steps, args.path, args.seg_rows,
+                                              args.strip_width)
         variants["fp16_storage_2048"] = measure([c5], lbm.LBM_FP16, args.steps, args.warmup, args.graph_steps,
-                                                "c5", args.prof_steps, args.path, args.seg_rows)
+                                                "c5", args.prof_steps, args.path, args.seg_rows, args.strip_width)
     for v in variants.values():
         v["gain_over_fp64"] = round(v["mlups"] / main_res["mlups"], 3)
     out = {
@@ -295,12 +305,14 @@ def main():
         "roofline": main_res["roofline"],
         "step_roofline": main_res["step_roofline"],
         "kernel_ms": main_res["kernel_ms"],
-        "autotune": {"seg_rows": main_res["seg_rows"], "path": main_res["path"],
+        "autotune": {"seg_rows": main_res["seg_rows"], "strip_width": main_res["strip_width"],
+                     "path": main_res["path"],
                      "ms_per_launch": main_res["autotune_ms"]},
         "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
                          "nodes": v["nodes"], "precision": v["precision"], "gain_over_fp64": v["gain_over_fp64"],
                          "roofline": v["roofline"], "step_roofline": v["step_roofline"],
-                         "kernel_ms": v["kernel_ms"], "seg_rows": v["seg_rows"], "path": v["path"]}
+                         "kernel_ms": v["kernel_ms"], "seg_rows": v["seg_rows"], "strip_width": v["strip_width"],
+                         "path": v["path"]}
                      for k, v in variants.items()},
         "kernel_source_hash": kernel_source_hash(),
     }

@@ -186,20 +186,33 @@ int32_t lbm_get_path(const lbm_ctx* ctx);
 int lbm_set_seg_rows(lbm_ctx* ctx, int32_t rows);
 int32_t lbm_get_seg_rows(const lbm_ctx* ctx);
 
+/* Columns owned per strip of the sweeping kernels, LBM_STRIP_W_MIN .. LBM_STRIP_W_MAX (default 54, the
+ * most a 64-lane wavefront covers with its 5-column halo on each side; LBM_E_INVAL outside).  Only the work
+ * decomposition changes: the fields are identical for every width (the centre-of-mass partial sums are
+ * added in a different order).  Synchronous. */
+#define LBM_STRIP_W_MIN 32
+#define LBM_STRIP_W_MAX 54
+int lbm_set_strip_width(lbm_ctx* ctx, int32_t width);
+int32_t lbm_get_strip_width(const lbm_ctx* ctx);
+
 /* The LBM_TUNE_NROWS segment heights tried by lbm_autotune, ascending (static array). */
 #define LBM_TUNE_NROWS 16
 const int32_t* lbm_tune_rows(void);
+/* The LBM_TUNE_NWIDTHS strip widths tried by lbm_autotune (static array). */
+#define LBM_TUNE_NWIDTHS 1
+const int32_t* lbm_tune_widths(void);
 
-/* Autotuner: time `launches` back-to-back launches of the sweeping kernel for each candidate height
- * (heights giving the same number of segments as a smaller one are skipped) -- for both sweeping
- * kernels (LBM_PATH_FUSED, LBM_PATH_WAVE) and the split pair (LBM_PATH_SPLIT, no height) when
- * both_paths != 0, else for the current sweeping path only -- and set the path and height of the fastest.
+/* Autotuner: time `launches` back-to-back launches of the sweeping kernel for each candidate strip width
+ * and height (heights giving the same number of segments as a smaller one at that width are skipped) -- for
+ * both sweeping kernels (LBM_PATH_FUSED, LBM_PATH_WAVE) and the split pair (LBM_PATH_SPLIT, no width or
+ * height) when both_paths != 0, else for the current sweeping path only -- and set the path, width and
+ * height of the fastest (the width is then read with lbm_get_strip_width).
  * The trial launches read the current state and write only scratch (the inactive halves of the ping-pong
  * buffers, the velocity planes and the centre-of-mass partials): the state, the droplet table and the step
  * counter are unchanged.  Called on the split path with both_paths == 0, nothing is tried.
- * rows_out, path_out (may be NULL) receive the choice; ms_out (may be NULL, 2 * LBM_TUNE_NROWS + 1 entries,
- * [fused heights..., wave heights..., split]) the average ms per launch (per step pair for the split
- * path) of each candidate (-1 if not tried).  Synchronous. */
+ * rows_out, path_out (may be NULL) receive the choice; ms_out (may be NULL, 2 * LBM_TUNE_NWIDTHS *
+ * LBM_TUNE_NROWS + 1 entries: [path (fused, wave)][width][height], then split) the average ms per launch
+ * (per step pair for the split path) of each candidate (-1 if not tried).  Synchronous. */
 int lbm_autotune(lbm_ctx* ctx, int32_t launches, int32_t both_paths, int32_t* rows_out, int32_t* path_out,
                  double* ms_out);
 

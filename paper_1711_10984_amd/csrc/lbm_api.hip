@@ -52,7 +52,7 @@ struct Layout {
   std::vector<TileDev> tiles;  // split-kernel tiles in launch order (XCD-aware), padded with inst = -1
   std::vector<TileDev> segs;   // fused-kernel strips in launch order
   int ntiles = 0, nsegs = 0, ndrop_total = 0, max_nd = 0, obs_stride = 0;
-  int max_segs = 0, max_seg_launch = 0, seg_rows = 0;
+  int max_segs = 0, max_seg_launch = 0, seg_rows = 0, strip_w = FUSED_TX;
   int64_t max_nodes = 0;
   size_t off_pool = 0, off_inst = 0, off_tiles = 0, off_segs = 0, off_drops = 0, off_part = 0, off_mask = 0,
          off_step = 0, off_obs = 0, off_dbg = 0, total = 0;
@@ -104,8 +104,9 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.tiles_x[TILING_SPLIT] = (c.nx + TILE_X - 1) / TILE_X;
     d.tiles_y[TILING_SPLIT] = (c.ny + TILE_Y - 1) / TILE_Y;
     d.tile_base[TILING_SPLIT] = tile_base;
-    d.tiles_x[TILING_FUSED] = (c.nx + FUSED_TX - 1) / FUSED_TX;
-    d.tiles_y[TILING_FUSED] = (c.ny + SEG_ROWS_MIN - 1) / SEG_ROWS_MIN;  // upper bound; see set_segments
+    // upper bounds (narrowest strips, shortest segments); see set_segments
+    d.tiles_x[TILING_FUSED] = (c.nx + STRIP_W_MIN - 1) / STRIP_W_MIN;
+    d.tiles_y[TILING_FUSED] = (c.ny + SEG_ROWS_MIN - 1) / SEG_ROWS_MIN;
     d.tile_base[TILING_FUSED] = seg_base;
     d.drop_base = drop_base;
     const int64_t plane = (int64_t)c.ny * d.pitch;
@@ -173,7 +174,7 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     for (int t = 0; t < count; ++t) out[(size_t)(t % chunk) * nxcd + t / chunk] = natural[t];
   };
   build_list(TILING_SPLIT, TILE_X, TILE_Y, L.ntiles, L.tiles);
-  L.max_segs = L.nsegs;  // strips of the smallest segment height: sizes the strip list and partials
+  L.max_segs = L.nsegs;  // strips of the narrowest width and smallest height: sizes the strip list and partials
   L.max_seg_launch = ((L.nsegs + 7) / 8) * 8;
   (void)build_list;
   size_t off = 0;
@@ -194,14 +195,16 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
   L.total = off;
 }
 
-// Fused-kernel strips for a segment height: per-instance counts, natural indices, partial offsets and
-// the launch list (XCD-aware order).  Fits in the regions sized for SEG_ROWS_MIN.
-void set_segments(Layout& L, int seg_rows) {
+// Sweeping-kernel strips for a strip width and segment height: per-instance counts, natural indices,
+// partial offsets and the launch list (XCD-aware order).  Fits in the regions sized for STRIP_W_MIN and
+// SEG_ROWS_MIN.
+void set_segments(Layout& L, int seg_rows, int strip_w) {
   int base = 0;
   int64_t part = 0;
   for (auto& d : L.inst) {
     d.seg_rows = seg_rows;
-    d.tiles_x[TILING_FUSED] = (d.nx + FUSED_TX - 1) / FUSED_TX;
+    d.strip_w = strip_w;
+    d.tiles_x[TILING_FUSED] = (d.nx + strip_w - 1) / strip_w;
     d.tiles_y[TILING_FUSED] = (d.ny + seg_rows - 1) / seg_rows;
     d.tile_base[TILING_FUSED] = base;
     d.part_base[TILING_FUSED] = part;
@@ -210,13 +213,14 @@ void set_segments(Layout& L, int seg_rows) {
   }
   L.nsegs = base;
   L.seg_rows = seg_rows;
+  L.strip_w = strip_w;
   std::vector<TileDev> natural;
   natural.reserve(base);
   for (size_t i = 0; i < L.inst.size(); ++i) {
     const InstDev& d = L.inst[i];
     for (int ty = 0; ty < d.tiles_y[TILING_FUSED]; ++ty)
       for (int tx = 0; tx < d.tiles_x[TILING_FUSED]; ++tx)
-        natural.push_back(TileDev{(int32_t)i, tx * FUSED_TX, ty * seg_rows, (int32_t)natural.size()});
+        natural.push_back(TileDev{(int32_t)i, tx * strip_w, ty * seg_rows, (int32_t)natural.size()});
   }
   const int nxcd = 8;
   const int chunk = (base + nxcd - 1) / nxcd;
@@ -527,6 +531,19 @@ int read_drops(lbm_ctx* c, int inst, std::vector<DropDev>& out) {
   return LBM_OK;
 }
 
+// Rebuild the strip list for a segment height and strip width and upload it.
+int apply_segments(lbm_ctx* c, int rows, int width) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  destroy_graphs(c);
+  set_segments(c->L, rows, width);
+  HIPCHK(hipMemcpyAsync(c->d_inst(), c->L.inst.data(), sizeof(InstDev) * c->L.inst.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_segs(), c->L.segs.data(), sizeof(TileDev) * c->L.segs.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -563,7 +580,7 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
   }
   lbm_ctx* c = new lbm_ctx();
   make_layout(ninst, cfgs, ndrop, c->L);
-  set_segments(c->L, SEG_ROWS_DEFAULT);
+  set_segments(c->L, SEG_ROWS_DEFAULT, FUSED_TX);
   if (workspace_bytes < c->L.total) {
     delete c;
     return fail(LBM_E_NOMEM, "workspace smaller than lbm_workspace_bytes()");
@@ -793,23 +810,28 @@ int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
   return LBM_OK;
 }
 
+
 int lbm_set_seg_rows(lbm_ctx* c, int32_t rows) {
   if (!c) return fail(LBM_E_INVAL, "null context");
   if (rows < SEG_ROWS_MIN || rows > SEG_ROWS_MAX)
     return fail(LBM_E_INVAL, "segment height must lie in [" + std::to_string(SEG_ROWS_MIN) + ", " +
                                  std::to_string(SEG_ROWS_MAX) + "]");
-  HIPCHK(hipStreamSynchronize(c->stream));
-  destroy_graphs(c);
-  set_segments(c->L, rows);
-  HIPCHK(hipMemcpyAsync(c->d_inst(), c->L.inst.data(), sizeof(InstDev) * c->L.inst.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  HIPCHK(hipMemcpyAsync(c->d_segs(), c->L.segs.data(), sizeof(TileDev) * c->L.segs.size(), hipMemcpyHostToDevice,
-                        c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return apply_segments(c, rows, c->L.strip_w);
 }
 
 int32_t lbm_get_seg_rows(const lbm_ctx* c) { return c ? c->L.seg_rows : -1; }
+
+int lbm_set_strip_width(lbm_ctx* c, int32_t width) {
+  if (!c) return fail(LBM_E_INVAL, "null context");
+  if (width < STRIP_W_MIN || width > FUSED_TX)
+    return fail(LBM_E_INVAL, "strip width must lie in [" + std::to_string(STRIP_W_MIN) + ", " +
+                                 std::to_string(FUSED_TX) + "]");
+  return apply_segments(c, c->L.seg_rows, width);
+}
+
+int32_t lbm_get_strip_width(const lbm_ctx* c) { return c ? c->L.strip_w : -1; }
+
+const int32_t* lbm_tune_widths(void) { return TUNE_WIDTHS; }
 
 const int32_t* lbm_tune_rows(void) { return TUNE_ROWS; }
 
@@ -817,8 +839,9 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows
                  double* ms_out) {
   if (!c) return fail(LBM_E_INVAL, "null context");
   if (launches <= 0) return fail(LBM_E_INVAL, "launches must be > 0");
+  constexpr int NR = LBM_TUNE_NROWS, NW = LBM_TUNE_NWIDTHS;
   if (ms_out)
-    for (int k = 0; k < 2 * LBM_TUNE_NROWS + 1; ++k) ms_out[k] = -1.0;
+    for (int k = 0; k < 2 * NW * NR + 1; ++k) ms_out[k] = -1.0;
   if (c->path == LBM_PATH_SPLIT && !both_paths) {
     if (rows_out) *rows_out = c->L.seg_rows;
     if (path_out) *path_out = c->path;
@@ -829,15 +852,15 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int best_rows = c->L.seg_rows, best_path = c->path;
+  int best_rows = c->L.seg_rows, best_path = c->path, best_w = c->L.strip_w;
   double best_ms = 1e300;
   int rc = LBM_OK;
-  std::vector<double> cand_ms(2 * LBM_TUNE_NROWS, 1e300);
+  std::vector<double> cand_ms(2 * NW * NR, 1e300);
   // Heights that give the same number of strip segments as a smaller candidate are skipped.
-  std::vector<bool> skip(LBM_TUNE_NROWS, false);
+  std::vector<bool> skip(NR, false);
   {
     std::vector<int64_t> seen;
-    for (int k = 0; k < LBM_TUNE_NROWS; ++k) {
+    for (int k = 0; k < NR; ++k) {
       int64_t nseg = 0;
       for (const auto& d : c->L.inst) nseg += (d.ny + TUNE_ROWS[k] - 1) / TUNE_ROWS[k];
       skip[k] = std::find(seen.begin(), seen.end(), nseg) != seen.end();
@@ -859,35 +882,38 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows
     for (int pi = 0; pi < 2 && rc == LBM_OK; ++pi) {
       if (!both_paths && paths[pi] != start_path) continue;
       c->path = paths[pi];
-      for (int k = 0; k < LBM_TUNE_NROWS; ++k) {
-        if (skip[k]) continue;
-        if ((rc = lbm_set_seg_rows(c, TUNE_ROWS[k])) != LBM_OK) break;
-        hipError_t e = trial(1);
-        (void)hipEventRecord(e0, c->stream);
-        if (e == hipSuccess) e = trial(launches);
-        (void)hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e != hipSuccess) {
-          rc = fail(LBM_E_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
-          break;
+      for (int wi = 0; wi < NW && rc == LBM_OK; ++wi)
+        for (int k = 0; k < NR; ++k) {
+          if (skip[k]) continue;
+          if ((rc = apply_segments(c, TUNE_ROWS[k], TUNE_WIDTHS[wi])) != LBM_OK) break;
+          hipError_t e = trial(1);
+          (void)hipEventRecord(e0, c->stream);
+          if (e == hipSuccess) e = trial(launches);
+          (void)hipEventRecord(e1, c->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          if (e != hipSuccess) {
+            rc = fail(LBM_E_HIP, std::string("autotune launch: ") + hipGetErrorString(e));
+            break;
+          }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          double& m = cand_ms[(pi * NW + wi) * NR + k];
+          m = std::min(m, (double)ms / launches);
         }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        double& m = cand_ms[pi * LBM_TUNE_NROWS + k];
-        m = std::min(m, (double)ms / launches);
-      }
     }
   }
   for (int pi = 0; pi < 2; ++pi)
-    for (int k = 0; k < LBM_TUNE_NROWS; ++k) {
-      const double m = cand_ms[pi * LBM_TUNE_NROWS + k];
-      if (ms_out && m < 1e299) ms_out[pi * LBM_TUNE_NROWS + k] = m;
-      if (m < best_ms) {
-        best_ms = m;
-        best_rows = TUNE_ROWS[k];
-        best_path = paths[pi];
+    for (int wi = 0; wi < NW; ++wi)
+      for (int k = 0; k < NR; ++k) {
+        const double m = cand_ms[(pi * NW + wi) * NR + k];
+        if (ms_out && m < 1e299) ms_out[(pi * NW + wi) * NR + k] = m;
+        if (m < best_ms) {
+          best_ms = m;
+          best_rows = TUNE_ROWS[k];
+          best_w = TUNE_WIDTHS[wi];
+          best_path = paths[pi];
+        }
       }
-    }
   // the split path (two tile kernels, no strip height) competes with the step time of the sweeping kernels
   if (both_paths && rc == LBM_OK) {
     c->path = LBM_PATH_SPLIT;
@@ -911,7 +937,7 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows
       (void)hipEventElapsedTime(&ms, e0, e1);
       split_ms = std::min(split_ms, (double)ms / launches);
     }
-    if (ms_out && split_ms < 1e299) ms_out[2 * LBM_TUNE_NROWS] = split_ms;
+    if (ms_out && split_ms < 1e299) ms_out[2 * NW * NR] = split_ms;
     if (split_ms < best_ms) {
       best_ms = split_ms;
       best_path = LBM_PATH_SPLIT;
@@ -922,7 +948,7 @@ int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows
   c->path = start_path;
   if (rc != LBM_OK) return rc;
   if ((rc = lbm_set_path(c, best_path)) != LBM_OK) return rc;
-  if ((rc = lbm_set_seg_rows(c, best_rows)) != LBM_OK) return rc;
+  if ((rc = apply_segments(c, best_rows, best_w)) != LBM_OK) return rc;
   if (rows_out) *rows_out = best_rows;
   if (path_out) *path_out = best_path;
   return LBM_OK;

@@ -13,11 +13,19 @@ namespace lbm {
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 8;
 constexpr int NTHREADS = 256;
-// Fused kernel: a workgroup owns a strip of FUSED_TX columns and FUSED_SY rows and sweeps it row by
-// row; one wavefront (64 lanes = FUSED_TX + 10 columns) per row, FUSED_R rows per sweep iteration.
+// Sweeping kernels: a workgroup owns a strip of strip_w columns (at most FUSED_TX, so that the strip and
+// its 5-column halo on each side fit the 64 lanes of a wavefront) and seg_rows rows and sweeps it row by
+// row; the fused kernel runs FUSED_R rows per sweep iteration, one wavefront each.
 constexpr int FUSED_LANES = 64;
 constexpr int FUSED_TX = FUSED_LANES - 10;
 constexpr int FUSED_R = 4;
+constexpr int STRIP_W_MIN = LBM_STRIP_W_MIN;
+static_assert(LBM_STRIP_W_MAX == FUSED_TX, "widest strip");
+// Strip widths tried by the autotuner (LBM_TUNE_NWIDTHS of them).  Only the widest: narrower strips
+// (48 columns, whose FP64 row segments are whole 128-byte lines) measured slower on the 2048^2 workloads
+// in every precision.
+constexpr int32_t TUNE_WIDTHS[] = {54};
+static_assert(sizeof(TUNE_WIDTHS) / sizeof(TUNE_WIDTHS[0]) == LBM_TUNE_NWIDTHS, "tune width list length");
 // Rows per strip segment: chosen at run time among these (the autotuner picks one per context).
 constexpr int SEG_ROWS_MIN = LBM_SEG_ROWS_MIN;
 constexpr int SEG_ROWS_MAX = LBM_SEG_ROWS_MAX;
@@ -35,7 +43,7 @@ constexpr int MASK_WORDS = MAXDROP / 64;  // one presence bit per droplet and ti
 struct InstDev {
   int32_t nx, ny, pitch, ndrop;
   int32_t tiles_x[2], tiles_y[2], tile_base[2];  // per tiling: counts and first natural index
-  int32_t drop_base, seg_rows;  // seg_rows: rows per fused-kernel strip segment
+  int32_t drop_base, seg_rows;  // seg_rows: rows per sweeping-kernel strip segment
   int64_t pstride;     // elements between consecutive planes of the pool (ny * pitch)
   int64_t off_f[2];    // element offsets of the two population buffers [9][ny][pitch], planes pstride apart
   int64_t off_phi[2];  // the two phi buffers [ny][pitch]
@@ -43,6 +51,7 @@ struct InstDev {
   int64_t off_ux, off_uy, off_n;  // velocity planes written by the LB kernel; density (diagnostics)
   int64_t part_base[2];  // per tiling: offset (doubles) of the centre-of-mass partials [tiles][ndrop][3]
   int32_t advection, walls;  // walls: LBM_WALLS_NONE or LBM_WALLS_Y
+  int32_t strip_w, reserved;  // strip_w: columns owned per sweeping-kernel strip
   double yper;                // period of y in droplet distances and centres: ny, or infinite with walls
   // model parameters, derived on the host in double precision
   double a, b, B0, B1, halfB1, D, Gamma, gamma, c0, omega, coef, A0, t_star;

@@ -854,11 +854,11 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   const int nx = I.nx, ny = I.ny, pitch = I.pitch, nd = I.ndrop;
   const int x0 = sd.x0, y0 = sd.y0;
   const int yend = min(y0 + I.seg_rows, ny);
-  const int xend = min(x0 + FUSED_TX, nx);
+  const int xend = min(x0 + I.strip_w, nx);
   const int col = lane - 5;                   // column offset of this lane
   const int gx = wrap_idx(x0 + col, nx);      // periodic global column
   const int gxm = gx == 0 ? nx - 1 : gx - 1, gxp = gx == nx - 1 ? 0 : gx + 1;
-  const bool own_col = col >= 0 && col < FUSED_TX && x0 + col < nx;
+  const bool own_col = col >= 0 && col < I.strip_w && x0 + col < nx;
   const int64_t plane = I.pstride;
   const T* __restrict__ phi_in = buf + I.off_phi[parity];
   const T* __restrict__ c_in = buf + I.off_c[parity];
@@ -1370,11 +1370,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int nx = I.nx, ny = I.ny, pitch = I.pitch, nd = I.ndrop;
   const int x0 = sd.x0, y0 = sd.y0;
   const int yend = min(y0 + I.seg_rows, ny);
-  const int xend = min(x0 + FUSED_TX, nx);
+  const int xend = min(x0 + I.strip_w, nx);
   const int col = lane - 5;
   const int gx = wrap_idx(x0 + col, nx);
   const int gxm = gx == 0 ? nx - 1 : gx - 1, gxp = gx == nx - 1 ? 0 : gx + 1;
-  const bool own_col = col >= 0 && col < FUSED_TX && x0 + col < nx;
+  const bool own_col = col >= 0 && col < I.strip_w && x0 + col < nx;
   const int64_t plane = I.pstride;
   const T* __restrict__ phi_in = buf + I.off_phi[parity];
   const T* __restrict__ c_in = buf + I.off_c[parity];

@@ -30,9 +30,11 @@ STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "p
 EXPORTED = ["lbm_workspace_bytes", "lbm_init_batch", "lbm_init", "lbm_step", "lbm_set_graph", "lbm_sync",
             "lbm_get_step", "lbm_fields", "lbm_observables", "lbm_droplets", "lbm_debug_stage",
             "lbm_time_kernels", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_set_seg_rows",
-            "lbm_get_seg_rows", "lbm_tune_rows", "lbm_autotune", "lbm_adjoint_bytes", "lbm_adjoint_forward",
+            "lbm_get_seg_rows", "lbm_set_strip_width", "lbm_get_strip_width", "lbm_tune_rows", "lbm_tune_widths",
+            "lbm_autotune", "lbm_adjoint_bytes", "lbm_adjoint_forward",
             "lbm_adjoint_backward", "lbm_destroy", "lbm_last_error"]
 LBM_SEG_ROWS_MIN, LBM_SEG_ROWS_MAX, LBM_TUNE_NROWS = 16, 4096, 16
+LBM_STRIP_W_MIN, LBM_STRIP_W_MAX, LBM_TUNE_NWIDTHS = 32, 54, 1
 PATH_NAMES = {LBM_PATH_FUSED: "fused", LBM_PATH_SPLIT: "split", LBM_PATH_WAVE: "wave"}
 
 
@@ -96,8 +98,13 @@ def load_library(path: Optional[str] = None):
     lib.lbm_set_seg_rows.argtypes = [vp, C.c_int32]
     lib.lbm_get_seg_rows.argtypes = [vp]
     lib.lbm_get_seg_rows.restype = C.c_int32
+    lib.lbm_set_strip_width.argtypes = [vp, C.c_int32]
+    lib.lbm_get_strip_width.argtypes = [vp]
+    lib.lbm_get_strip_width.restype = C.c_int32
     lib.lbm_tune_rows.argtypes = []
     lib.lbm_tune_rows.restype = C.POINTER(C.c_int32)
+    lib.lbm_tune_widths.argtypes = []
+    lib.lbm_tune_widths.restype = C.POINTER(C.c_int32)
     lib.lbm_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
     lib.lbm_adjoint_bytes.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
     lib.lbm_adjoint_forward.argtypes = [vp, vp, C.c_size_t, C.c_int32, C.c_int64, C.c_int32, dp]
@@ -248,25 +255,41 @@ def lbm_get_seg_rows(ctx: int) -> int:
     return int(load_library().lbm_get_seg_rows(C.c_void_p(ctx)))
 
 
+def lbm_set_strip_width(ctx: int, width: int) -> None:
+    _check(load_library().lbm_set_strip_width(C.c_void_p(ctx), int(width)))
+
+
+def lbm_get_strip_width(ctx: int) -> int:
+    return int(load_library().lbm_get_strip_width(C.c_void_p(ctx)))
+
+
 def lbm_tune_rows():
     p = load_library().lbm_tune_rows()
     return [int(p[i]) for i in range(LBM_TUNE_NROWS)]
 
 
+def lbm_tune_widths():
+    p = load_library().lbm_tune_widths()
+    return [int(p[i]) for i in range(LBM_TUNE_NWIDTHS)]
+
+
 def lbm_autotune(ctx: int, launches: int, both_paths: bool = True):
     """Returns (rows, path, {"fused:rows" / "wave:rows": ms per launch}) for the candidates tried."""
     rows, path = C.c_int32(0), C.c_int32(0)
-    ms = np.zeros(2 * LBM_TUNE_NROWS + 1)
+    nw, nr = LBM_TUNE_NWIDTHS, LBM_TUNE_NROWS
+    ms = np.zeros(2 * nw * nr + 1)
     _check(load_library().lbm_autotune(C.c_void_p(ctx), int(launches), int(bool(both_paths)), C.byref(rows),
                                        C.byref(path), _dptr(ms)))
-    cand = lbm_tune_rows()
+    heights, widths = lbm_tune_rows(), lbm_tune_widths()
     times = {}
     for pi, name in enumerate(("fused", "wave")):
-        for k, r in enumerate(cand):
-            if ms[pi * LBM_TUNE_NROWS + k] >= 0:
-                times[f"{name}:{r}"] = float(ms[pi * LBM_TUNE_NROWS + k])
-    if ms[2 * LBM_TUNE_NROWS] >= 0:
-        times["split"] = float(ms[2 * LBM_TUNE_NROWS])
+        for wi, w in enumerate(widths):
+            for k, r in enumerate(heights):
+                v = ms[(pi * nw + wi) * nr + k]
+                if v >= 0:
+                    times[f"{name}:{w}x{r}"] = float(v)
+    if ms[2 * nw * nr] >= 0:
+        times["split"] = float(ms[2 * nw * nr])
     return int(rows.value), int(path.value), times
 
 
@@ -374,12 +397,24 @@ class Sim:
     def path(self) -> int:
         return lbm_get_path(self.ctx)
 
+    @property
+    def seg_rows(self) -> int:
+        return lbm_get_seg_rows(self.ctx)
+
     def set_seg_rows(self, rows: int) -> None:
         lbm_set_seg_rows(self.ctx, rows)
 
+    @property
+    def strip_width(self) -> int:
+        return lbm_get_strip_width(self.ctx)
+
+    def set_strip_width(self, width: int) -> None:
+        lbm_set_strip_width(self.ctx, width)
+
     def autotune(self, launches: int = 5, both_paths: bool = True):
-        """Pick the kernel path (fused or wave sweep with its segment height, or the split pair) by timing each
-        candidate (the state is unchanged).  Returns (rows, path, times)."""
+        """Pick the kernel path (fused or wave sweep with its strip width and segment height, or the split pair)
+        by timing each candidate (the state is unchanged).  Returns (rows, path, times); the chosen width is
+        `strip_width`.  Keys of times: "fused:WxH", "wave:WxH", "split"."""
         return lbm_autotune(self.ctx, launches, both_paths)
 
     def time_kernels(self, n: int) -> Dict[str, float]:

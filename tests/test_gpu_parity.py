@@ -265,26 +265,35 @@ def test_no_droplets_and_tiny_lattice(path):
 
 @pytest.mark.parametrize("path", [0, 2])
 def test_segment_heights_agree_bitwise_and_autotune_keeps_state(path):
-    """The sweeping kernels' strip height changes only the work decomposition: every height gives the
-    same bits; the autotuner's trial launches leave the state, droplets and step counter untouched."""
+    """The sweeping kernels' strip width and height change only the work decomposition: every width and
+    height gives the same bits; the autotuner's trial launches leave the state, droplets and step counter
+    untouched."""
+    lbm = _lbm()
     w = W.c5_emulsion(n=300, ndrop=4, R=14.0, seed=31)
     ref = None
-    for rows in (16, 32, 64, 128, 256):
+    for rows, width in ((16, 54), (32, 48), (64, 32), (128, 41), (256, 54), (20, 48)):
         s = gpu_sim(w, graph_steps=0, path=path)
         s.set_seg_rows(rows)
+        s.set_strip_width(width)
+        assert s.strip_width == width and s.seg_rows == rows
         s.step(37)
         f = s.fields()
         if ref is None:
             ref = f
         else:
             for k in FIELDS:
-                assert np.array_equal(f[k], ref[k]), (rows, k)
+                assert np.array_equal(f[k], ref[k]), (rows, width, k)
+        for bad in (lbm.LBM_STRIP_W_MIN - 1, lbm.LBM_STRIP_W_MAX + 1):
+            with pytest.raises(lbm.LBMError):
+                s.set_strip_width(bad)
         s.close()
     s = gpu_sim(w, graph_steps=10, path=path)
     s.step(5)
     before, drops_before, step_before = s.fields(), s.droplets(), s.step_count
     chosen, chosen_path, times = s.autotune(3, both_paths=False)
     assert chosen_path == path and chosen in s.tune_rows() and len(times) >= 3
+    assert s.strip_width in lbm.lbm_tune_widths()
+    assert {k.split(":")[1].split("x")[0] for k in times} == {str(x) for x in lbm.lbm_tune_widths()}
     after = s.fields()
     for k in FIELDS:
         assert np.array_equal(before[k], after[k]), k
