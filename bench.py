@@ -98,7 +98,7 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     tune_ms = {}
     if path != 1 and seg_rows == 0:
         # state-preserving: the trial launches write scratch only
-        seg_rows, path, tune_ms = sim.autotune(10, both_paths=path < 0)
+        seg_rows, path, tune_ms = sim.autotune(30, both_paths=path < 0)
         if path == 1:
             seg_rows = None
     elif path != 1:

@@ -2,7 +2,7 @@
 
 FP64: the kernels evaluate the same expressions in the same order as the oracle's plain definitions,
 without FMA contraction, so fields agree to the last bit; the only difference is the summation order
-of the centre-of-mass reductions (1e-16 relative in r_CM).  The bar is the benchmark spec's 1e-12 relative
+of the centre-of-mass reductions (1e-16 relative in r_CM).  The bar is 1e-12 relative
 (infinity norm per field, normalised by the oracle field's infinity norm) after 1000 steps.
 FP32: compared with the FP64 oracle within bounds derived from single-precision rounding.
 """
@@ -260,6 +260,30 @@ def test_no_droplets_and_tiny_lattice(path):
     sim.step(25)
     ref.run(25)
     compare(sim.fields(), ref.fields(), 1e-12, "tiny 3x4")
+    sim.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_maximum_droplet_count_matches_oracle(path):
+    """The droplet limit of a lattice (256 active droplets: four 64-bit mask words per strip or tile) against
+    the oracle: fields within 1e-12 and every centre within 1e-12 lattice units after 30 steps."""
+    lbm = _lbm()
+    w = W.c5_emulsion(seed=41, n=448, ndrop=lbm.LBM_MAXDROP, R=4.0)
+    w.params["A0"] = 1e-3  # sources strong enough to move every droplet within the run
+    sim = gpu_sim(w, path=path, graph_steps=10)
+    ref = oracle_sim(w)
+    sim.step(30)
+    ref.run(30)
+    compare(sim.fields(), ref.fields(), 1e-12, "256 droplets")
+    got, want = sim.droplets(), ref.drops()
+    assert len(got) == len(want) == lbm.LBM_MAXDROP
+
+    def mi(d):
+        return (d + 0.5 * w.nx) % w.nx - 0.5 * w.nx
+
+    dev = max(max(abs(mi(g["x"] - r.x)), abs(mi(g["y"] - r.y))) for g, r in zip(got, want))
+    moved = max(abs(mi(g["x"] - d.x)) + abs(mi(g["y"] - d.y)) for g, d in zip(got, w.drops))
+    assert dev < 1e-12 and moved > 1e-6, (dev, moved)
     sim.close()
 
 
