@@ -33,8 +33,9 @@ struct AdjModel {
   double yper;
 };
 
-// One backward step: the adjoint at n + 1 -> the adjoint at n.  part receives per-block partial sums of
-// sum_r cb1(r) * ramp * count_n(r) (the step's contribution to d/dA0), at most adj_blocks(nx * ny) values.
+// One backward step: the adjoint at n + 1 -> the adjoint at n.  Each block adds its partial sum of
+// sum_r cb1(r) * ramp * count_n(r) (the step's contribution to d/dA0) to part[block]; part holds
+// adj_blocks(nx * ny) running totals, zeroed before the first step.
 template <typename T>
 hipError_t launch_adjoint_step(hipStream_t s, const AdjModel& m, const AdjFwd& f, const AdjPlanes<T>& p,
                                const DropDev* drops_n, int ndrop, double* part);

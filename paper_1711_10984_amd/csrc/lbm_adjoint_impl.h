@@ -145,14 +145,15 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj1(AdjModel m, AdjFwd f, AdjP
       src = (double)cb0 * m.ramp * (double)cnt;
     }
   }
-  // deterministic per-block partial sum of the A0 contribution
+  // deterministic per-block partial sum of the A0 contribution, added to the block's running total (steps
+  // are taken one after another, so each block's total accumulates in a fixed order)
   for (int o = 32; o > 0; o >>= 1) src += __shfl_xor(src, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = src;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < ADJ_THREADS / 64; ++w) s += red[w];
-    part[blockIdx.x] = s;
+    part[blockIdx.x] += s;
   }
 }
 

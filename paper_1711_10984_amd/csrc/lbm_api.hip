@@ -1067,7 +1067,7 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int every) {
   A.off_fwd = off;
   off = align_up(off + sizeof(double) * ADJ_FWD_PLANES * (size_t)(every + 1) * (size_t)A.nodes, ALIGN);
   A.off_adj = off;   off = align_up(off + c->L.elem * (size_t)(22 + ADJ_TMP_PLANES) * A.nodes, ALIGN);
-  A.off_part = off;  off = align_up(off + sizeof(double) * (size_t)A.nb * (size_t)(nsteps + 1), ALIGN);
+  A.off_part = off;  off = align_up(off + sizeof(double) * (size_t)A.nb * 2, ALIGN);  // seed sums, dA0 totals
   A.total = off;
   return A;
 }
@@ -1139,7 +1139,9 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
   T* adj = reinterpret_cast<T*>(w + A.off_adj);
   T* lam[2] = {adj, adj + 11 * M};  // adjoint state (f 9 planes, phi, c) at n and at n + 1
   T* tmp = adj + 22 * M;
-  double* part = reinterpret_cast<double*>(w + A.off_part);
+  double* part = reinterpret_cast<double*>(w + A.off_part);  // seed partial sums (nb)
+  double* dA0_part = part + A.nb;                             // per-block dA0 totals over all steps (nb)
+  HIPCHK(hipMemsetAsync(dA0_part, 0, sizeof(double) * A.nb, c->stream));
   AdjModel m;
   m.nx = d.nx;
   m.ny = d.ny;
@@ -1216,8 +1218,7 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
       const double tn = (double)(n0 + k);
       m.ramp = tn < g.t_star ? tn : g.t_star;
       const AdjPlanes<T> p = planes(sslot, lam[cur], lam[cur ^ 1]);
-      HIPCHK(launch_adjoint_step<T>(c->stream, m, fwd_at(k - k0), p, adj_seg_drops(A, sslot), nd,
-                                    part + (size_t)(k + 1) * A.nb));
+      HIPCHK(launch_adjoint_step<T>(c->stream, m, fwd_at(k - k0), p, adj_seg_drops(A, sslot), nd, dA0_part));
       cur ^= 1;
     }
   }
@@ -1229,11 +1230,11 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
     for (int64_t i = 0; i < M; ++i) dc0[i] = (double)h[(size_t)i];
   }
   if (dA0) {
-    std::vector<double> hp((size_t)A.nb * (size_t)(N + 1));
-    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> hp((size_t)A.nb);
+    HIPCHK(hipMemcpyAsync(hp.data(), dA0_part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     double s = 0.0;
-    for (size_t i = (size_t)A.nb; i < hp.size(); ++i) s += hp[i];
+    for (double v : hp) s += v;
     *dA0 = s;
   }
   // back to the state at the end of the forward pass
