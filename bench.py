@@ -67,6 +67,32 @@ def measured_traffic(kernel: str, workload: str, precision: str, strip_w, seg_ro
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+def emulsion_4096():
+    """The 2048^2 emulsion's recipe on a 4096^2 lattice: 256 droplets (the same density), R = 20."""
+    from paper_1711_10984_amd import workloads as W
+    return W.c5_emulsion(seed=1015, n=4096, ndrop=256, R=20.0)
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Plain device-to-device copy of nbytes (torch), best of reps: bytes read + written per second (GB/s).
+    The practical ceiling that the kernels' algorithmic bandwidth is also compared with."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def build_sim(workloads, precision, graph_steps, path):
     from paper_1711_10984_amd import lbm
     return lbm.Sim([w.param_dict() for w in workloads], [w.phi0 for w in workloads], [w.c0 for w in workloads],
@@ -137,6 +163,23 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     }
 
 
+def sweep_heights(workloads, precision, prof_steps):
+    """Both sweeping kernels at every strip height the autotuner tries, prof_steps eagerly launched steps each,
+    in a fixed order (fused heights ascending, then wave heights ascending), so that a profiler's per-dispatch
+    records can be attributed to (kernel, height) by their order.  Returns that order with the hipEvent
+    times."""
+    sim = build_sim(workloads, precision, None, 0)
+    out = []
+    for path in (0, 2):
+        sim.set_path(path)
+        for h in sim.tune_rows():
+            sim.set_seg_rows(h)
+            out.append({"path": PATH_NAMES[path], "seg_rows": h, "strip_width": sim.strip_width,
+                        "kernel_ms": sim.time_kernels(prof_steps)})
+    sim.close()
+    return out
+
+
 def _minimg(d, L):
     return (d + 0.5 * L) % L - 0.5 * L
 
@@ -198,7 +241,8 @@ def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
     return {"workload": f"{w.name}, {nsteps} steps, checkpoint every {every}", "nodes": w.nodes,
             "path": PATH_NAMES[path], "seg_rows": rows if path != 1 else None,
             "strip_width": width if path != 1 else None,
-            "forward_ms_per_step": round(best_f / nsteps * 1e3, 5), "backward_ms_per_step": round(best_b / nsteps * 1e3, 5),
+            "forward_ms_per_step": round(best_f / nsteps * 1e3, 5),
+            "backward_ms_per_step": round(best_b / nsteps * 1e3, 5),
             "backward_mlups": round(w.nodes * nsteps / best_b / 1e6, 1),
             "backward_over_forward": round(best_b / best_f, 2)}
 
@@ -233,8 +277,12 @@ def main():
     ap.add_argument("--seg-rows", type=int, default=0, help="sweeping-kernel strip height (0: autotune)")
     ap.add_argument("--strip-width", type=int, default=0,
                     help="sweeping-kernel strip width with --seg-rows (0: the library default)")
-    ap.add_argument("--only", choices=["fp64", "fp32", "fp16", "c3", "adjoint"], default=None,
+    ap.add_argument("--only", default=None,
+                    choices=["fp64", "fp32", "fp16", "c3", "fp32_4096", "fp16_4096", "adjoint"],
                     help="run one configuration (for profiling); the JSON line then reports that one")
+    ap.add_argument("--sweep-heights", action="store_true",
+                    help="with --only (default fp64): launch both sweeping kernels at every autotuner height, "
+                         "--prof-steps steps each, and print the order (for per-height rocprofv3 counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32/FP16-vs-FP64 accuracy runs")
@@ -259,13 +307,25 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
+    copy_gbs = copy_bandwidth()
     c5 = W.c5_emulsion()
     if args.only == "adjoint":
         print(json.dumps({"only": "adjoint", "fp64": adjoint_measure(lbm.LBM_FP64, repeats=1)}), flush=True)
         return
-    if args.only in ("fp32", "fp16", "c3"):
+    if args.sweep_heights:
+        only = args.only or "fp64"
+        wl, prec, label = {"fp64": ([c5], lbm.LBM_FP64, "c5"), "fp32": ([c5], lbm.LBM_FP32, "c5"),
+                           "fp16": ([c5], lbm.LBM_FP16, "c5"), "c3": (W.c3_batch(), lbm.LBM_FP32, "c3"),
+                           "fp32_4096": ([emulsion_4096()], lbm.LBM_FP32, "c5_4096"),
+                           "fp16_4096": ([emulsion_4096()], lbm.LBM_FP16, "c5_4096")}[only]
+        print(json.dumps({"sweep": label, "precision": PREC_NAMES[prec], "prof_steps": args.prof_steps,
+                          "order": sweep_heights(wl, prec, args.prof_steps)}), flush=True)
+        return
+    if args.only in ("fp32", "fp16", "c3", "fp32_4096", "fp16_4096"):
         wl, prec, label = {"fp32": ([c5], lbm.LBM_FP32, "c5"), "fp16": ([c5], lbm.LBM_FP16, "c5"),
-                           "c3": (W.c3_batch(), lbm.LBM_FP32, "c3")}[args.only]
+                           "c3": (W.c3_batch(), lbm.LBM_FP32, "c3"),
+                           "fp32_4096": ([emulsion_4096()], lbm.LBM_FP32, "c5_4096"),
+                           "fp16_4096": ([emulsion_4096()], lbm.LBM_FP16, "c5_4096")}[args.only]
         r = measure(wl, prec, args.steps, args.warmup, args.graph_steps, label, args.prof_steps, args.path,
                     args.seg_rows, args.strip_width)
         print(json.dumps({"only": args.only, "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
@@ -284,8 +344,19 @@ def main():
                                               args.strip_width)
         variants["fp16_storage_2048"] = measure([c5], lbm.LBM_FP16, args.steps, args.warmup, args.graph_steps,
                                                 "c5", args.prof_steps, args.path, args.seg_rows, args.strip_width)
+        # 4096^2: twice the 256 MB last-level cache per step even in FP16, so no step's state stays cached
+        big = emulsion_4096()
+        variants["fp32_4096"] = measure([big], lbm.LBM_FP32, args.steps, args.warmup, args.graph_steps, "c5_4096",
+                                        args.prof_steps, args.path, args.seg_rows, args.strip_width)
+        variants["fp16_storage_4096"] = measure([big], lbm.LBM_FP16, args.steps, args.warmup, args.graph_steps,
+                                                "c5_4096", args.prof_steps, args.path, args.seg_rows,
+                                                args.strip_width)
+        del big
     for v in variants.values():
         v["gain_over_fp64"] = round(v["mlups"] / main_res["mlups"], 3)
+    for res in [main_res] + list(variants.values()):
+        res["roofline"]["copy_gbs"] = round(copy_gbs, 1)
+        res["roofline"]["frac_of_copy"] = round(res["roofline"]["achieved"] / copy_gbs, 4)
     out = {
         "metric": METRIC,
         "value": round(main_res["mlups"], 1),

@@ -73,20 +73,35 @@ def droplet_fields(nx: int, ny: int, drops: List[DropSpec], psi_out: float = 0.0
     """phi0 = phi_eq * tanh(2 (R - d) / xi) about the nearest droplet (Eq. 20 profile),
     psi0 = psi_in (1 + phi0/phi_eq)/2 + psi_out (1 - phi0/phi_eq)/2 + U(-noise, noise),
     psi_in = psi_front on the half facing e_hat, psi_back on the other half."""
-    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
     phi = np.full((ny, nx), -1.0)
     psi_in = np.zeros((ny, nx))
     best = np.full((ny, nx), np.inf)
+    # Each droplet updates only a periodic window of half-width h around its centre.  Beyond distance
+    # R_max + 10 xi from every centre the profile rounds to -1.0 exactly (tanh saturates in double precision
+    # past 19) and psi_in is multiplied by 0.0, and every node a window covers is covered by its nearest
+    # droplet's window too, so the result is the same, bit for bit, as evaluating every droplet everywhere.
+    h = int(math.ceil(max(d.R for d in drops) + 10.0 * xi + 1.0)) if drops else 0
+    windowed = 2 * h + 2 <= min(nx, ny)
     for d in drops:
+        if windowed:
+            cx, cy = int(math.floor(d.x)), int(math.floor(d.y))
+            xs = np.arange(cx - h, cx + h + 2) % nx
+            ys = np.arange(cy - h, cy + h + 2) % ny
+            sub = np.ix_(ys, xs)
+            x = xs.astype(np.float64)[None, :]
+            y = ys.astype(np.float64)[:, None]
+        else:
+            sub = (slice(None), slice(None))
+            y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
         dx = _minimg(x - d.x, nx)
         dy = _minimg(y - d.y, ny)
         r = np.hypot(dx, dy)
         prof = np.tanh(2.0 * (d.R - r) / xi)
-        closer = r < best
-        best = np.where(closer, r, best)
-        phi = np.where(closer, prof, phi)
+        closer = r < best[sub]
+        best[sub] = np.where(closer, r, best[sub])
+        phi[sub] = np.where(closer, prof, phi[sub])
         front = dx * d.ex + dy * d.ey >= 0.0
-        psi_in = np.where(closer, np.where(front, d.psi_front, d.psi_back), psi_in)
+        psi_in[sub] = np.where(closer, np.where(front, d.psi_front, d.psi_back), psi_in[sub])
     frac_in = 0.5 * (1.0 + phi)
     psi = psi_in * frac_in + psi_out * (1.0 - frac_in)
     if noise > 0.0:
