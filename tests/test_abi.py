@@ -122,3 +122,37 @@ def test_unknown_precision_rejected():
     lbm = _lbm()
     with pytest.raises(lbm.LBMError, match="precision must be"):
         lbm.lbm_workspace_bytes([lbm.make_config(dict(nx=16, ny=16), 3)], [0])
+
+
+def test_header_compiles_as_c99_and_a_c_caller_agrees_with_the_binding(tmp_path):
+    """include/lbm.h is a C header: a C99 program (pedantic, warnings as errors) builds against it, links the
+    library and gets the same answers from the host-only entry points as the Python binding."""
+    import shutil
+    import subprocess
+    lbm = _lbm()
+    lib = lbm.load_library()
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    exe = tmp_path / "c_abi_check"
+    libdir = os.path.dirname(lbm.LIB_PATH)
+    cmd = [gcc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "c_abi_check.c"), "-o", str(exe), lbm.LIB_PATH,
+           "-Wl,-rpath," + libdir]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = dict(line.split(" ", 1) for line in out.strip().splitlines())
+    cfgs = [lbm.make_config(dict(nx=256, ny=256, tau=1.0, a=-0.001, b=0.001, B0=0.006, B1=-0.05, D=0.1,
+                                 Gamma=1.0, t_star=2.0e6), lbm.LBM_FP64),
+            lbm.make_config(dict(nx=100, ny=37, tau=1.0, a=-0.001, b=0.001, B0=0.006, B1=-0.05, D=0.1,
+                                 Gamma=1.0, t_star=2.0e6), lbm.LBM_FP64)]
+    assert int(got["single_rc"]) == 0 and int(got["batch_rc"]) == 0
+    assert int(got["single_bytes"]) == lbm.lbm_workspace_bytes(cfgs[:1], [1])
+    assert int(got["batch_bytes"]) == lbm.lbm_workspace_bytes(cfgs, [1, 0])
+    assert int(got["bad_rc"]) == lbm.LBM_E_INVAL and got["bad_has_message"] == "1"
+    assert int(got["sizeof_config"]) == C.sizeof(lbm.lbm_config)
+    assert int(got["sizeof_droplet"]) == C.sizeof(lbm.lbm_droplet)
+    assert int(got["sizeof_obs"]) == C.sizeof(lbm.lbm_obs)
+    assert int(got["first_tune_row"]) == lbm.lbm_tune_rows()[0]
+    assert got["wave_kernel"] == lbm.lbm_kernel_name(lbm.LBM_PATH_WAVE, 0)
+    del lib
