@@ -169,7 +169,8 @@ int lbm_droplets(lbm_ctx* ctx, int32_t inst, lbm_droplet* out);
  * production kernels, without advancing the state.  out: host [LBM_NSTAGE][ny][nx] doubles in
  * the order mu_phi, X = (B1/2)|grad phi|^2, Fx, Fy, n, ux, uy, phi^{n+1/2}, c^{n+1/2}, M
  * (bracket of Eq. 18), X^{n+1/2}, phi^{n+1}, c^{n+1}, f*_0..8 (post-collision, before
- * streaming).  Instances of at most 512 x 512 nodes (LBM_E_INVAL otherwise).  Synchronous. */
+ * streaming; with FP32 arithmetic the deviation from w_i n0 plus w_i n0 in double, before the storage
+ * rounding).  Instances of at most 512 x 512 nodes (LBM_E_INVAL otherwise).  Synchronous. */
 int lbm_debug_stage(lbm_ctx* ctx, int32_t inst, double* out);
 
 /* Kernel sequence used by lbm_step and lbm_debug_stage: LBM_PATH_FUSED (default), LBM_PATH_SPLIT or

@@ -147,6 +147,7 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     d.wn[0] = WGT[0] * c.n0;
     d.wn[1] = WGT[1] * c.n0;
     d.wn[2] = WGT[5] * c.n0;
+    d.n0 = c.n0;
     tile_base += d.tiles_x[TILING_SPLIT] * d.tiles_y[TILING_SPLIT];
     seg_base += d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED];
     drop_base += d.ndrop;

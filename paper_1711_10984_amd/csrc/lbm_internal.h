@@ -56,6 +56,7 @@ struct InstDev {
   // model parameters, derived on the host in double precision
   double a, b, B0, B1, halfB1, D, Gamma, gamma, c0, omega, coef, A0, t_star;
   double wn[3];  // rest populations w_i n0 of the three weight classes (centre, axis, diagonal)
+  double n0;     // rest density
 };
 
 // Droplet table entry on the device.

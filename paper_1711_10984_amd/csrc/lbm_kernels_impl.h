@@ -160,6 +160,92 @@ __device__ __forceinline__ T collide1(T f, T wn, T cw, T eu, T eF, T exu, T eyu,
   return (f - omega * (f - feq)) + Fi;
 }
 
+// The same collision for a deviation d = f - w n0 from the rest population, with dn = n - n0:
+// d* = d - omega (d - deq) + Fi, deq = feq - w n0 = w dn + w n (3 e.u + 4.5 (e.u)^2 - 1.5 u^2).
+template <typename T>
+__device__ __forceinline__ T collide1_dev(T d, T w, T dn, T wn, T cw, T eu, T eF, T exu, T eyu, T Fx, T Fy,
+                                          T usq, T omega) {
+  const T deq = w * dn + wn * (((T(3) * eu) + (T(4.5) * eu) * eu) - T(1.5) * usq);
+  const T Fi = cw * (T(3) * (exu * Fx + eyu * Fy) + (T(9) * eu) * eF);
+  return (d - omega * (d - deq)) + Fi;
+}
+
+// Constants of the lattice-Boltzmann part of a node: weights w_i, (1 - 1/(2 tau)) w_i, 1/tau, the rest
+// populations w_i n0 in the arithmetic type, and n0.
+template <typename T>
+struct LbConst {
+  T w0, w1, w5, cw0, cw1, cw5, omega, wr0, wr1, wr5, n0;
+};
+
+// Moments of one node (Eq. 11) from its nine stored populations pulled to it (q, in direction order): the
+// density n and the velocity u = (sum f_i e_i + F/2) / n.  The node's populations are left in d for lb_collide.
+// FP64 takes the populations as stored and groups the sums as the oracle does, so its bits are the oracle's.
+// In FP32 those sums cancel: u ~ 1e-4 is a difference of populations ~ 0.1, and FP32 keeps only three of its
+// digits.  FP32 (and FP16 storage) therefore works on the deviations d_i = f_i - w_i n0 (exact in FP32 for a
+// population within a factor two of w_i n0): n = n0 + dn with dn = sum d_i, and n u = sum d_i e_i + F/2, where
+// the rest populations cancel exactly.
+template <typename T, typename P>
+__device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k, T Fx, T Fy, T (&d)[9], T& dn,
+                                           T& nn, T& ux, T& uy) {
+  const T wr[9] = {k.wr0, k.wr1, k.wr1, k.wr1, k.wr1, k.wr5, k.wr5, k.wr5, k.wr5};
+  if constexpr (sizeof(T) == 8) {
+    for (int i = 0; i < 9; ++i) d[i] = pop_ld<T>(q[i], wr[i]);
+    dn = T(0);
+    nn = ((d[0] + (d[2] + d[4])) + (d[1] + d[3])) + ((d[5] + d[6]) + (d[7] + d[8]));
+  } else {
+    for (int i = 0; i < 9; ++i) {
+      if constexpr (std::is_same<T, P>::value)
+        d[i] = q[i] - wr[i];
+      else
+        d[i] = T(q[i]);
+    }
+    dn = ((d[0] + (d[2] + d[4])) + (d[1] + d[3])) + ((d[5] + d[6]) + (d[7] + d[8]));
+    nn = k.n0 + dn;
+  }
+  const T mx = (d[1] + (d[5] + d[8])) - (d[3] + (d[6] + d[7]));
+  const T my = (d[2] + (d[5] + d[6])) - (d[4] + (d[7] + d[8]));
+  ux = (mx + T(0.5) * Fx) / nn;
+  uy = (my + T(0.5) * Fy) / nn;
+}
+
+// BGK collision with forcing of one node (Eqs. 10, 12, 13) after lb_moments: out receives the populations to
+// store, s the post-collision populations (for the stage export).  FP64 relaxes the populations as the oracle
+// does.  FP32 and FP16 storage relax the deviations (collide1_dev) and store d* + w_i n0 rounded to FP32, or d*
+// rounded to FP16; s is then d* + w_i n0 summed in double, before that rounding.
+template <typename T, typename P>
+__device__ __forceinline__ void lb_collide(const T (&d)[9], T dn, T nn, T ux, T uy, T Fx, T Fy, const LbConst<T>& k,
+                                           P (&out)[9], double (&s)[9]) {
+  const T usq = ux * ux + uy * uy;
+  const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
+  const T wn0 = k.w0 * nn, wn1 = k.w1 * nn, wn5 = k.w5 * nn;
+  const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
+  // direction i with weight w, w n, (1 - 1/(2 tau)) w, rest population wr, e.u, e.F, e_x - u_x, e_y - u_y
+  auto one = [&](int i, T w, T wn, T cw, T wr, T eu, T eF, T exu, T eyu) {
+    if constexpr (sizeof(T) == 8) {
+      (void)w;
+      const T f = collide1(d[i], wn, cw, eu, eF, exu, eyu, Fx, Fy, usq, k.omega);
+      s[i] = f;
+      out[i] = pop_st<P>(f, wr);
+    } else {
+      const T ds = collide1_dev(d[i], w, dn, wn, cw, eu, eF, exu, eyu, Fx, Fy, usq, k.omega);
+      s[i] = (double)ds + (double)wr;
+      if constexpr (std::is_same<T, P>::value)
+        out[i] = ds + wr;
+      else
+        out[i] = P(ds);
+    }
+  };
+  one(0, k.w0, wn0, k.cw0, k.wr0, T(0), T(0), nux, nuy);
+  one(1, k.w1, wn1, k.cw1, k.wr1, ux, Fx, xp1, nuy);
+  one(2, k.w1, wn1, k.cw1, k.wr1, uy, Fy, nux, yp1);
+  one(3, k.w1, wn1, k.cw1, k.wr1, nux, nFx, xm1, nuy);
+  one(4, k.w1, wn1, k.cw1, k.wr1, nuy, nFy, nux, ym1);
+  one(5, k.w5, wn5, k.cw5, k.wr5, ux + uy, Fx + Fy, xp1, yp1);
+  one(6, k.w5, wn5, k.cw5, k.wr5, nux + uy, nFx + Fy, xm1, yp1);
+  one(7, k.w5, wn5, k.cw5, k.wr5, nux + nuy, nFx + nFy, xm1, ym1);
+  one(8, k.w5, wn5, k.cw5, k.wr5, ux - uy, Fx - Fy, xp1, ym1);
+}
+
 // Sum (or min/max) over the workgroup in a fixed order; every thread receives lane 0's result.
 struct OpAdd {
   __device__ double operator()(double a, double b) const { return a + b; }
@@ -367,6 +453,7 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
   const T omega = T(I.omega), coef = T(I.coef);
   const T w0 = cst<T>(4.0 / 9.0), w1 = cst<T>(1.0 / 9.0), w5 = cst<T>(1.0 / 36.0);
   const T cw0 = coef * w0, cw1 = coef * w1, cw5 = coef * w5;
+  const LbConst<T> lbk{w0, w1, w5, cw0, cw1, cw5, omega, wr0, wr1, wr5, T(I.n0)};
   const int64_t nplane = (int64_t)nx * ny;
 
   for (int idx = tid; idx < TX * TY; idx += NTHREADS) {
@@ -388,20 +475,17 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
     const int64_t r0 = (int64_t)y * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
     // with walls, the populations that would come from behind a plate are the node's own, bounced back
     const bool bb0 = I.walls && y == 0, bbn = I.walls && y == ny - 1;
-    const T f0 = pop_ld<T>(fin[r0 + x], wr0);
-    const T f1 = pop_ld<T>(fin[plane + r0 + xm], wr1);
-    const T f2 = pop_ld<T>(bb0 ? fin[4 * plane + r0 + x] : fin[2 * plane + rm + x], wr1);
-    const T f3 = pop_ld<T>(fin[3 * plane + r0 + xp], wr1);
-    const T f4 = pop_ld<T>(bbn ? fin[2 * plane + r0 + x] : fin[4 * plane + rp + x], wr1);
-    const T f5 = pop_ld<T>(bb0 ? fin[7 * plane + r0 + x] : fin[5 * plane + rm + xm], wr5);
-    const T f6 = pop_ld<T>(bb0 ? fin[8 * plane + r0 + x] : fin[6 * plane + rm + xp], wr5);
-    const T f7 = pop_ld<T>(bbn ? fin[5 * plane + r0 + x] : fin[7 * plane + rp + xp], wr5);
-    const T f8 = pop_ld<T>(bbn ? fin[6 * plane + r0 + x] : fin[8 * plane + rp + xm], wr5);
-    const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
-    const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
-    const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
-    const T ux = (mx + T(0.5) * Fx) / nn;
-    const T uy = (my + T(0.5) * Fy) / nn;
+    const P q[9] = {fin[r0 + x],
+                    fin[plane + r0 + xm],
+                    bb0 ? fin[4 * plane + r0 + x] : fin[2 * plane + rm + x],
+                    fin[3 * plane + r0 + xp],
+                    bbn ? fin[2 * plane + r0 + x] : fin[4 * plane + rp + x],
+                    bb0 ? fin[7 * plane + r0 + x] : fin[5 * plane + rm + xm],
+                    bb0 ? fin[8 * plane + r0 + x] : fin[6 * plane + rm + xp],
+                    bbn ? fin[5 * plane + r0 + x] : fin[7 * plane + rp + xp],
+                    bbn ? fin[6 * plane + r0 + x] : fin[8 * plane + rp + xm]};
+    T d[9], dn, nn, ux, uy;
+    lb_moments<T, P>(q, lbk, Fx, Fy, d, dn, nn, ux, uy);
     const int64_t o = r0 + x;
     if (MODE == 2) {
       buf[I.off_n + o] = nn;
@@ -412,28 +496,10 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
     buf[I.off_ux + o] = ux;
     buf[I.off_uy + o] = uy;
     // S5: collision (Eqs. 10, 12, 13)
-    const T usq = ux * ux + uy * uy;
-    const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
-    const T wn0 = w0 * nn, wn1 = w1 * nn, wn5 = w5 * nn;
-    const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
-    const T s0 = collide1(f0, wn0, cw0, T(0), T(0), nux, nuy, Fx, Fy, usq, omega);
-    const T s1 = collide1(f1, wn1, cw1, ux, Fx, xp1, nuy, Fx, Fy, usq, omega);
-    const T s2 = collide1(f2, wn1, cw1, uy, Fy, nux, yp1, Fx, Fy, usq, omega);
-    const T s3 = collide1(f3, wn1, cw1, nux, nFx, xm1, nuy, Fx, Fy, usq, omega);
-    const T s4 = collide1(f4, wn1, cw1, nuy, nFy, nux, ym1, Fx, Fy, usq, omega);
-    const T s5 = collide1(f5, wn5, cw5, ux + uy, Fx + Fy, xp1, yp1, Fx, Fy, usq, omega);
-    const T s6 = collide1(f6, wn5, cw5, nux + uy, nFx + Fy, xm1, yp1, Fx, Fy, usq, omega);
-    const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
-    const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
-    fout[o] = pop_st<P>(s0, wr0);
-    fout[plane + o] = pop_st<P>(s1, wr1);
-    fout[2 * plane + o] = pop_st<P>(s2, wr1);
-    fout[3 * plane + o] = pop_st<P>(s3, wr1);
-    fout[4 * plane + o] = pop_st<P>(s4, wr1);
-    fout[5 * plane + o] = pop_st<P>(s5, wr5);
-    fout[6 * plane + o] = pop_st<P>(s6, wr5);
-    fout[7 * plane + o] = pop_st<P>(s7, wr5);
-    fout[8 * plane + o] = pop_st<P>(s8, wr5);
+    P out[9];
+    double sv[9];
+    lb_collide<T, P>(d, dn, nn, ux, uy, Fx, Fy, lbk, out, sv);
+    for (int i = 0; i < 9; ++i) fout[i * plane + o] = out[i];
     if (MODE == 1) {
       const int64_t q = (int64_t)y * nx + x;
       dbg[0 * nplane + q] = (double)s_mu[i1];
@@ -443,8 +509,7 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
       dbg[4 * nplane + q] = (double)nn;
       dbg[5 * nplane + q] = (double)ux;
       dbg[6 * nplane + q] = (double)uy;
-      const T sv[9] = {s0, s1, s2, s3, s4, s5, s6, s7, s8};
-      for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = (double)sv[i];
+      for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = sv[i];
     }
   }
 }
@@ -913,6 +978,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   const T omega = T(I.omega), coef = T(I.coef);
   const T w0 = cst<T>(4.0 / 9.0), w1 = cst<T>(1.0 / 9.0), w5 = cst<T>(1.0 / 36.0);
   const T cw0 = coef * w0, cw1 = coef * w1, cw5 = coef * w5;
+  const LbConst<T> lbk{w0, w1, w5, cw0, cw1, cw5, omega, wr0, wr1, wr5, T(I.n0)};
   const T Gamma = T(I.Gamma), D = T(I.D), gam = T(I.gamma), c0 = T(I.c0);
   const int adv = I.advection;
 
@@ -1004,40 +1070,16 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
         const T ph = r_phi[sm][lane], cv = r_c[sm][lane];
         const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
         const T Fy = (-(ph * gmy) - gcy) - cv * gXy;
-        const T f0 = pop_ld<T>(pf[0], wr0), f1 = pop_ld<T>(pf[1], wr1), f2 = pop_ld<T>(pf[2], wr1),
-                f3 = pop_ld<T>(pf[3], wr1), f4 = pop_ld<T>(pf[4], wr1), f5 = pop_ld<T>(pf[5], wr5),
-                f6 = pop_ld<T>(pf[6], wr5), f7 = pop_ld<T>(pf[7], wr5), f8 = pop_ld<T>(pf[8], wr5);
-        const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
-        const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
-        const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
-        const T ux = (mx + T(0.5) * Fx) / nn;
-        const T uy = (my + T(0.5) * Fy) / nn;
+        T d[9], dn, nn, ux, uy;
+        lb_moments<T, P>(pf, lbk, Fx, Fy, d, dn, nn, ux, uy);
         r_ux[sm][lane] = ux;
         r_uy[sm][lane] = uy;
         if (own_col && r >= y0 && r < yend) {
-          const T usq = ux * ux + uy * uy;
-          const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
-          const T wn0 = w0 * nn, wn1 = w1 * nn, wn5 = w5 * nn;
-          const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
-          const T s0 = collide1(f0, wn0, cw0, T(0), T(0), nux, nuy, Fx, Fy, usq, omega);
-          const T s1 = collide1(f1, wn1, cw1, ux, Fx, xp1, nuy, Fx, Fy, usq, omega);
-          const T s2 = collide1(f2, wn1, cw1, uy, Fy, nux, yp1, Fx, Fy, usq, omega);
-          const T s3 = collide1(f3, wn1, cw1, nux, nFx, xm1, nuy, Fx, Fy, usq, omega);
-          const T s4 = collide1(f4, wn1, cw1, nuy, nFy, nux, ym1, Fx, Fy, usq, omega);
-          const T s5 = collide1(f5, wn5, cw5, ux + uy, Fx + Fy, xp1, yp1, Fx, Fy, usq, omega);
-          const T s6 = collide1(f6, wn5, cw5, nux + uy, nFx + Fy, xm1, yp1, Fx, Fy, usq, omega);
-          const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
-          const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
+          P out[9];
+          double sv[9];
+          lb_collide<T, P>(d, dn, nn, ux, uy, Fx, Fy, lbk, out, sv);
           const int64_t o = (int64_t)r * pitch + gx;
-          fout[o] = pop_st<P>(s0, wr0);
-          fout[plane + o] = pop_st<P>(s1, wr1);
-          fout[2 * plane + o] = pop_st<P>(s2, wr1);
-          fout[3 * plane + o] = pop_st<P>(s3, wr1);
-          fout[4 * plane + o] = pop_st<P>(s4, wr1);
-          fout[5 * plane + o] = pop_st<P>(s5, wr5);
-          fout[6 * plane + o] = pop_st<P>(s6, wr5);
-          fout[7 * plane + o] = pop_st<P>(s7, wr5);
-          fout[8 * plane + o] = pop_st<P>(s8, wr5);
+          for (int i = 0; i < 9; ++i) fout[i * plane + o] = out[i];
           if (DBG) {
             const int64_t q = (int64_t)r * nx + (x0 + col);
             dbg[2 * nplane + q] = (double)Fx;
@@ -1045,8 +1087,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
             dbg[4 * nplane + q] = (double)nn;
             dbg[5 * nplane + q] = (double)ux;
             dbg[6 * nplane + q] = (double)uy;
-            const T sv[9] = {s0, s1, s2, s3, s4, s5, s6, s7, s8};
-            for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = (double)sv[i];
+            for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = sv[i];
           }
         }
       }
@@ -1435,6 +1476,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const T omega = T(I.omega), coef = T(I.coef);
   const T w0 = cst<T>(4.0 / 9.0), w1 = cst<T>(1.0 / 9.0), w5 = cst<T>(1.0 / 36.0);
   const T cw0 = coef * w0, cw1 = coef * w1, cw5 = coef * w5;
+  const LbConst<T> lbk{w0, w1, w5, cw0, cw1, cw5, omega, wr0, wr1, wr5, T(I.n0)};
   const T Gamma = T(I.Gamma), D = T(I.D), gam = T(I.gamma), c0 = T(I.c0);
   const int adv = I.advection;
 
@@ -1527,40 +1569,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       const T ph = P2, cv = C2;
       const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
       const T Fy = (-(ph * gmy) - gcy) - cv * gXy;
-      const T f0 = pop_ld<T>(pf.f[0], wr0), f1 = pop_ld<T>(pf.f[1], wr1), f2 = pop_ld<T>(pf.f[2], wr1),
-              f3 = pop_ld<T>(pf.f[3], wr1), f4 = pop_ld<T>(pf.f[4], wr1), f5 = pop_ld<T>(pf.f[5], wr5),
-              f6 = pop_ld<T>(pf.f[6], wr5), f7 = pop_ld<T>(pf.f[7], wr5), f8 = pop_ld<T>(pf.f[8], wr5);
-      const T nn = ((f0 + (f2 + f4)) + (f1 + f3)) + ((f5 + f6) + (f7 + f8));
-      const T mx = (f1 + (f5 + f8)) - (f3 + (f6 + f7));
-      const T my = (f2 + (f5 + f6)) - (f4 + (f7 + f8));
-      const T ux = (mx + T(0.5) * Fx) / nn;
-      const T uy = (my + T(0.5) * Fy) / nn;
+      T d[9], dn, nn, ux, uy;
+      lb_moments<T, P>(pf.f, lbk, Fx, Fy, d, dn, nn, ux, uy);
       UX2 = ux;
       UY2 = uy;
       if (own_col && r >= y0 && r < yend) {
-        const T usq = ux * ux + uy * uy;
-        const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
-        const T wn0 = w0 * nn, wn1 = w1 * nn, wn5 = w5 * nn;
-        const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
-        const T s0 = collide1(f0, wn0, cw0, T(0), T(0), nux, nuy, Fx, Fy, usq, omega);
-        const T s1 = collide1(f1, wn1, cw1, ux, Fx, xp1, nuy, Fx, Fy, usq, omega);
-        const T s2 = collide1(f2, wn1, cw1, uy, Fy, nux, yp1, Fx, Fy, usq, omega);
-        const T s3 = collide1(f3, wn1, cw1, nux, nFx, xm1, nuy, Fx, Fy, usq, omega);
-        const T s4 = collide1(f4, wn1, cw1, nuy, nFy, nux, ym1, Fx, Fy, usq, omega);
-        const T s5 = collide1(f5, wn5, cw5, ux + uy, Fx + Fy, xp1, yp1, Fx, Fy, usq, omega);
-        const T s6 = collide1(f6, wn5, cw5, nux + uy, nFx + Fy, xm1, yp1, Fx, Fy, usq, omega);
-        const T s7 = collide1(f7, wn5, cw5, nux + nuy, nFx + nFy, xm1, ym1, Fx, Fy, usq, omega);
-        const T s8 = collide1(f8, wn5, cw5, ux - uy, Fx - Fy, xp1, ym1, Fx, Fy, usq, omega);
+        P out[9];
+        double sv[9];
+        lb_collide<T, P>(d, dn, nn, ux, uy, Fx, Fy, lbk, out, sv);
         P* const o = fout + (int64_t)r * pitch;
-        st_col(o, fx, pop_st<P>(s0, wr0));
-        st_col(o + plane, fx, pop_st<P>(s1, wr1));
-        st_col(o + 2 * plane, fx, pop_st<P>(s2, wr1));
-        st_col(o + 3 * plane, fx, pop_st<P>(s3, wr1));
-        st_col(o + 4 * plane, fx, pop_st<P>(s4, wr1));
-        st_col(o + 5 * plane, fx, pop_st<P>(s5, wr5));
-        st_col(o + 6 * plane, fx, pop_st<P>(s6, wr5));
-        st_col(o + 7 * plane, fx, pop_st<P>(s7, wr5));
-        st_col(o + 8 * plane, fx, pop_st<P>(s8, wr5));
+        for (int i = 0; i < 9; ++i) st_col(o + i * plane, fx, out[i]);
         if (DBG) {
           const int64_t qq = (int64_t)r * nx + (x0 + col);
           dbg[2 * nplane + qq] = (double)Fx;
@@ -1568,8 +1586,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           dbg[4 * nplane + qq] = (double)nn;
           dbg[5 * nplane + qq] = (double)ux;
           dbg[6 * nplane + qq] = (double)uy;
-          const T sv[9] = {s0, s1, s2, s3, s4, s5, s6, s7, s8};
-          for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + qq] = (double)sv[i];
+          for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + qq] = sv[i];
         }
       }
       if (r + PFD < yend + 3) load_s2(pf, r + PFD);

@@ -46,7 +46,8 @@ class LBMError(RuntimeError):
 
 class lbm_config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32), ("advection", C.c_int32),
-                ("walls", C.c_int32), ("reserved", C.c_int32), ("tau", C.c_double), ("n0", C.c_double), ("a", C.c_double), ("b", C.c_double),
+                ("walls", C.c_int32), ("reserved", C.c_int32), ("tau", C.c_double), ("n0", C.c_double),
+                ("a", C.c_double), ("b", C.c_double),
                 ("B0", C.c_double), ("B1", C.c_double), ("D", C.c_double), ("Gamma", C.c_double),
                 ("gamma", C.c_double), ("A0", C.c_double), ("t_star", C.c_double), ("c0", C.c_double)]
 

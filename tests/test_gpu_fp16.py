@@ -1,10 +1,15 @@
 """FP16 population storage (LBM_FP16): populations kept as the FP16-rounded deviation f_i - w_i n0 from
 the rest state, fields and arithmetic in FP32.
 
-* Storage semantics, exactly: from the rest state f_i = w_i n0 (deviation 0, exact in FP16) both the
-  FP32 and the FP16 runs read the same FP32 populations, so one step later phi and c agree bit for bit
-  and every stored population of the FP16 run is fp16(f*_32 - fp32(w_i n0)) widened back by + fp32(w_i n0),
-  with f*_32 the FP32 run's population (emulated here with numpy's IEEE float16/float32 arithmetic).
+* Storage semantics, exactly: from the rest state f_i = w_i n0 (deviation 0, exact in both) the FP32 and
+  the FP16 runs compute the same post-collision deviations d*_i in FP32, so one step later phi and c agree
+  bit for bit, and every population of the FP16 run is fp16(d*_i), widened back as fp32(fp16(d*_i)) +
+  fp32(w_i n0) and pulled along e_i.  d*_i comes from the FP32 run's stage export (d*_i + w_i n0 in double);
+  the storage is emulated with numpy's IEEE float16/float32 arithmetic.  The export is a separately compiled
+  instantiation of the kernel, and FP32 arithmetic is contracted into FMAs where the compiler chooses, so its
+  d*_i may differ from the stepping kernel's by one FP32 rounding.  Where that straddles an FP16 rounding
+  boundary the stored value moves by one FP16 ulp, so the check is: every population within one FP16 ulp of
+  the emulation, and at least 99.9 % of them equal to it.
 * Accuracy against the FP64 oracle: storing a population rounds it by at most 2^-11 |d_i| (d_i the
   deviation).  The equilibrium-droplet workload starts far from equilibrium: in the oracle run |u| reaches
   0.08 and |d_i| 0.11 (45 % of w_i n0) within the first 200 steps, so the storage error is up to
@@ -23,6 +28,7 @@ pytestmark = pytest.mark.gpu
 
 FIELDS = ("f", "phi", "c", "n", "ux", "uy")
 WGT = np.array([4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36])
+E = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]  # D2Q9 directions (x, y)
 
 
 def sim_of(w, precision, path, graph_steps=None):
@@ -40,14 +46,23 @@ def test_storage_rounding_after_one_step_is_exact(path):
     from paper_1711_10984_amd import lbm
     w = W.c2_single_active(n=96, seed=41)
     s32, s16 = sim_of(w, lbm.LBM_FP32, path), sim_of(w, lbm.LBM_FP16, path)
+    st = s32.stages()
     s32.step(1)
     s16.step(1)
     a, b = s32.fields(), s16.fields()
     assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["c"], b["c"])
-    wn = np.float32(WGT * float(w.params.get("n0", 1.0))).astype(np.float32)[:, None, None]
-    f32 = a["f"].astype(np.float32)
-    emulated = (np.float32(np.float16(f32 - wn)) + wn).astype(np.float64)
-    assert np.array_equal(b["f"], emulated), float(np.max(np.abs(b["f"] - emulated)))
+    wn = np.float32(WGT * float(w.params.get("n0", 1.0)))
+    emulated = np.empty_like(b["f"])
+    for i, (ex, ey) in enumerate(E):
+        dev = np.float32(st[f"fstar{i}"] - np.float64(wn[i]))  # exact: the export is fp32 d* + fp32 w n0
+        assert np.array_equal(dev.astype(np.float64) + np.float64(wn[i]), st[f"fstar{i}"])
+        stored = (np.float32(np.float16(dev)) + wn[i]).astype(np.float64)
+        emulated[i] = np.roll(stored, (ey, ex), axis=(0, 1))  # pulled: f_i(r) = f*_i(r - e_i)
+    ulp = np.spacing(np.abs(emulated - np.float64(wn)[:, None, None]).astype(np.float16)).astype(np.float64)
+    diff = np.abs(b["f"] - emulated)
+    print("populations off the emulation:", int(np.count_nonzero(diff)), "of", diff.size)
+    assert np.all(diff <= ulp * 1.0000001), float(np.max(diff / ulp))
+    assert np.count_nonzero(diff) <= 1e-3 * diff.size
     # the rounding is really there: FP16 differs from FP32 somewhere
     assert not np.array_equal(b["f"], a["f"])
     s32.close()
