@@ -188,7 +188,9 @@ def lowp_accuracy(workloads, steps, log_every, graph_steps, path, low):
     """A lower precision (`low`: LBM_FP32 or LBM_FP16) against FP64 on the GPU for the same inputs: largest
     centre-of-mass deviation over the run (trajectories logged every `log_every` steps), drift of the phi
     integral in both precisions, and the relative L2 difference of the velocity field at the end (first
-    lattice)."""
+    lattice).  Lattices whose droplets come within 2R of each other (touching or coalescing, in the FP64 run)
+    are reported apart: once two droplets merge, their tracked centres share one body and follow no defined
+    trajectory, so the deviation there measures the merger, not the arithmetic."""
     import numpy as np
     from paper_1711_10984_amd import lbm
     traj = {}
@@ -205,20 +207,31 @@ def lowp_accuracy(workloads, steps, log_every, graph_steps, path, low):
         end[prec] = sim.fields(0)
         phi_sum[prec] = [sim.observables(i)["sum_phi"] - s0[i] for i in range(len(workloads))]
         sim.close()
-    dev = 0.0
-    for a, b in zip(traj[lbm.LBM_FP64], traj[low]):
-        for i, w in enumerate(workloads):
+    dev_apart, touching = 0.0, {}
+    for i, w in enumerate(workloads):
+        dev, close = 0.0, False
+        for a, b in zip(traj[lbm.LBM_FP64], traj[low]):
             for (xa, ya), (xb, yb) in zip(a[i], b[i]):
                 dev = max(dev, float(np.hypot(_minimg(xa - xb, w.nx), _minimg(ya - yb, w.ny))))
+            for j in range(len(a[i])):
+                for k in range(j + 1, len(a[i])):
+                    sep = np.hypot(_minimg(a[i][j][0] - a[i][k][0], w.nx), _minimg(a[i][j][1] - a[i][k][1], w.ny))
+                    close = close or sep < w.drops[j].R + w.drops[k].R
+        if close:
+            touching[w.name] = round(dev, 6)
+        else:
+            dev_apart = max(dev_apart, dev)
     u64, u32 = end[lbm.LBM_FP64], end[low]
     num = np.sqrt(np.sum((u64["ux"] - u32["ux"]) ** 2 + (u64["uy"] - u32["uy"]) ** 2))
     den = np.sqrt(np.sum(u64["ux"] ** 2 + u64["uy"] ** 2))
-    return {"steps": steps, "lattices": len(workloads), "log_every": log_every,
-            "max_cm_deviation_lu": round(dev, 6),
-            "phi_integral_drift_fp64": round(float(max(phi_sum[lbm.LBM_FP64], key=abs)), 6),
-            f"phi_integral_drift_{PREC_NAMES[low]}": round(float(max(phi_sum[low], key=abs)), 6),
-            "velocity_l2_rel_diff": float(num / den) if den > 0 else None}
-
+    out = {"steps": steps, "lattices": len(workloads), "log_every": log_every,
+           "max_cm_deviation_lu": round(dev_apart, 6),
+           "phi_integral_drift_fp64": round(float(max(phi_sum[lbm.LBM_FP64], key=abs)), 6),
+           f"phi_integral_drift_{PREC_NAMES[low]}": round(float(max(phi_sum[low], key=abs)), 6),
+           "velocity_l2_rel_diff": float(num / den) if den > 0 else None}
+    if touching:
+        out["lattices_with_touching_droplets"] = touching
+    return out
 
 def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
     """Reverse mode on the 256^2 single-active-droplet workload: wall time of the checkpointed forward pass and
@@ -391,7 +404,7 @@ def main():
         out["fp32_accuracy"] = {
             "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
                                                 args.path, lbm.LBM_FP32),
-            "batched_c3": lowp_accuracy(W.c3_batch(), 20000, 100, args.graph_steps, args.path, lbm.LBM_FP32),
+            "batched_c3": lowp_accuracy(W.c3_batch(), 100000, 500, args.graph_steps, args.path, lbm.LBM_FP32),
         }
         out["fp16_accuracy"] = {
             "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
