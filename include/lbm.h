@@ -48,7 +48,8 @@ extern "C" {
 #define LBM_E_STATE -5    /* call not valid in the current state */
 
 #define LBM_FP64 0 /* populations, fields and arithmetic in FP64 */
-#define LBM_FP32 1 /* populations, fields and arithmetic in FP32; droplet sums in FP64 */
+#define LBM_FP32 1 /* populations stored as FP32 deviations f_i - w_i n0 from the rest state, fields and
+                      arithmetic in FP32; droplet sums in FP64 */
 #define LBM_FP16 2 /* populations stored as FP16 deviations f_i - w_i n0 from the rest state (round to
                       nearest even), widened to FP32 on load; fields and arithmetic FP32; sums FP64 */
 

@@ -1,8 +1,9 @@
 """Build the HIP library paper_1711_10984_amd/liblbm.so for gfx950 (MI355X).
 
 FP64 kernels and the host side are compiled without floating-point contraction, so that the FP64 path
-evaluates every expression in the order written; the FP32 kernels are compiled with fused multiply-add
-contraction.  Packed FP32 instructions are disabled everywhere.
+evaluates every expression in the order written.  The FP32 and FP16-storage kernels contract a * b + c into a
+fused multiply-add within a source expression only (-ffp-contract=on), so every instantiation of a kernel (the
+stepping and the stage-exporting one) rounds alike.  Packed FP32 instructions are disabled everywhere.
 """
 import os
 import subprocess
@@ -11,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 # (source, floating-point contraction)
-SRC = [("lbm_kernels_f64.hip", "off"), ("lbm_kernels_f32.hip", "fast"), ("lbm_kernels_f16.hip", "fast"),
-       ("lbm_adjoint_f64.hip", "off"), ("lbm_adjoint_f32.hip", "fast"),
+SRC = [("lbm_kernels_f64.hip", "off"), ("lbm_kernels_f32.hip", "on"), ("lbm_kernels_f16.hip", "on"),
+       ("lbm_adjoint_f64.hip", "off"), ("lbm_adjoint_f32.hip", "on"),
        ("lbm_api.hip", "off")]
 LIB = os.path.join(HERE, "liblbm.so")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")

@@ -273,22 +273,27 @@ decltype(auto) with_types(int prec, F&& f) {
   return f(float{}, _Float16{});
 }
 
-// Host side of the population storage (the kernels' pop_st / pop_ld): P == T stores the population; a
-// _Float16 store keeps fp16(fp32(f) - fp32(w_i n0)), widened back as fp32(stored) + fp32(w_i n0).
+// Host side of the population storage (the kernels' lb_moments / lb_collide).  FP64 stores the population.
+// FP32 stores the deviation from the rest population, fp32(f - fp32(w_i n0)), read back as that deviation plus
+// fp32(w_i n0).  FP16 storage keeps fp16(fp32(f) - fp32(w_i n0)), widened back as fp32(stored) + fp32(w_i n0).
 template <typename T, typename P>
 P host_pop_store(double f, double wn) {
-  if constexpr (std::is_same<T, P>::value) {
+  if constexpr (sizeof(T) == 8) {
     (void)wn;
     return (T)f;
+  } else if constexpr (std::is_same<T, P>::value) {
+    return (P)(f - (double)(float)wn);
   } else {
     return (P)((float)f - (float)wn);
   }
 }
 template <typename T, typename P>
 double host_pop_load(P s, double wn) {
-  if constexpr (std::is_same<T, P>::value) {
+  if constexpr (sizeof(T) == 8) {
     (void)wn;
     return (double)s;
+  } else if constexpr (std::is_same<T, P>::value) {
+    return (double)s + (double)(float)wn;
   } else {
     return (double)((float)s + (float)wn);
   }

@@ -179,11 +179,11 @@ struct LbConst {
 
 // Moments of one node (Eq. 11) from its nine stored populations pulled to it (q, in direction order): the
 // density n and the velocity u = (sum f_i e_i + F/2) / n.  The node's populations are left in d for lb_collide.
-// FP64 takes the populations as stored and groups the sums as the oracle does, so its bits are the oracle's.
-// In FP32 those sums cancel: u ~ 1e-4 is a difference of populations ~ 0.1, and FP32 keeps only three of its
-// digits.  FP32 (and FP16 storage) therefore works on the deviations d_i = f_i - w_i n0 (exact in FP32 for a
-// population within a factor two of w_i n0): n = n0 + dn with dn = sum d_i, and n u = sum d_i e_i + F/2, where
-// the rest populations cancel exactly.
+// FP64 stores and takes the populations themselves and groups the sums as the oracle does, so its bits are the
+// oracle's.  With FP32 arithmetic those sums would cancel: u ~ 1e-4 is a difference of populations ~ 0.1, and
+// FP32 keeps only three of its digits.  FP32 and FP16 storage therefore store and work on the deviations
+// d_i = f_i - w_i n0: n = n0 + dn with dn = sum d_i, and n u = sum d_i e_i + F/2, where the rest populations
+// have cancelled exactly.
 template <typename T, typename P>
 __device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k, T Fx, T Fy, T (&d)[9], T& dn,
                                            T& nn, T& ux, T& uy) {
@@ -193,12 +193,7 @@ __device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k,
     dn = T(0);
     nn = ((d[0] + (d[2] + d[4])) + (d[1] + d[3])) + ((d[5] + d[6]) + (d[7] + d[8]));
   } else {
-    for (int i = 0; i < 9; ++i) {
-      if constexpr (std::is_same<T, P>::value)
-        d[i] = q[i] - wr[i];
-      else
-        d[i] = T(q[i]);
-    }
+    for (int i = 0; i < 9; ++i) d[i] = T(q[i]);
     dn = ((d[0] + (d[2] + d[4])) + (d[1] + d[3])) + ((d[5] + d[6]) + (d[7] + d[8]));
     nn = k.n0 + dn;
   }
@@ -208,10 +203,10 @@ __device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k,
   uy = (my + T(0.5) * Fy) / nn;
 }
 
-// BGK collision with forcing of one node (Eqs. 10, 12, 13) after lb_moments: out receives the populations to
-// store, s the post-collision populations (for the stage export).  FP64 relaxes the populations as the oracle
-// does.  FP32 and FP16 storage relax the deviations (collide1_dev) and store d* + w_i n0 rounded to FP32, or d*
-// rounded to FP16; s is then d* + w_i n0 summed in double, before that rounding.
+// BGK collision with forcing of one node (Eqs. 10, 12, 13) after lb_moments: out receives the values to store,
+// s the post-collision populations (for the stage export).  FP64 relaxes and stores the populations as the
+// oracle does.  FP32 and FP16 storage relax the deviations (collide1_dev) and store d* (in FP32, or rounded to
+// FP16); s is then d* + w_i n0 summed in double.
 template <typename T, typename P>
 __device__ __forceinline__ void lb_collide(const T (&d)[9], T dn, T nn, T ux, T uy, T Fx, T Fy, const LbConst<T>& k,
                                            P (&out)[9], double (&s)[9]) {
@@ -229,10 +224,7 @@ __device__ __forceinline__ void lb_collide(const T (&d)[9], T dn, T nn, T ux, T 
     } else {
       const T ds = collide1_dev(d[i], w, dn, wn, cw, eu, eF, exu, eyu, Fx, Fy, usq, k.omega);
       s[i] = (double)ds + (double)wr;
-      if constexpr (std::is_same<T, P>::value)
-        out[i] = ds + wr;
-      else
-        out[i] = P(ds);
+      out[i] = P(ds);
     }
   };
   one(0, k.w0, wn0, k.cw0, k.wr0, T(0), T(0), nux, nuy);
@@ -1394,14 +1386,16 @@ __device__ __forceinline__ T div9n(const Nbr<T>& c, const Nbr<T>& X, T D) {
 
 
 template <typename T, typename P, bool DBG>
-// Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD;
-// FP32 fits three.
+// Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD; FP32
+// fits four (127 registers) and FP16 storage three.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
                                              const InstDev* __restrict__ insts, T* __restrict__ buf,
                                              const DropDev* __restrict__ drops, double* __restrict__ part,
                                              uint64_t* __restrict__ mask, const int64_t* __restrict__ step,
                                              double* __restrict__ dbg, int dbg_inst) {
   __shared__ double acc[MAXDROP][3];
+  // droplet candidates of this segment (read-only after set-up): near the box, and production disks reaching it
+  __shared__ unsigned long long s_near[MASK_WORDS], s_src[MASK_WORDS];
 
   const TileDev sd = segs[blockIdx.x];
   if (sd.inst < 0) return;
@@ -1427,8 +1421,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int64_t nplane = (int64_t)nx * ny;
 
   // --- droplet culling for the owned box [x0, xend) x [y0, yend); lane l examines droplets l + 64 w.
-  // The candidate masks are kept lane-distributed (lane w holds word w) to spare scalar registers.
-  unsigned long long near_v = 0ull, src_v = 0ull, seg_v = 0ull;
+  // The candidate masks go to LDS; the mask of droplets met (seg_v) is kept lane-distributed (lane w holds
+  // word w) to spare scalar registers.
+  unsigned long long seg_v = 0ull;
+  if (lane < MASK_WORDS) {
+    s_near[lane] = 0ull;
+    s_src[lane] = 0ull;
+  }
   bool any_src = false;
   if (nd > 0) {
     const double Lx = nx, Ly = I.yper;
@@ -1463,12 +1462,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       const unsigned long long nb = __ballot(w * 64 + lane < nd && mind2[w] <= lim);
       const unsigned long long sb = __ballot(srcf[w]);
       if (lane == w) {
-        near_v = nb;
-        src_v = sb;
+        s_near[w] = nb;
+        s_src[w] = sb;
       }
       any_src = any_src || sb != 0ull;
     }
   }
+  __syncthreads();  // the candidate masks in LDS are complete
   const double tn = (double)(*step);
   const double A = I.A0 * (tn < I.t_star ? tn : I.t_star);
 
@@ -1639,7 +1639,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       const double xd = (double)(x0 + col), yd = (double)r;
       int cnt = 0;
       for (int w = 0; any_src && w < MASK_WORDS; ++w) {
-        unsigned long long m = read_lane64(src_v, w);
+        unsigned long long m = s_src[w];
         while (m) {
           const int k = w * 64 + __ffsll(m) - 1;
           m &= m - 1;
@@ -1667,7 +1667,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           int best = -1;
           double bd = 0.0;
           for (int w = 0; w < MASK_WORDS; ++w) {
-            unsigned long long m = read_lane64(near_v, w);
+            unsigned long long m = s_near[w];
             while (m) {
               const int k = w * 64 + __ffsll(m) - 1;
               m &= m - 1;
