@@ -260,20 +260,40 @@ def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
             "backward_over_forward": round(best_b / best_f, 2)}
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle as it stands on this host's cores, on a bounded sample of the same workload."""
-    from oracle import OracleSim, Params, Drop
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+def oracle_rate(w, budget_s, max_steps=1000):
+    """Full steps of the FP64 oracle on workload w for about budget_s seconds: (MLUPS, steps, seconds, threads)."""
+    from oracle import OracleSim, Params, Drop, num_threads
     s = OracleSim(Params(nx=w.nx, ny=w.ny, **w.params), w.phi0, w.c0, [Drop(**d) for d in w.drop_dicts()])
     steps, t0 = 0, time.perf_counter()
     while True:
         s.run(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 1000:
+        if el >= budget_s or steps >= max_steps:
             break
-    return {"value": round(w.nodes * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{w.name}: {steps} FP64 steps of the full {w.nx}x{w.ny} lattice in {el:.1f} s"}
+    return w.nodes * steps / el / 1e6, steps, el, num_threads()
+
+
+def cpu_baseline(w, budget_s, single_budget_s=8.0, factory="c5_emulsion"):
+    """The FP64 oracle as it stands on this host's cores, on a bounded sample of workload w; also on one thread
+    (a child process with OMP_NUM_THREADS=1, since OpenMP fixes its thread count at start-up), on the workload
+    that workloads.<factory>() builds (the same one)."""
+    import subprocess
+    rate, steps, el, threads = oracle_rate(w, budget_s)
+    out = {"value": round(rate, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{w.name}: {steps} FP64 steps of the full {w.nx}x{w.ny} lattice in {el:.1f} s"}
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; from paper_1711_10984_amd import workloads as W; "
+            "w = W.%s(); r = bench.oracle_rate(w, %r); print(json.dumps(list(r) + [w.nx, w.ny]))"
+            % (os.path.dirname(os.path.abspath(__file__)), factory, single_budget_s))
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, OMP_NUM_THREADS="1"),
+                             capture_output=True, text=True, timeout=600)
+        r1, s1, e1, t1, nx1, ny1 = json.loads(res.stdout.strip().splitlines()[-1])
+        out["single_thread"] = {"value": round(r1, 3), "cores": t1,
+                                "sample": f"{s1} FP64 steps of the full {nx1}x{ny1} lattice in {e1:.1f} s"}
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        out["single_thread"] = {"error": str(e)[:200]}
+    return out
 
 
 def main():

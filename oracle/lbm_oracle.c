@@ -51,6 +51,9 @@
  *    mirror image with u_y reversed (no flow through the plate).  Droplet
  *    distances and centres are not periodic in y.
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -497,6 +500,15 @@ void orc_run(orc_sim* s, int64_t nsteps) {
 }
 
 int orc_stage_count(void) { return ST_COUNT; }
+
+/* Threads the OpenMP loops run on (1 without OpenMP). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void orc_stages(orc_sim* s, double* out) { do_step(s, out); }
 

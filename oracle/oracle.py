@@ -89,6 +89,7 @@ def load():
         lib.orc_free.argtypes = [C.c_void_p]
         lib.orc_run.argtypes = [C.c_void_p, C.c_int64]
         lib.orc_stage_count.restype = C.c_int
+        lib.orc_num_threads.restype = C.c_int
         lib.orc_stages.argtypes = [C.c_void_p, dp]
         lib.orc_get_step.restype = C.c_int64
         lib.orc_get_step.argtypes = [C.c_void_p]
@@ -206,3 +207,8 @@ def div9(k: np.ndarray, X: np.ndarray):
     out = np.empty_like(k)
     load().orc_div9(nx, ny, _ptr(k), _ptr(X), _ptr(out))
     return out
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use in this process."""
+    return int(load().orc_num_threads())
