@@ -294,6 +294,26 @@ def test_instability_is_reported():
 
 
 @pytest.mark.parametrize("path", PATHS)
+def test_nonfinite_state_is_reported(path):
+    """A NaN injected into the initial surfactant field (host-forced) spreads through the stencils; the kernels
+    run on and the observables flag it: nonfinite, LBM_E_UNSTABLE.  A clean run of the same lattice is not
+    flagged."""
+    w = W.c1_equilibrium()
+    c = w.c0.copy()
+    c[10, 20] = np.nan
+    sim = gpu_sim(w, c=c, path=path)
+    sim.step(3)
+    ob = sim.observables()
+    assert ob["nonfinite"] and ob["unstable"]
+    sim.close()
+    clean = gpu_sim(w, path=path)
+    clean.step(3)
+    ob = clean.observables()
+    assert not ob["nonfinite"] and not ob["unstable"]
+    clean.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
 def test_no_droplets_and_tiny_lattice(path):
     w = W.c1_equilibrium()
     f, phi, c = W.random_state(3, 4, 3)

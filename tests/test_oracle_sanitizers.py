@@ -1,0 +1,33 @@
+"""The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (CPU): tests/oracle_sanitize_driver.c runs
+the oracle's C interface on edge-case lattices (3 x 3, 3 x 4 and 37 x 4 with walls, a droplet across both
+periodic edges, both advection forms, no droplets) in a build with -fsanitize=address,undefined; any
+out-of-bounds access, leak or undefined behaviour aborts it with a report."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_oracle_is_clean_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    exe = tmp_path / "oracle_sanitize"
+    cmd = [gcc, "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fopenmp",
+           "-I", os.path.join(ROOT, "oracle"), os.path.join(ROOT, "tests", "oracle_sanitize_driver.c"),
+           "-o", str(exe), "-lm"]
+    b = subprocess.run(cmd, capture_output=True, text=True)
+    if b.returncode != 0 and "sanitize" in b.stderr and "not supported" in b.stderr:
+        pytest.skip("sanitizer runtime not available")
+    assert b.returncode == 0, b.stderr[-2000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0", UBSAN_OPTIONS="print_stacktrace=1",
+               OMP_NUM_THREADS="2")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=300)
+    print(r.stdout)
+    assert r.returncode == 0, (r.stdout + r.stderr)[-3000:]
+    assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr[-3000:]
+    assert r.stdout.count("nonfinite 0") == 7
