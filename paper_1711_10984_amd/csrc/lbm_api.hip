@@ -11,6 +11,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/lbm.h"
 #include "lbm_adjoint.h"
 #include "lbm_internal.h"
@@ -25,6 +27,14 @@ int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
+
+// A named host range on profiler timelines (rocprofv3 --marker-trace); a plain call when no tool is attached.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 #define HIPCHK(call)                                                                          \
   do {                                                                                        \
@@ -668,9 +678,11 @@ int lbm_set_graph(lbm_ctx* c, int32_t steps_per_graph) {
 int lbm_step(lbm_ctx* c, int64_t n) {
   if (!c) return fail(LBM_E_INVAL, "null context");
   if (n < 0) return fail(LBM_E_INVAL, "n must be >= 0");
+  Range range("lbm_step");
   int64_t left = n;
   if (c->graph_steps > 0) {
     while (left >= c->graph_steps) {
+      Range replay("lbm_step graph replay");
       if (!c->exec[c->parity]) {
         int rc = build_graph(c, c->parity);
         if (rc != LBM_OK) return rc;
@@ -698,6 +710,7 @@ int lbm_sync(lbm_ctx* c) {
 int64_t lbm_get_step(const lbm_ctx* c) { return c ? c->step : -1; }
 
 int lbm_fields(lbm_ctx* c, int32_t inst, double* f_pre, double* phi, double* cc, double* n, double* ux, double* uy) {
+  Range range("lbm_fields");
   int rc = check_inst(c, inst);
   if (rc != LBM_OK) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -718,6 +731,7 @@ int lbm_droplets(lbm_ctx* c, int32_t inst, lbm_droplet* out) {
 }
 
 int lbm_observables(lbm_ctx* c, int32_t inst, lbm_obs* obs, double* drop_out) {
+  Range range("lbm_observables");
   int rc = check_inst(c, inst);
   if (rc != LBM_OK) return rc;
   if (!obs) return fail(LBM_E_INVAL, "obs must not be NULL");
@@ -790,6 +804,7 @@ int lbm_debug_stage(lbm_ctx* c, int32_t inst, double* out) {
 }
 
 int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
+  Range range("lbm_time_kernels");
   if (!c || !ms_out) return fail(LBM_E_INVAL, "null argument");
   if (n <= 0) return fail(LBM_E_INVAL, "n must be > 0");
   std::vector<hipEvent_t> ev((size_t)n * 4);
@@ -843,6 +858,7 @@ const int32_t* lbm_tune_rows(void) { return TUNE_ROWS; }
 
 int lbm_autotune(lbm_ctx* c, int32_t launches, int32_t both_paths, int32_t* rows_out, int32_t* path_out,
                  double* ms_out) {
+  Range range("lbm_autotune");
   if (!c) return fail(LBM_E_INVAL, "null context");
   if (launches <= 0) return fail(LBM_E_INVAL, "launches must be > 0");
   constexpr int NR = LBM_TUNE_NROWS, NW = LBM_TUNE_NWIDTHS;
@@ -1263,6 +1279,7 @@ int lbm_adjoint_bytes(const lbm_ctx* c, int64_t nsteps, int32_t every, size_t* b
 
 int lbm_adjoint_forward(lbm_ctx* c, void* ws, size_t bytes, int32_t drop, int64_t nsteps, int32_t every,
                         double* J) {
+  Range range("lbm_adjoint_forward");
   int rc = adj_check(c, drop, nsteps, every);
   if (rc != LBM_OK) return rc;
   if (!ws) return fail(LBM_E_INVAL, "adjoint workspace must not be NULL");
@@ -1294,6 +1311,7 @@ int lbm_adjoint_forward(lbm_ctx* c, void* ws, size_t bytes, int32_t drop, int64_
 }
 
 int lbm_adjoint_backward(lbm_ctx* c, void* ws, size_t bytes, double* dJ_dA0, double* dJ_dc0) {
+  Range range("lbm_adjoint_backward");
   if (!c) return fail(LBM_E_INVAL, "null context");
   if (!c->adj.valid) return fail(LBM_E_STATE, "no forward pass recorded (lbm_adjoint_forward)");
   if (c->step != c->adj.n0 + c->adj.nsteps)

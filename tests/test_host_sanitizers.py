@@ -32,7 +32,8 @@ def test_host_entry_points_clean_under_sanitizers(tmp_path):
     assert r.returncode == 0, r.stderr[-2000:]
     lib = tmp_path / "liblbm_san.so"
     r = subprocess.run([clang + "++", "-shared", "-fsanitize=address,undefined", "-o", str(lib)] + kernels +
-                       [str(api), "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")],
+                       [str(api), "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lrocprofiler-sdk-roctx",
+                        "-Wl,-rpath," + os.path.join(ROCM, "lib")],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     exe = tmp_path / "c_abi_check_san"
