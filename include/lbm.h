@@ -229,8 +229,8 @@ int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
  * surfactant field c at the start of the run, n0.  The adjoint is the exact transpose of the discrete step
  * (Eqs. 3, 5, 10-19) with these held fixed: the nodes inside each production disk, the upwind side chosen by
  * the sign of u in Eqs. (16)-(17) and the droplet masks (phi >= 0, nearest centre); none of them is
- * differentiable.  Contexts of one periodic lattice, LBM_FP64 or LBM_FP32, LBM_ADV_PAPER (LBM_E_INVAL
- * otherwise).
+ * differentiable.  Contexts of one lattice (periodic, or with LBM_WALLS_Y), LBM_FP64 or LBM_FP32,
+ * LBM_ADV_PAPER (LBM_E_INVAL otherwise).
  * Memory: a checkpoint of the state every `every` steps (9 population planes, phi, c), and for the interval
  * being reversed phi, c and 11 FP64 stage planes of each step, plus about 24 planes of one backward step, live
  * in a caller-owned device workspace of lbm_adjoint_bytes bytes (the library allocates nothing); it must stay

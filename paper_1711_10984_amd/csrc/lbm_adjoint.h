@@ -29,6 +29,7 @@ struct AdjPlanes {
 
 struct AdjModel {
   int nx, ny;
+  int walls;  // LBM_WALLS_NONE or LBM_WALLS_Y
   double a, b, B0, B1, D, Gamma, gamma, omega, coef, ramp;  // ramp = min(n, t*): dA(n)/dA0
   double yper;
 };

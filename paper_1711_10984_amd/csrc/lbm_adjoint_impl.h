@@ -1,12 +1,13 @@
-// Reverse-mode (adjoint) kernels of one timestep of the hybrid scheme (Sec. 2, Eqs. 3, 5, 10-19) on a
-// periodic lattice: given the adjoint (f_bar, phi_bar, c_bar) of the state at n + 1 and the forward
-// intermediates of step n, they produce the adjoint of the state at n and the step's contribution to the
-// derivative with respect to the production rate A0.
+// Reverse-mode (adjoint) kernels of one timestep of the hybrid scheme (Sec. 2, Eqs. 3, 5, 10-19) on a lattice
+// periodic in x, and in y or between two plates: given the adjoint (f_bar, phi_bar, c_bar) of the state at n + 1
+// and the forward intermediates of step n, they produce the adjoint of the state at n and the step's
+// contribution to the derivative with respect to the production rate A0.
 //
 // The discrete forward step is differentiated as written (the exact transpose of each operation).  On a
 // periodic lattice the 9-point gradient is antisymmetric and the 9-point Laplacian symmetric, so their
-// transposes are -grad9 and lap9.  Held fixed (non-differentiable): the membership of each node in the
-// production disks, the upwind side chosen by the sign of u in Eqs. (16)-(17), and the droplet masks.
+// transposes are -grad9 and lap9; with walls the mirror ghost rows enter as described at Nbh and G9y_T.
+// Held fixed (non-differentiable): the membership of each node in the production disks, the upwind side chosen
+// by the sign of u in Eqs. (16)-(17), and the droplet masks.
 //
 // Five launches per step, each one stencil layer deep over dense [ny][nx] planes:
 //   K1  gradient planes of the forward fields; adjoint of Eq. (19) (c update, link divergence, production
@@ -25,15 +26,20 @@ namespace {
 
 constexpr int ADJ_THREADS = 256;  // adj_blocks() in lbm_adjoint.h assumes this size
 
-// Periodic 3 x 3 neighbourhood of node (x, y) of a dense plane.
+// 3 x 3 neighbourhood of node (x, y) of a dense plane: periodic in x, and in y without walls.  With walls a
+// row beyond a plate is the mirror image of the boundary row (the forward's ghost rows), and odd(dy) is -1 for
+// such a row: a field that is odd under the mirror (u_y in the forward; the adjoint operand of a transposed
+// y-gradient, see below) changes sign there.
 struct Nbh {
   int x, y, nx;
   int xs[3], ys[3];
+  int sg[3];
   __device__ int d(int dx, int dy) const { return ys[dy + 1] * nx + xs[dx + 1]; }
   __device__ int p(int dx, int dy, int pitch) const { return ys[dy + 1] * pitch + xs[dx + 1]; }
+  __device__ int odd(int dy) const { return sg[dy + 1]; }
 };
 
-__device__ __forceinline__ Nbh make_nbh(int idx, int nx, int ny) {
+__device__ __forceinline__ Nbh make_nbh(int idx, int nx, int ny, int walls) {
   Nbh k;
   k.nx = nx;
   k.y = idx / nx;
@@ -41,10 +47,25 @@ __device__ __forceinline__ Nbh make_nbh(int idx, int nx, int ny) {
   k.xs[0] = k.x == 0 ? nx - 1 : k.x - 1;
   k.xs[1] = k.x;
   k.xs[2] = k.x == nx - 1 ? 0 : k.x + 1;
-  k.ys[0] = k.y == 0 ? ny - 1 : k.y - 1;
+  const bool bot = k.y == 0, top = k.y == ny - 1;
+  k.ys[0] = bot ? (walls ? 0 : ny - 1) : k.y - 1;
   k.ys[1] = k.y;
-  k.ys[2] = k.y == ny - 1 ? 0 : k.y + 1;
+  k.ys[2] = top ? (walls ? ny - 1 : 0) : k.y + 1;
+  k.sg[0] = walls && bot ? -1 : 1;
+  k.sg[1] = 1;
+  k.sg[2] = walls && top ? -1 : 1;
   return k;
+}
+
+// Transposes of the 9-point operators with the mirror ghost rows of the walls.  On a periodic lattice
+// G9x^T = -G9x, G9y^T = -G9y and L9^T = L9.  With walls, the outputs at a boundary row also read the ghost row,
+// which is the boundary row itself, and there are no outputs beyond the plate.  Gathering at node j, both
+// effects together amount to evaluating the same periodic formula with the adjoint operand continued across
+// the plate by its mirror image: even for L9 and G9x (symmetric in y), odd for G9y (antisymmetric in y).
+template <typename T, class V>
+__device__ __forceinline__ T G9y_T(const Nbh& k, V v) {
+  auto w = [&](int dx, int dy) { return T(k.odd(dy)) * v(dx, dy); };
+  return G9y<T>(w);
 }
 
 // 9-point stencils of a value function v(dx, dy), grouped as in the forward kernels.
@@ -84,7 +105,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj1(AdjModel m, AdjFwd f, AdjP
   const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
   double src = 0.0;
   if (idx < N) {
-    const Nbh k = make_nbh(idx, m.nx, m.ny);
+    const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
     const int pitch = p.pitch;
     auto phi = [&](int dx, int dy) { return p.phi[k.p(dx, dy, pitch)]; };
     auto cc = [&](int dx, int dy) { return p.c[k.p(dx, dy, pitch)]; };
@@ -162,7 +183,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj2(AdjModel m, AdjFwd f, AdjP
   const int N = m.nx * m.ny;
   const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
   if (idx >= N) return;
-  const Nbh k = make_nbh(idx, m.nx, m.ny);
+  const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
   const T B0 = T(m.B0), B1 = T(m.B1), b = T(m.b);
   auto BM = [&](int dx, int dy) { const int q = k.d(dx, dy); return (B0 + B1 * T(f.ch[q])) * p.Mb[q]; };
   auto gchxM = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gchx[q] * p.Mb[q]; };
@@ -173,9 +194,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj2(AdjModel m, AdjFwd f, AdjP
   auto gphyM = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gphy[q] * p.Mb[q]; };
   // M = a phi^{1/2} + b (phi^n)^3 - B(c^{1/2}) lap9(phi^{1/2}) - B1 grad9 c^{1/2} . grad9 phi^{1/2};
   // X^{1/2} = (B1/2) |grad9 phi^{1/2}|^2
-  p.phb[idx] = ((p.phb[idx] - L9<T>(BM)) + B1 * (G9x<T>(gchxM) + G9y<T>(gchyM))) -
-               B1 * (G9x<T>(gphxX) + G9y<T>(gphyX));
-  p.chb[idx] = (p.chb[idx] - B1 * p.lph[idx] * p.Mb[idx]) + B1 * (G9x<T>(gphxM) + G9y<T>(gphyM));
+  p.phb[idx] = ((p.phb[idx] - L9<T>(BM)) + B1 * (G9x<T>(gchxM) + G9y_T<T>(k, gchyM))) -
+               B1 * (G9x<T>(gphxX) + G9y_T<T>(k, gphyX));
+  p.chb[idx] = (p.chb[idx] - B1 * p.lph[idx] * p.Mb[idx]) + B1 * (G9x<T>(gphxM) + G9y_T<T>(k, gphyM));
   const T ph0 = p.phi[k.p(0, 0, p.pitch)];
   p.pb[idx] = T(3) * b * (ph0 * ph0) * p.Mb[idx];
 }
@@ -185,10 +206,14 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjP
   const int N = m.nx * m.ny;
   const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
   if (idx >= N) return;
-  const Nbh k = make_nbh(idx, m.nx, m.ny);
+  const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
   const int pitch = p.pitch;
   auto ux = [&](int dx, int dy) { return T(f.ux[k.d(dx, dy)]); };
-  auto uy = [&](int dx, int dy) { return T(f.uy[k.d(dx, dy)]); };
+  // beyond a plate the forward's advection stencil sees u_y reversed
+  auto uy = [&](int dx, int dy) { return T(k.odd(dy)) * T(f.uy[k.d(dx, dy)]); };
+  // With walls the gathered formula below holds as written once ob, g and u_x are continued across a plate by
+  // their mirror images and u_y by its negative mirror image (the outputs at a boundary row read the ghost row,
+  // and no outputs lie beyond the plate).
   // Advection of Eqs. (16)-(17), o(r) = g - [g divu + ux dgx + uy dgy], divu = (ux(E) - ux(W))/2 +
   // (uy(N) - uy(S))/2, dgx = g - g(W) if ux > 0 else g(E) - g (same in y); gathered at node q.
   T uxb = T(0), uyb = T(0);
@@ -218,8 +243,11 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjP
   p.pb[idx] += gb[0];
   T cbv = gb[1];
 
-  // Streaming (Eq. 10): f^{n+1}_i(r + e_i) = f*_i(r)  ->  f*_bar_i(r) = f_bar'_i(r + e_i).
+  // Streaming (Eq. 10): f^{n+1}_i(r + e_i) = f*_i(r)  ->  f*_bar_i(r) = f_bar'_i(r + e_i).  With walls, a
+  // population streamed into a plate returns to r reversed: f^{n+1}_opp(i)(r) = f*_i(r)  ->  f*_bar_i(r) =
+  // f_bar'_opp(i)(r).
   const int EX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, EY9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const int OPP9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
   const T W9[9] = {cst<T>(4.0 / 9.0),  cst<T>(1.0 / 9.0),  cst<T>(1.0 / 9.0),  cst<T>(1.0 / 9.0), cst<T>(1.0 / 9.0),
                    cst<T>(1.0 / 36.0), cst<T>(1.0 / 36.0), cst<T>(1.0 / 36.0), cst<T>(1.0 / 36.0)};
   const T nn = T(f.n[idx]), u = ux(0, 0), v = uy(0, 0), Fx = T(f.Fx[idx]), Fy = T(f.Fy[idx]);
@@ -228,7 +256,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjP
   T nb = T(0), ub = uxb, vb = uyb, Fxb = T(0), Fyb = T(0), fsb[9];
   for (int i = 0; i < 9; ++i) {
     const T ex = T(EX9[i]), ey = T(EY9[i]);
-    fsb[i] = p.fb1[(size_t)i * N + k.d(EX9[i], EY9[i])];
+    const int ty = k.y + EY9[i];
+    fsb[i] = m.walls && (ty < 0 || ty >= m.ny) ? p.fb1[(size_t)OPP9[i] * N + idx]
+                                               : p.fb1[(size_t)i * N + k.d(EX9[i], EY9[i])];
     const T eu = ex * u + ey * v, eF = ex * Fx + ey * Fy;
     // f* = (1 - omega) f + omega feq(n, u) + Fi(u, F) (Eqs. 10, 12, 13)
     const T feq = W9[i] * nn * (((T(1) + T(3) * eu) + T(4.5) * eu * eu) - T(1.5) * usq);
@@ -258,7 +288,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj4(AdjModel m, AdjPlanes<T> p
   const int N = m.nx * m.ny;
   const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
   if (idx >= N) return;
-  const Nbh k = make_nbh(idx, m.nx, m.ny);
+  const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
   const int pitch = p.pitch;
   // F = -phi grad9 mu - grad9 c - c grad9 X (Eq. 14)
   auto Fxb = [&](int dx, int dy) { return p.Fxb[k.d(dx, dy)]; };
@@ -269,9 +299,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj4(AdjModel m, AdjPlanes<T> p
   auto cFy = [&](int dx, int dy) { return p.c[k.p(dx, dy, pitch)] * p.Fyb[k.d(dx, dy)]; };
   const T fx = p.Fxb[idx], fy = p.Fyb[idx];
   p.pb[idx] -= fx * p.gmx[idx] + fy * p.gmy[idx];
-  p.cb[idx] += (G9x<T>(Fxb) + G9y<T>(Fyb)) - (fx * p.gXx[idx] + fy * p.gXy[idx]);
-  p.mub[idx] = G9x<T>(phFx) + G9y<T>(phFy);
-  p.Xb[idx] = G9x<T>(cFx) + G9y<T>(cFy);
+  p.cb[idx] += (G9x<T>(Fxb) + G9y_T<T>(k, Fyb)) - (fx * p.gXx[idx] + fy * p.gXy[idx]);
+  p.mub[idx] = G9x<T>(phFx) + G9y_T<T>(k, phFy);
+  p.Xb[idx] = G9x<T>(cFx) + G9y_T<T>(k, cFy);
 }
 
 template <typename T>
@@ -279,7 +309,7 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj5(AdjModel m, AdjPlanes<T> p
   const int N = m.nx * m.ny;
   const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
   if (idx >= N) return;
-  const Nbh k = make_nbh(idx, m.nx, m.ny);
+  const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
   const int pitch = p.pitch;
   const T a = T(m.a), b = T(m.b), B0 = T(m.B0), B1 = T(m.B1);
   // mu = a phi + b phi^3 - B(c) lap9 phi - B1 grad9 phi . grad9 c;  X = (B1/2) |grad9 phi|^2 (Eqs. 3, 5)
@@ -291,9 +321,9 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj5(AdjModel m, AdjPlanes<T> p
   auto gpxX = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gpx[q] * p.Xb[q]; };
   auto gpyX = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gpy[q] * p.Xb[q]; };
   const T ph = p.phi[k.p(0, 0, pitch)], mb = p.mub[idx];
-  p.pb[idx] += (((a + T(3) * b * (ph * ph)) * mb - L9<T>(BMu)) + B1 * (G9x<T>(gcxMu) + G9y<T>(gcyMu))) -
-               B1 * (G9x<T>(gpxX) + G9y<T>(gpyX));
-  p.cb[idx] += B1 * (G9x<T>(gpxMu) + G9y<T>(gpyMu)) - B1 * p.lp[idx] * mb;
+  p.pb[idx] += (((a + T(3) * b * (ph * ph)) * mb - L9<T>(BMu)) + B1 * (G9x<T>(gcxMu) + G9y_T<T>(k, gcyMu))) -
+               B1 * (G9x<T>(gpxX) + G9y_T<T>(k, gpyX));
+  p.cb[idx] += B1 * (G9x<T>(gpxMu) + G9y_T<T>(k, gpyMu)) - B1 * p.lp[idx] * mb;
 }
 
 template <typename T>

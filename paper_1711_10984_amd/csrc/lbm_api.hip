@@ -1063,7 +1063,6 @@ int adj_check(const lbm_ctx* c, int32_t drop, int64_t nsteps, int32_t every) {
   const lbm_config& g = c->cfg[0];
   if (g.precision != LBM_FP64 && g.precision != LBM_FP32)
     return fail(LBM_E_INVAL, "the adjoint runs in LBM_FP64 or LBM_FP32");
-  if (g.walls != LBM_WALLS_NONE) return fail(LBM_E_INVAL, "the adjoint is implemented for periodic lattices");
   if (g.advection != LBM_ADV_PAPER) return fail(LBM_E_INVAL, "the adjoint is implemented for LBM_ADV_PAPER");
   if (drop < 0 || drop >= c->L.inst[0].ndrop) return fail(LBM_E_INVAL, "droplet index out of range");
   if (nsteps < 1 || every < 1) return fail(LBM_E_INVAL, "nsteps and checkpoint interval must be >= 1");
@@ -1177,6 +1176,7 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
   m.omega = d.omega;
   m.coef = d.coef;
   m.yper = d.yper;
+  m.walls = d.walls;
   m.ramp = 0.0;
   auto planes = [&](const char* sslot, T* in, T* out) {
     AdjPlanes<T> p;

@@ -11,6 +11,8 @@ membership, the upwind sides and the droplet masks fixed; a perturbation of 1e-6
   sides there, and the differences then see the kinks of the piecewise-smooth map (they converge to the
   adjoint only erratically, 1e-4 .. 1e-2 at h = 1e-4 .. 1e-7 for such directions, against 2e-6 at h = 1e-6
   for directions near the droplet);
+* between plates: J, dJ/dA0 and dJ/dpsi at nodes on and next to both plates against the oracle's
+  differences, on all three paths;
 * FP32 adjoint against the FP64 one; the torch.autograd wrapper; the state is restored and a second
   backward pass repeats the first bit for bit; the checkpoint interval and the kernel path leave the gradients
   unchanged bit for bit.
@@ -118,6 +120,44 @@ def test_gradients_against_oracle_differences(path):
         ad = float(np.sum(dc0 * v))
         print("directional derivative adjoint", ad, "oracle differences", fd)
         assert abs(ad - fd) <= 2e-5 * abs(fd) + 1e-9
+
+
+def _near_wall_workload():
+    """A droplet of radius 10 three nodes from the lower plate (64 x 40, plates at y = -1/2 and 39.5), production
+    on the +x side, surfactant 0.1 everywhere."""
+    d = W.DropSpec(x=32.0, y=13.0, R=10.0, Rs=2.5, ex=1.0, ey=0.0, active=1, psi_front=0.1, psi_back=0.1)
+    phi, psi = W.droplet_fields(64, 40, [d], psi_out=0.1, seed=51)
+    params = dict(W.PAPER_EQUILIBRIUM, tau=0.6, gamma=1.5e-3, A0=2e-6, walls=1)
+    return W.Workload("plates_64x40_near_wall", 64, 40, params, phi, psi, [d])
+
+
+@pytest.mark.parametrize("path", [0, 1, 2])
+def test_walls_gradients_against_oracle_differences(path):
+    """Reverse mode between plates: J agrees with the oracle's forward run; dJ/dA0 and dJ/dc(n0) at single
+    nodes agree with the oracle's central differences.  The nodes include both plate rows and the rows next to
+    them, below the droplet and far from it, so the mirror and bounce-back transposes are exercised.  Single
+    nodes, not random directions: the fluid is nearly at rest along the plates, and a direction spread over
+    many nodes there flips upwind sides within h = 1e-5 (single-node differences agree to 1e-5 between
+    h = 1e-6 and 1e-7)."""
+    w = _near_wall_workload()
+    N = 200
+    s, J, dA0, dc0 = adjoint(w, N, 50, path=path)
+    s.close()
+    A0 = w.params["A0"]
+    assert abs(J - _oracle_J(w, w.c0, A0, N)) < 1e-12
+    # steps of 1e-3 A0 and more flip upwind sides along the plates (the differences move by 1 % between
+    # steps of 1e-3 and 3e-3 A0); at 1e-4 and 1e-5 A0 they agree with each other to 1e-15
+    hA = 1e-4 * A0
+    fdA = (_oracle_J(w, w.c0, A0 + hA, N) - _oracle_J(w, w.c0, A0 - hA, N)) / (2 * hA)
+    print("walls: dJ/dA0 adjoint", dA0, "oracle differences", fdA)
+    assert abs(dA0 - fdA) <= 1e-5 * abs(fdA)
+    h = 1e-6
+    for y, x in ((0, 32), (1, 32), (2, 30), (0, 5), (39, 32), (38, 20), (13, 42), (13, 22)):
+        v = np.zeros_like(w.c0)
+        v[y, x] = 1.0
+        fd = (_oracle_J(w, w.c0 + h * v, A0, N) - _oracle_J(w, w.c0 - h * v, A0, N)) / (2 * h)
+        print("walls: dJ/dc", (y, x), "adjoint", dc0[y, x], "oracle differences", fd)
+        assert abs(dc0[y, x] - fd) <= 2e-5 * abs(fd) + 1e-9
 
 
 def test_fp32_adjoint_tracks_fp64():
