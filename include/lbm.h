@@ -153,7 +153,8 @@ int64_t lbm_get_step(const lbm_ctx* ctx);
 
 /* Copy instance `inst` to host arrays (any may be NULL): pre-collision populations f_pre
  * [9][ny][nx] at time n, phi, c, and the density and velocity of Eq. (11) at time n (with half
- * the force of Eq. 14 computed from the current phi, c).  Synchronous. */
+ * the force of Eq. 14 computed from the current phi, c).  Synchronous.  Returns LBM_E_UNSTABLE
+ * (after filling the arrays) if a value it returns is non-finite. */
 int lbm_fields(lbm_ctx* ctx, int32_t inst, double* f_pre, double* phi, double* c, double* n, double* ux,
                double* uy);
 

@@ -714,9 +714,21 @@ int lbm_fields(lbm_ctx* c, int32_t inst, double* f_pre, double* phi, double* cc,
   int rc = check_inst(c, inst);
   if (rc != LBM_OK) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
-  return with_types(c->L.prec, [&](auto t, auto p) {
+  rc = with_types(c->L.prec, [&](auto t, auto p) {
     return fields_impl<decltype(t), decltype(p)>(c, inst, f_pre, phi, cc, n, ux, uy);
   });
+  if (rc != LBM_OK) return rc;
+  // a non-finite state surfaces here as well as in lbm_observables (the arrays are filled regardless)
+  const size_t np = (size_t)c->L.inst[inst].nx * c->L.inst[inst].ny;
+  const struct {
+    const double* a;
+    size_t n;
+  } outs[6] = {{f_pre, 9 * np}, {phi, np}, {cc, np}, {n, np}, {ux, np}, {uy, np}};
+  for (const auto& o : outs)
+    if (o.a)
+      for (size_t i = 0; i < o.n; ++i)
+        if (!std::isfinite(o.a[i])) return fail(LBM_E_UNSTABLE, "non-finite values in the state");
+  return LBM_OK;
 }
 
 int lbm_droplets(lbm_ctx* c, int32_t inst, lbm_droplet* out) {

@@ -160,16 +160,6 @@ __device__ __forceinline__ T collide1(T f, T wn, T cw, T eu, T eF, T exu, T eyu,
   return (f - omega * (f - feq)) + Fi;
 }
 
-// The same collision for a deviation d = f - w n0 from the rest population, with dn = n - n0:
-// d* = d - omega (d - deq) + Fi, deq = feq - w n0 = w dn + w n (3 e.u + 4.5 (e.u)^2 - 1.5 u^2).
-template <typename T>
-__device__ __forceinline__ T collide1_dev(T d, T w, T dn, T wn, T cw, T eu, T eF, T exu, T eyu, T Fx, T Fy,
-                                          T usq, T omega) {
-  const T deq = w * dn + wn * (((T(3) * eu) + (T(4.5) * eu) * eu) - T(1.5) * usq);
-  const T Fi = cw * (T(3) * (exu * Fx + eyu * Fy) + (T(9) * eu) * eF);
-  return (d - omega * (d - deq)) + Fi;
-}
-
 // Constants of the lattice-Boltzmann part of a node: weights w_i, (1 - 1/(2 tau)) w_i, 1/tau, the rest
 // populations w_i n0 in the arithmetic type, and n0.
 template <typename T>
@@ -199,43 +189,83 @@ __device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k,
   }
   const T mx = (d[1] + (d[5] + d[8])) - (d[3] + (d[6] + d[7]));
   const T my = (d[2] + (d[5] + d[6])) - (d[4] + (d[7] + d[8]));
-  ux = (mx + T(0.5) * Fx) / nn;
-  uy = (my + T(0.5) * Fy) / nn;
+  if constexpr (sizeof(T) == 8) {
+    ux = (mx + T(0.5) * Fx) / nn;
+    uy = (my + T(0.5) * Fy) / nn;
+  } else {  // one division
+    const T rn = T(1) / nn;
+    ux = (mx + T(0.5) * Fx) * rn;
+    uy = (my + T(0.5) * Fy) * rn;
+  }
 }
 
 // BGK collision with forcing of one node (Eqs. 10, 12, 13) after lb_moments: out receives the values to store,
 // s the post-collision populations (for the stage export).  FP64 relaxes and stores the populations as the
-// oracle does.  FP32 and FP16 storage relax the deviations (collide1_dev) and store d* (in FP32, or rounded to
-// FP16); s is then d* + w_i n0 summed in double.
+// oracle does.  FP32 and FP16 storage relax the deviations and store d* (in FP32, or rounded to FP16); s is then
+// d* + w_i n0 summed in double.  Their arithmetic is arranged for fewer instructions, with the same equations:
+//   d_eq_i = w_i dn + w_i n p_i,   p_i = (3 + 4.5 e.u) e.u - 1.5 u.u
+//   F_i    = 3 (1 - 1/(2 tau)) w_i h_i,   h_i = (e.F - u.F) + 3 (e.u)(e.F)
+//   d*_i   = d_i + omega (d_eq_i - d_i) + F_i
+// so that each moving direction costs nine operations, and u.u, u.F and the per-weight products are shared.
+// A deviation d* in the storage type.  FP16 storage keeps fp16(d*) of the FP32 value d*: the empty asm makes
+// d* opaque, so that the compiler cannot fuse the last FMA of d* with the conversion into one mixed-precision
+// instruction that rounds only once.
+template <typename P>
+__device__ __forceinline__ P store_dev(float ds) {
+  if constexpr (sizeof(P) == 2) asm("" : "+v"(ds));
+  return P(ds);
+}
+
 template <typename T, typename P>
 __device__ __forceinline__ void lb_collide(const T (&d)[9], T dn, T nn, T ux, T uy, T Fx, T Fy, const LbConst<T>& k,
                                            P (&out)[9], double (&s)[9]) {
   const T usq = ux * ux + uy * uy;
-  const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
   const T wn0 = k.w0 * nn, wn1 = k.w1 * nn, wn5 = k.w5 * nn;
-  const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
-  // direction i with weight w, w n, (1 - 1/(2 tau)) w, rest population wr, e.u, e.F, e_x - u_x, e_y - u_y
-  auto one = [&](int i, T w, T wn, T cw, T wr, T eu, T eF, T exu, T eyu) {
-    if constexpr (sizeof(T) == 8) {
-      (void)w;
+  if constexpr (sizeof(T) == 8) {
+    const T nux = -ux, nuy = -uy, nFx = -Fx, nFy = -Fy;
+    const T xp1 = T(1) - ux, xm1 = T(-1) - ux, yp1 = T(1) - uy, ym1 = T(-1) - uy;
+    // direction i with w n, (1 - 1/(2 tau)) w, rest population wr, e.u, e.F, e_x - u_x, e_y - u_y
+    auto one = [&](int i, T wn, T cw, T wr, T eu, T eF, T exu, T eyu) {
       const T f = collide1(d[i], wn, cw, eu, eF, exu, eyu, Fx, Fy, usq, k.omega);
       s[i] = f;
       out[i] = pop_st<P>(f, wr);
-    } else {
-      const T ds = collide1_dev(d[i], w, dn, wn, cw, eu, eF, exu, eyu, Fx, Fy, usq, k.omega);
+    };
+    one(0, wn0, k.cw0, k.wr0, T(0), T(0), nux, nuy);
+    one(1, wn1, k.cw1, k.wr1, ux, Fx, xp1, nuy);
+    one(2, wn1, k.cw1, k.wr1, uy, Fy, nux, yp1);
+    one(3, wn1, k.cw1, k.wr1, nux, nFx, xm1, nuy);
+    one(4, wn1, k.cw1, k.wr1, nuy, nFy, nux, ym1);
+    one(5, wn5, k.cw5, k.wr5, ux + uy, Fx + Fy, xp1, yp1);
+    one(6, wn5, k.cw5, k.wr5, nux + uy, nFx + Fy, xm1, yp1);
+    one(7, wn5, k.cw5, k.wr5, nux + nuy, nFx + nFy, xm1, ym1);
+    one(8, wn5, k.cw5, k.wr5, ux - uy, Fx - Fy, xp1, ym1);
+  } else {
+    const T A = T(-1.5) * usq, uF = ux * Fx + uy * Fy;
+    const T wd0 = k.w0 * dn, wd1 = k.w1 * dn, wd5 = k.w5 * dn;
+    const T k0 = T(3) * k.cw0, k1 = T(3) * k.cw1, k5 = T(3) * k.cw5;
+    auto one = [&](int i, T wd, T wn, T kc, T wr, T eu, T eF) {
+      const T p = (T(3) + T(4.5) * eu) * eu + A;
+      const T deq = wn * p + wd;
+      const T h = (T(3) * eu) * eF + (eF - uF);
+      T ds = kc * h + (k.omega * (deq - d[i]) + d[i]);
       s[i] = (double)ds + (double)wr;
-      out[i] = P(ds);
+      out[i] = store_dev<P>(ds);
+    };
+    {  // rest population: e = 0
+      const T deq = wn0 * A + wd0;
+      T ds = k0 * (-uF) + (k.omega * (deq - d[0]) + d[0]);
+      s[0] = (double)ds + (double)k.wr0;
+      out[0] = store_dev<P>(ds);
     }
-  };
-  one(0, k.w0, wn0, k.cw0, k.wr0, T(0), T(0), nux, nuy);
-  one(1, k.w1, wn1, k.cw1, k.wr1, ux, Fx, xp1, nuy);
-  one(2, k.w1, wn1, k.cw1, k.wr1, uy, Fy, nux, yp1);
-  one(3, k.w1, wn1, k.cw1, k.wr1, nux, nFx, xm1, nuy);
-  one(4, k.w1, wn1, k.cw1, k.wr1, nuy, nFy, nux, ym1);
-  one(5, k.w5, wn5, k.cw5, k.wr5, ux + uy, Fx + Fy, xp1, yp1);
-  one(6, k.w5, wn5, k.cw5, k.wr5, nux + uy, nFx + Fy, xm1, yp1);
-  one(7, k.w5, wn5, k.cw5, k.wr5, nux + nuy, nFx + nFy, xm1, ym1);
-  one(8, k.w5, wn5, k.cw5, k.wr5, ux - uy, Fx - Fy, xp1, ym1);
+    one(1, wd1, wn1, k1, k.wr1, ux, Fx);
+    one(2, wd1, wn1, k1, k.wr1, uy, Fy);
+    one(3, wd1, wn1, k1, k.wr1, -ux, -Fx);
+    one(4, wd1, wn1, k1, k.wr1, -uy, -Fy);
+    one(5, wd5, wn5, k5, k.wr5, ux + uy, Fx + Fy);
+    one(6, wd5, wn5, k5, k.wr5, uy - ux, Fy - Fx);
+    one(7, wd5, wn5, k5, k.wr5, -(ux + uy), -(Fx + Fy));
+    one(8, wd5, wn5, k5, k.wr5, ux - uy, Fx - Fy);
+  }
 }
 
 // Sum (or min/max) over the workgroup in a fixed order; every thread receives lane 0's result.
@@ -259,6 +289,32 @@ __device__ double block_reduce(double v, double* sh, Op op) {
   for (int w = 1; w < NTHREADS / 64; ++w) r = op(r, sh[w]);
   __syncthreads();
   return r;
+}
+
+// Sum of three values over the workgroup in a fixed order (lane 0's butterfly result per wave, waves
+// in order); every thread receives the result.
+__device__ __forceinline__ void block_reduce3(double& a, double& b, double& c, double (*red)[3]) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wv][0] = a;
+    red[wv][1] = b;
+    red[wv][2] = c;
+  }
+  __syncthreads();
+  a = red[0][0];
+  b = red[0][1];
+  c = red[0][2];
+  for (int w = 1; w < NTHREADS / 64; ++w) {
+    a += red[w][0];
+    b += red[w][1];
+    c += red[w][2];
+  }
+  __syncthreads();
 }
 
 // Droplet bookkeeping of one tile: candidate lists for the nearest-centre assignment and for the
@@ -677,7 +733,7 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(int tiling, int ndrop_total
                                                      const double* __restrict__ part,
                                                      const uint64_t* __restrict__ mask,
                                                      int64_t* __restrict__ step, int increment) {
-  __shared__ double red[NTHREADS / 64];
+  __shared__ double red[NTHREADS / 64][3];
   const int g = blockIdx.x;
   if (g == 0 && threadIdx.x == 0 && increment) *step = *step + 1;
   if (g >= ndrop_total) return;
@@ -687,22 +743,30 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(int tiling, int ndrop_total
   const int ntl = I.tiles_x[tiling] * I.tiles_y[tiling];
   const int64_t tb = I.tile_base[tiling];
   const double* pb = part + I.part_base[tiling];
+  // Thread t adds the partials of tiles t, t + NTHREADS, ... in increasing order; the presence bits of UNR
+  // of its tiles are loaded together so that their latencies overlap.
+  constexpr int UNR = 4;
+  const int word = k >> 6;
+  const unsigned long long bit = 1ull << (k & 63);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int tl = threadIdx.x; tl < ntl; tl += NTHREADS) {
-    const int64_t t = tb + tl;
-    if ((mask[t * MASK_WORDS + (k >> 6)] >> (k & 63)) & 1ull) {
-      const double* p = pb + ((int64_t)tl * I.ndrop + k) * 3;
-      a0 += p[0];
-      a1 += p[1];
-      a2 += p[2];
+  for (int base = threadIdx.x; base < ntl; base += UNR * NTHREADS) {
+    unsigned long long m[UNR];
+    for (int u = 0; u < UNR; ++u) {
+      const int tl = base + u * NTHREADS;
+      m[u] = tl < ntl ? mask[(tb + tl) * MASK_WORDS + word] : 0ull;
     }
+    for (int u = 0; u < UNR; ++u)
+      if (m[u] & bit) {
+        const double* p = pb + ((int64_t)(base + u * NTHREADS) * I.ndrop + k) * 3;
+        a0 += p[0];
+        a1 += p[1];
+        a2 += p[2];
+      }
   }
-  const double s0 = block_reduce(a0, red, OpAdd());
-  const double s1 = block_reduce(a1, red, OpAdd());
-  const double s2 = block_reduce(a2, red, OpAdd());
-  if (threadIdx.x == 0 && s0 > 0.0) {
-    drops[g].x = wrapd(d.x + s1 / s0, (double)I.nx);
-    drops[g].y = wrapd(d.y + s2 / s0, I.yper);
+  block_reduce3(a0, a1, a2, red);
+  if (threadIdx.x == 0 && a0 > 0.0) {
+    drops[g].x = wrapd(d.x + a1 / a0, (double)I.nx);
+    drops[g].y = wrapd(d.y + a2 / a0, I.yper);
   }
 }
 
@@ -864,32 +928,6 @@ __device__ __forceinline__ T advect_n(T gc, T ge, T gw, T gn, T gs, T uc, T ue, 
   const T Ft = uyt * (uyt >= T(0) ? gc : gn);
   const T Fb = uyb * (uyb >= T(0) ? gs : gc);
   return gc - ((Fr - Fl) + (Ft - Fb));
-}
-
-// Sum of three values over the workgroup in a fixed order (lane 0's butterfly result per wave, waves
-// in order); every thread receives the result.
-__device__ __forceinline__ void block_reduce3(double& a, double& b, double& c, double (*red)[3]) {
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_xor(a, o, 64);
-    b += __shfl_xor(b, o, 64);
-    c += __shfl_xor(c, o, 64);
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[wv][0] = a;
-    red[wv][1] = b;
-    red[wv][2] = c;
-  }
-  __syncthreads();
-  a = red[0][0];
-  b = red[0][1];
-  c = red[0][2];
-  for (int w = 1; w < NTHREADS / 64; ++w) {
-    a += red[w][0];
-    b += red[w][1];
-    c += red[w][2];
-  }
-  __syncthreads();
 }
 
 template <typename T, typename P, bool DBG>

@@ -188,9 +188,10 @@ def lbm_get_step(ctx: int) -> int:
     return int(load_library().lbm_get_step(C.c_void_p(ctx)))
 
 
-def lbm_fields(ctx: int, inst: int, f_pre=None, phi=None, c=None, n=None, ux=None, uy=None) -> None:
-    _check(load_library().lbm_fields(C.c_void_p(ctx), inst, _dptr(f_pre), _dptr(phi), _dptr(c), _dptr(n),
-                                     _dptr(ux), _dptr(uy)))
+def lbm_fields(ctx: int, inst: int, f_pre=None, phi=None, c=None, n=None, ux=None, uy=None) -> int:
+    """Returns LBM_OK, or LBM_E_UNSTABLE when a returned value is non-finite (the arrays are filled)."""
+    return _check(load_library().lbm_fields(C.c_void_p(ctx), inst, _dptr(f_pre), _dptr(phi), _dptr(c), _dptr(n),
+                                            _dptr(ux), _dptr(uy)), allow=(LBM_E_UNSTABLE,))
 
 
 def lbm_observables(ctx: int, inst: int, drop_out: Optional[np.ndarray]):

@@ -296,8 +296,8 @@ def test_instability_is_reported():
 @pytest.mark.parametrize("path", PATHS)
 def test_nonfinite_state_is_reported(path):
     """A NaN injected into the initial surfactant field (host-forced) spreads through the stencils; the kernels
-    run on and the observables flag it: nonfinite, LBM_E_UNSTABLE.  A clean run of the same lattice is not
-    flagged."""
+    run on and the observables flag it (nonfinite, LBM_E_UNSTABLE), as does lbm_fields (LBM_E_UNSTABLE, the
+    arrays filled).  A clean run of the same lattice is not flagged."""
     w = W.c1_equilibrium()
     c = w.c0.copy()
     c[10, 20] = np.nan
@@ -305,11 +305,15 @@ def test_nonfinite_state_is_reported(path):
     sim.step(3)
     ob = sim.observables()
     assert ob["nonfinite"] and ob["unstable"]
+    phi = np.empty((w.ny, w.nx))
+    lbm = _lbm()
+    assert lbm.lbm_fields(sim.ctx, 0, phi=phi) == lbm.LBM_E_UNSTABLE and not np.isfinite(phi).all()
     sim.close()
     clean = gpu_sim(w, path=path)
     clean.step(3)
     ob = clean.observables()
     assert not ob["nonfinite"] and not ob["unstable"]
+    assert lbm.lbm_fields(clean.ctx, 0, phi=phi) == lbm.LBM_OK and np.isfinite(phi).all()
     clean.close()
 
 
