@@ -871,6 +871,9 @@ __global__ __launch_bounds__(NTHREADS) void k_obs(int parity, const TileDev* __r
 // Each sweep iteration advances every stage by FUSED_R rows (one wavefront per row).  Stage s needs rows
 // r-1..r+1 of stage s-1, which the one-row skew provides without recomputing any row in y; only the
 // 5 halo columns per side are computed twice (by both neighbouring strips).
+// Nearest-centre candidates of a segment whose centre-of-mass sums the sweeping kernels accumulate per lane
+// (or per thread) across rows; further candidates (rare) are reduced row by row.
+constexpr int CM_SLOTS = 4;
 constexpr int RING = 8;
 
 struct FusedShared {
@@ -1426,14 +1429,19 @@ __device__ __forceinline__ T div9n(const Nbr<T>& c, const Nbr<T>& X, T D) {
 template <typename T, typename P, bool DBG>
 // Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD; FP32
 // fits four (127 registers) and FP16 storage three.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : sizeof(P) == 4 ? 4 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
                                              const InstDev* __restrict__ insts, T* __restrict__ buf,
                                              const DropDev* __restrict__ drops, double* __restrict__ part,
                                              uint64_t* __restrict__ mask, const int64_t* __restrict__ step,
                                              double* __restrict__ dbg, int dbg_inst) {
-  __shared__ double acc[MAXDROP][3];
+  // centre-of-mass sums of the segment's first CM_SLOTS nearest-centre candidates, per lane (a lane adds its
+  // own nodes row after row; one butterfly per slot at the end of the segment)
+  __shared__ double acc[CM_SLOTS][3][64];
   // droplet candidates of this segment (read-only after set-up): near the box, and production disks reaching it
   __shared__ unsigned long long s_near[MASK_WORDS], s_src[MASK_WORDS];
+  // slot of each droplet (CM_SLOTS: none) and droplet of each slot
+  __shared__ unsigned char s_slot[MAXDROP];
+  __shared__ int s_cand[CM_SLOTS];
 
   const TileDev sd = segs[blockIdx.x];
   if (sd.inst < 0) return;
@@ -1506,6 +1514,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       any_src = any_src || sb != 0ull;
     }
   }
+  for (int s = 0; s < CM_SLOTS; ++s) acc[s][0][lane] = acc[s][1][lane] = acc[s][2][lane] = 0.0;
+  if (nd > 0) {
+    __syncthreads();  // s_near complete
+    int before = 0;   // candidates among droplets below 64 w
+    for (int w = 0; w < MASK_WORDS; ++w) {
+      const unsigned long long m = s_near[w];
+      const int k = w * 64 + lane;
+      const int r = before + __popcll(m & ((1ull << lane) - 1ull));
+      const bool cand = (m >> lane) & 1ull;
+      s_slot[k] = (unsigned char)(cand && r < CM_SLOTS ? r : CM_SLOTS);
+      if (cand && r < CM_SLOTS) s_cand[r] = k;
+      before += __popcll(m);
+    }
+  }
+  unsigned slots_met = 0u;  // wave-uniform: slot s received a node
+  const int t_local = sd.t - I.tile_base[TILING_FUSED];
+  double* const part_t = part + I.part_base[TILING_FUSED] + (int64_t)t_local * nd * 3;
   __syncthreads();  // the candidate masks in LDS are complete
   const double tn = (double)(*step);
   const double A = I.A0 * (tn < I.t_star ? tn : I.t_star);
@@ -1725,9 +1750,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           cv2 = v * minimg(yd - d.y, I.yper);
         }
       }
-      // per-row wave sums of the centre-of-mass contributions, one droplet at a time (fixed butterfly order)
-      if (!DBG && nd > 0) {
-        unsigned long long pend = __ballot(kd >= 0);
+      // centre-of-mass contributions: candidate number r of the segment (in droplet order) has slot r; a lane
+      // adds its node to its slot.  Candidates beyond the slots (rare) take the row's wave sum (fixed
+      // butterfly order) straight into the strip's partials.
+      if (!DBG && nd > 0 && __ballot(kd >= 0) != 0ull) {
+        const int slot = kd >= 0 ? (int)s_slot[kd] : CM_SLOTS;
+        if (slot < CM_SLOTS) {
+          acc[slot][0][lane] += cv0;
+          acc[slot][1][lane] += cv1;
+          acc[slot][2][lane] += cv2;
+        }
+        for (int s = 0; s < CM_SLOTS; ++s)
+          if (__ballot(slot == s) != 0ull) slots_met |= 1u << s;
+        unsigned long long pend = __ballot(slot == CM_SLOTS && kd >= 0);
         while (pend) {
           const int k = __builtin_amdgcn_readlane(kd, __ffsll(pend) - 1);
           const bool sel = kd == k;
@@ -1741,14 +1776,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           const bool seen = (read_lane64(seg_v, k >> 6) & bit) != 0ull;
           if (lane == (k >> 6)) seg_v |= bit;
           if (lane == 0) {
+            double* const p = part_t + (int64_t)k * 3;
             if (seen) {
-              acc[k][0] += s0;
-              acc[k][1] += s1;
-              acc[k][2] += s2;
+              p[0] += s0;
+              p[1] += s1;
+              p[2] += s2;
             } else {
-              acc[k][0] = s0;
-              acc[k][1] = s1;
-              acc[k][2] = s2;
+              p[0] = s0;
+              p[1] = s1;
+              p[2] = s2;
             }
           }
           pend &= ~__ballot(sel);
@@ -1769,15 +1805,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       if (it + j < nit) sweep(it + j, pfs[j]);
   }
   if (DBG || nd == 0) return;
-  __syncthreads();  // acc was written by lane 0
-  const int t_local = sd.t - I.tile_base[TILING_FUSED];
-  for (int w = 0; w < MASK_WORDS; ++w) {
-    const int k = w * 64 + lane;
-    if (k < nd && ((read_lane64(seg_v, w) >> lane) & 1ull)) {
-      double* p = part + I.part_base[TILING_FUSED] + ((int64_t)t_local * nd + k) * 3;
-      p[0] = acc[k][0];
-      p[1] = acc[k][1];
-      p[2] = acc[k][2];
+  // the slots' wave sums (fixed butterfly order), for the candidates that received nodes
+  for (int s = 0; s < CM_SLOTS; ++s) {
+    if (!(slots_met & (1u << s))) continue;
+    const int k = s_cand[s];
+    double s0 = acc[s][0][lane], s1 = acc[s][1][lane], s2 = acc[s][2][lane];
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o, 64);
+      s1 += __shfl_xor(s1, o, 64);
+      s2 += __shfl_xor(s2, o, 64);
+    }
+    if (lane == (k >> 6)) seg_v |= 1ull << (k & 63);
+    if (lane == 0) {
+      double* const p = part_t + (int64_t)k * 3;
+      p[0] = s0;
+      p[1] = s1;
+      p[2] = s2;
     }
   }
   if (lane < MASK_WORDS) mask[(int64_t)sd.t * MASK_WORDS + lane] = seg_v;
