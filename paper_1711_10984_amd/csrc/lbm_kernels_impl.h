@@ -1442,6 +1442,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   // slot of each droplet (CM_SLOTS: none) and droplet of each slot
   __shared__ unsigned char s_slot[MAXDROP];
   __shared__ int s_cand[CM_SLOTS];
+  __shared__ double s_cxy[CM_SLOTS][2];  // centre of each slot's droplet
 
   const TileDev sd = segs[blockIdx.x];
   if (sd.inst < 0) return;
@@ -1515,18 +1516,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
   }
   for (int s = 0; s < CM_SLOTS; ++s) acc[s][0][lane] = acc[s][1][lane] = acc[s][2][lane] = 0.0;
+  int ncand = 0;  // wave-uniform: number of nearest-centre candidates
   if (nd > 0) {
     __syncthreads();  // s_near complete
-    int before = 0;   // candidates among droplets below 64 w
     for (int w = 0; w < MASK_WORDS; ++w) {
       const unsigned long long m = s_near[w];
       const int k = w * 64 + lane;
-      const int r = before + __popcll(m & ((1ull << lane) - 1ull));
+      const int r = ncand + __popcll(m & ((1ull << lane) - 1ull));  // candidates below droplet k
       const bool cand = (m >> lane) & 1ull;
       s_slot[k] = (unsigned char)(cand && r < CM_SLOTS ? r : CM_SLOTS);
-      if (cand && r < CM_SLOTS) s_cand[r] = k;
-      before += __popcll(m);
+      if (cand && r < CM_SLOTS) {
+        const DropDev d = drops[I.drop_base + k];
+        s_cand[r] = k;
+        s_cxy[r][0] = d.x;
+        s_cxy[r][1] = d.y;
+      }
+      ncand += __popcll(m);
     }
+    ncand = __builtin_amdgcn_readfirstlane(ncand);
   }
   unsigned slots_met = 0u;  // wave-uniform: slot s received a node
   const int t_local = sd.t - I.tile_base[TILING_FUSED];
@@ -1727,27 +1734,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         }
         const double v = (double)phn;
         if (!DBG && nd > 0 && v >= 0.0) {
+          // nearest centre among the candidates (a single candidate is the nearest)
           int best = -1;
-          double bd = 0.0;
-          for (int w = 0; w < MASK_WORDS; ++w) {
-            unsigned long long m = s_near[w];
-            while (m) {
-              const int k = w * 64 + __ffsll(m) - 1;
-              m &= m - 1;
-              const DropDev d = drops[I.drop_base + k];
-              const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, I.yper);
-              const double d2 = dx * dx + dy * dy;
-              if (best < 0 || d2 < bd) {
-                best = k;
-                bd = d2;
+          if (ncand == 1) {
+            best = s_cand[0];
+          } else {
+            double bd = 0.0;
+            for (int w = 0; w < MASK_WORDS; ++w) {
+              unsigned long long m = s_near[w];
+              while (m) {
+                const int k = w * 64 + __ffsll(m) - 1;
+                m &= m - 1;
+                const DropDev d = drops[I.drop_base + k];
+                const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, I.yper);
+                const double d2 = dx * dx + dy * dy;
+                if (best < 0 || d2 < bd) {
+                  best = k;
+                  bd = d2;
+                }
               }
             }
           }
-          const DropDev d = drops[I.drop_base + best];
+          const int sl = s_slot[best];
+          double cx, cy;
+          if (sl < CM_SLOTS) {
+            cx = s_cxy[sl][0];
+            cy = s_cxy[sl][1];
+          } else {
+            const DropDev d = drops[I.drop_base + best];
+            cx = d.x;
+            cy = d.y;
+          }
           kd = best;
           cv0 = v;
-          cv1 = v * minimg(xd - d.x, (double)nx);
-          cv2 = v * minimg(yd - d.y, I.yper);
+          cv1 = v * minimg(xd - cx, (double)nx);
+          cv2 = v * minimg(yd - cy, I.yper);
         }
       }
       // centre-of-mass contributions: candidate number r of the segment (in droplet order) has slot r; a lane
