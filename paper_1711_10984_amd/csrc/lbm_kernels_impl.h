@@ -879,7 +879,8 @@ constexpr int RING = 8;
 struct FusedShared {
   unsigned long long near_mask[MASK_WORDS], src_mask[MASK_WORDS], seg_mask[MASK_WORDS], it_mask[MASK_WORDS];
   double red[NTHREADS / 64][3];
-  double acc[MAXDROP][3];
+  // centre-of-mass sums of the segment's first nearest-centre candidate, per thread across iterations
+  double slot[3][NTHREADS];
 };
 
 // 9-point stencils on three LDS rows: up = row r+1 (N), mid = row r, dn = row r-1 (S); lane l.
@@ -1004,6 +1005,21 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
     }
     __syncthreads();
   }
+  // the first candidate (lowest droplet index) owns the per-thread slot; ncand candidates in all
+  int cand0 = -1, ncand = 0;
+  if (nd > 0) {
+    for (int w = MASK_WORDS - 1; w >= 0; --w) {
+      const unsigned long long m = sh.near_mask[w];
+      if (m) cand0 = w * 64 + __ffsll(m) - 1;
+      ncand += __popcll(m);
+    }
+    cand0 = __builtin_amdgcn_readfirstlane(cand0);
+    ncand = __builtin_amdgcn_readfirstlane(ncand);
+  }
+  sh.slot[0][tid] = sh.slot[1][tid] = sh.slot[2][tid] = 0.0;
+  bool met0 = false;
+  const int t_local = sd.t - I.tile_base[TILING_FUSED];
+  double* const part_t = part + I.part_base[TILING_FUSED] + (int64_t)t_local * nd * 3;
   const double tn = (double)(*step);
   const double A = I.A0 * (tn < I.t_star ? tn : I.t_star);
 
@@ -1217,19 +1233,24 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
         }
         const double v = (double)phn;
         if (!DBG && nd > 0 && v >= 0.0) {
+          // nearest centre among the candidates (a single candidate is the nearest)
           int best = -1;
-          double bd = 0.0;
-          for (int w = 0; w < MASK_WORDS; ++w) {
-            unsigned long long m = sh.near_mask[w];
-            while (m) {
-              const int k = w * 64 + __ffsll(m) - 1;
-              m &= m - 1;
-              const DropDev d = drops[I.drop_base + k];
-              const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, I.yper);
-              const double d2 = dx * dx + dy * dy;
-              if (best < 0 || d2 < bd) {
-                best = k;
-                bd = d2;
+          if (ncand == 1) {
+            best = cand0;
+          } else {
+            double bd = 0.0;
+            for (int w = 0; w < MASK_WORDS; ++w) {
+              unsigned long long m = sh.near_mask[w];
+              while (m) {
+                const int k = w * 64 + __ffsll(m) - 1;
+                m &= m - 1;
+                const DropDev d = drops[I.drop_base + k];
+                const double dx = minimg(xd - d.x, (double)nx), dy = minimg(yd - d.y, I.yper);
+                const double d2 = dx * dx + dy * dy;
+                if (best < 0 || d2 < bd) {
+                  best = k;
+                  bd = d2;
+                }
               }
             }
           }
@@ -1238,12 +1259,19 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
           cv0 = v;
           cv1 = v * minimg(xd - d.x, (double)nx);
           cv2 = v * minimg(yd - d.y, I.yper);
+          if (kd == cand0) {  // the slot: this thread's running sums, in row order
+            sh.slot[0][tid] += cv0;
+            sh.slot[1][tid] += cv1;
+            sh.slot[2][tid] += cv2;
+            met0 = true;
+            kd = -1;
+          }
         }
       }
     }
-    // deterministic per-sweep reduction of the centre-of-mass contributions (only when some node of
-    // this sweep iteration has phi^{n+1} >= 0)
-    if (!DBG && nd > 0 && __syncthreads_or(kd >= 0)) {
+    // other candidates (rare): deterministic per-sweep workgroup sums of their contributions, added to the
+    // strip's partials in global memory (with a single candidate there are none, and no barrier is needed)
+    if (!DBG && ncand > 1 && __syncthreads_or(kd >= 0)) {
       if (tid < MASK_WORDS) sh.it_mask[tid] = 0ull;
       __syncthreads();
       if (kd >= 0) atomicOr(&sh.it_mask[kd >> 6], 1ull << (kd & 63));
@@ -1257,15 +1285,16 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
           block_reduce3(s0, s1, s2, sh.red);
           if (tid == 0) {
             const unsigned long long bit = 1ull << (k & 63);
+            double* const p = part_t + (int64_t)k * 3;
             if (sh.seg_mask[k >> 6] & bit) {
-              sh.acc[k][0] += s0;
-              sh.acc[k][1] += s1;
-              sh.acc[k][2] += s2;
+              p[0] += s0;
+              p[1] += s1;
+              p[2] += s2;
             } else {
               sh.seg_mask[k >> 6] |= bit;
-              sh.acc[k][0] = s0;
-              sh.acc[k][1] = s1;
-              sh.acc[k][2] = s2;
+              p[0] = s0;
+              p[1] = s1;
+              p[2] = s2;
             }
           }
         }
@@ -1273,15 +1302,19 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
     }
   }
   if (DBG || nd == 0) return;
-  // partials of the droplets present in this strip, and the presence mask
-  __syncthreads();
-  const int t_local = sd.t - I.tile_base[TILING_FUSED];
-  if (tid < nd && ((sh.seg_mask[tid >> 6] >> (tid & 63)) & 1ull)) {
-    double* p = part + I.part_base[TILING_FUSED] + ((int64_t)t_local * nd + tid) * 3;
-    p[0] = sh.acc[tid][0];
-    p[1] = sh.acc[tid][1];
-    p[2] = sh.acc[tid][2];
+  // the slot's workgroup sum (fixed order), and the presence mask
+  if (__syncthreads_or(met0)) {
+    double s0 = sh.slot[0][tid], s1 = sh.slot[1][tid], s2 = sh.slot[2][tid];
+    block_reduce3(s0, s1, s2, sh.red);
+    if (tid == 0) {
+      double* const p = part_t + (int64_t)cand0 * 3;
+      p[0] = s0;
+      p[1] = s1;
+      p[2] = s2;
+      sh.seg_mask[cand0 >> 6] |= 1ull << (cand0 & 63);
+    }
   }
+  __syncthreads();
   if (tid < MASK_WORDS) mask[(int64_t)sd.t * MASK_WORDS + tid] = sh.seg_mask[tid];
 }
 
