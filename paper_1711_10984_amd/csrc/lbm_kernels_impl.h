@@ -1461,7 +1461,7 @@ __device__ __forceinline__ T div9n(const Nbr<T>& c, const Nbr<T>& X, T D) {
 
 template <typename T, typename P, bool DBG>
 // Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD; FP32
-// fits four (127 registers) and FP16 storage three.
+// fits four (128 registers, a few bytes spilled) and FP16 storage three.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : sizeof(P) == 4 ? 4 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
                                              const InstDev* __restrict__ insts, T* __restrict__ buf,
                                              const DropDev* __restrict__ drops, double* __restrict__ part,
