@@ -323,7 +323,7 @@ def main():
                     help="also run one plain 512 MiB device copy (reference for rocprofv3 counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the timestep is a single-GPU kernel; the "
+        print("bench.py runs on one GPU only (the timestep is a single-GPU kernel; the "
               "multi-GPU decomposition is a design note, not code) -- use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -1,4 +1,4 @@
-"""The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (CPU): tests/oracle_sanitize_driver.c runs
+"""The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (CPU): tests/oracle_sanitize_main.c runs
 the oracle's C interface on edge-case lattices (3 x 3, 3 x 4 and 37 x 4 with walls, a droplet across both
 periodic edges, both advection forms, no droplets) in a build with -fsanitize=address,undefined; any
 out-of-bounds access, leak or undefined behaviour aborts it with a report."""
@@ -18,7 +18,7 @@ def test_oracle_is_clean_under_address_and_undefined_behaviour_sanitizers(tmp_pa
     exe = tmp_path / "oracle_sanitize"
     cmd = [gcc, "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fopenmp",
-           "-I", os.path.join(ROOT, "oracle"), os.path.join(ROOT, "tests", "oracle_sanitize_driver.c"),
+           "-I", os.path.join(ROOT, "oracle"), os.path.join(ROOT, "tests", "oracle_sanitize_main.c"),
            "-o", str(exe), "-lm"]
     b = subprocess.run(cmd, capture_output=True, text=True)
     if b.returncode != 0 and "sanitize" in b.stderr and "not supported" in b.stderr:
