@@ -884,30 +884,19 @@ struct FusedShared {
 };
 
 // 9-point stencils on three LDS rows: up = row r+1 (N), mid = row r, dn = row r-1 (S); lane l.
-// U (unscaled): 12 x the gradient and 6 x the Laplacian, the diagonal differences of the gradient shared
-// (NE - NW) + (SE - SW) = (NE - SW) - (NW - SE) and (NE - SE) + (NW - SW) = (NE - SW) + (NW - SE); the FP32
-// kernels fold the scales into their coefficients.
-template <bool U = false, typename T>
+template <typename T>
 __device__ __forceinline__ void grad9r(const T* up, const T* mid, const T* dn, int l, T& gx, T& gy) {
   const T E = mid[l + 1], Wv = mid[l - 1], N = up[l], S = dn[l];
   const T NE = up[l + 1], NW = up[l - 1], SW = dn[l - 1], SE = dn[l + 1];
-  if constexpr (U) {
-    const T d1 = NE - SW, d2 = NW - SE;
-    gx = T(4) * (E - Wv) + (d1 - d2);
-    gy = T(4) * (N - S) + (d1 + d2);
-  } else {
-    gx = (T(4) * (E - Wv) + ((NE - NW) + (SE - SW))) * cst<T>(1.0 / 12.0);
-    gy = (T(4) * (N - S) + ((NE - SE) + (NW - SW))) * cst<T>(1.0 / 12.0);
-  }
+  gx = (T(4) * (E - Wv) + ((NE - NW) + (SE - SW))) * cst<T>(1.0 / 12.0);
+  gy = (T(4) * (N - S) + ((NE - SE) + (NW - SW))) * cst<T>(1.0 / 12.0);
 }
 
-template <bool U = false, typename T>
+template <typename T>
 __device__ __forceinline__ T lap9r(const T* up, const T* mid, const T* dn, int l) {
   const T E = mid[l + 1], Wv = mid[l - 1], N = up[l], S = dn[l];
   const T NE = up[l + 1], NW = up[l - 1], SW = dn[l - 1], SE = dn[l + 1];
-  const T s = T(4) * ((E + Wv) + (N + S)) + ((NE + NW) + (SE + SW)) - T(20) * mid[l];
-  if constexpr (U) return s;
-  return s * cst<T>(1.0 / 6.0);
+  return (T(4) * ((E + Wv) + (N + S)) + ((NE + NW) + (SE + SW)) - T(20) * mid[l]) * cst<T>(1.0 / 6.0);
 }
 
 template <typename T>
@@ -1040,13 +1029,6 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
   const T cw0 = coef * w0, cw1 = coef * w1, cw5 = coef * w5;
   const LbConst<T> lbk{w0, w1, w5, cw0, cw1, cw5, omega, wr0, wr1, wr5, T(I.n0)};
   const T Gamma = T(I.Gamma), D = T(I.D), gam = T(I.gamma), c0 = T(I.c0);
-  // FP32 arithmetic: the stencils are unscaled (U) and their 1/12 and 1/6 sit in these coefficients.  FP64
-  // keeps the oracle's arithmetic: its factors are exactly 1, so every product below equals the plain
-  // coefficient.  (k_wave keeps the scaled stencils: in FP32 the extra coefficients make it spill.)
-  constexpr bool U = sizeof(T) == 4;
-  const T kg = U ? cst<T>(1.0 / 12.0) : T(1), kl = U ? cst<T>(1.0 / 6.0) : T(1);
-  const T B0l = B0 * kl, B1l = B1 * kl, B1gg = B1 * (kg * kg), hB1gg = halfB1 * (kg * kg);
-  const T Gl = Gamma * kl, Dl = D * kl;
   const int adv = I.advection;
 
   // stage row validity windows: stage s computes rows [y0 - (5 - s), yend + (5 - s))
@@ -1108,13 +1090,13 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
       if (l1 && r >= y0 - 4 && r < yend + 4) {
         const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
         T gpx, gpy, gcx, gcy;
-        grad9r<U>(r_phi[su], r_phi[sm], r_phi[sdn], lane, gpx, gpy);
-        grad9r<U>(r_c[su], r_c[sm], r_c[sdn], lane, gcx, gcy);
-        const T lp = lap9r<U>(r_phi[su], r_phi[sm], r_phi[sdn], lane);
+        grad9r(r_phi[su], r_phi[sm], r_phi[sdn], lane, gpx, gpy);
+        grad9r(r_c[su], r_c[sm], r_c[sdn], lane, gcx, gcy);
+        const T lp = lap9r(r_phi[su], r_phi[sm], r_phi[sdn], lane);
         const T ph = r_phi[sm][lane];
-        const T B = B0l + B1l * r_c[sm][lane];
-        const T mu = ((a * ph + b * (ph * ph * ph)) - B * lp) - B1gg * (gpx * gcx + gpy * gcy);
-        const T X = hB1gg * (gpx * gpx + gpy * gpy);
+        const T B = B0 + B1 * r_c[sm][lane];
+        const T mu = ((a * ph + b * (ph * ph * ph)) - B * lp) - B1 * (gpx * gcx + gpy * gcy);
+        const T X = halfB1 * (gpx * gpx + gpy * gpy);
         r_mu[sm][lane] = mu;
         r_X[sm][lane] = X;
         if (DBG && own_col && r >= y0 && r < yend) {
@@ -1131,12 +1113,12 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
       if (l2 && r >= y0 - 3 && r < yend + 3) {
         const int su = (r + 1) & (RING - 1), sm = r & (RING - 1), sdn = (r - 1) & (RING - 1);
         T gmx, gmy, gXx, gXy, gcx, gcy;
-        grad9r<U>(r_mu[su], r_mu[sm], r_mu[sdn], lane, gmx, gmy);
-        grad9r<U>(r_X[su], r_X[sm], r_X[sdn], lane, gXx, gXy);
-        grad9r<U>(r_c[su], r_c[sm], r_c[sdn], lane, gcx, gcy);
+        grad9r(r_mu[su], r_mu[sm], r_mu[sdn], lane, gmx, gmy);
+        grad9r(r_X[su], r_X[sm], r_X[sdn], lane, gXx, gXy);
+        grad9r(r_c[su], r_c[sm], r_c[sdn], lane, gcx, gcy);
         const T ph = r_phi[sm][lane], cv = r_c[sm][lane];
-        const T Fx = ((-(ph * gmx) - gcx) - cv * gXx) * kg;
-        const T Fy = ((-(ph * gmy) - gcy) - cv * gXy) * kg;
+        const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
+        const T Fy = (-(ph * gmy) - gcy) - cv * gXy;
         T d[9], dn, nn, ux, uy;
         lb_moments<T, P>(pf, lbk, Fx, Fy, d, dn, nn, ux, uy);
         r_ux[sm][lane] = ux;
@@ -1193,13 +1175,13 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
         const int su = (walls && r == ny - 1) ? sm : (r + 1) & (RING - 1);
         const int sdn = (walls && r == 0) ? sm : (r - 1) & (RING - 1);
         T gphx, gphy, gchx, gchy;
-        grad9r<U>(r_ph[su], r_ph[sm], r_ph[sdn], lane, gphx, gphy);
-        grad9r<U>(r_ch[su], r_ch[sm], r_ch[sdn], lane, gchx, gchy);
-        const T lph = lap9r<U>(r_ph[su], r_ph[sm], r_ph[sdn], lane);
+        grad9r(r_ph[su], r_ph[sm], r_ph[sdn], lane, gphx, gphy);
+        grad9r(r_ch[su], r_ch[sm], r_ch[sdn], lane, gchx, gchy);
+        const T lph = lap9r(r_ph[su], r_ph[sm], r_ph[sdn], lane);
         const T pn = r_phi[sm][lane];
-        const T Bh = B0l + B1l * r_ch[sm][lane];
-        const T M = ((a * r_ph[sm][lane] + b * (pn * pn * pn)) - Bh * lph) - B1gg * (gchx * gphx + gchy * gphy);
-        const T Xh = hB1gg * (gphx * gphx + gphy * gphy);
+        const T Bh = B0 + B1 * r_ch[sm][lane];
+        const T M = ((a * r_ph[sm][lane] + b * (pn * pn * pn)) - Bh * lph) - B1 * (gchx * gphx + gchy * gphy);
+        const T Xh = halfB1 * (gphx * gphx + gphy * gphy);
         r_M[sm][lane] = M;
         r_Xh[sm][lane] = Xh;
         if (DBG && own_col && r >= y0 && r < yend) {
@@ -1219,9 +1201,9 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
         const int sm = r & (RING - 1);
         const int su = (walls && r == ny - 1) ? sm : (r + 1) & (RING - 1);
         const int sdn = (walls && r == 0) ? sm : (r - 1) & (RING - 1);
-        const T phn = r_ph[sm][lane] + Gl * lap9r<U>(r_M[su], r_M[sm], r_M[sdn], lane);
+        const T phn = r_ph[sm][lane] + Gamma * lap9r(r_M[su], r_M[sm], r_M[sdn], lane);
         const T ch = r_ch[sm][lane];
-        const T lch = lap9r<U>(r_ch[su], r_ch[sm], r_ch[sdn], lane);
+        const T lch = lap9r(r_ch[su], r_ch[sm], r_ch[sdn], lane);
         const T dv = div9r(r_ch[su], r_ch[sm], r_ch[sdn], D, r_Xh[su], r_Xh[sm], r_Xh[sdn], lane);
         const double xd = (double)(x0 + col), yd = (double)r;
         int cnt = 0;
@@ -1239,7 +1221,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
           }
         }
         const double src = A * (double)cnt;
-        const T cn = (((ch + Dl * lch) + dv) - gam * (ch - c0)) + T(src);
+        const T cn = (((ch + D * lch) + dv) - gam * (ch - c0)) + T(src);
         const int64_t o = (int64_t)r * pitch + gx;
         if (!DBG) {
           phi_out[o] = phn;
@@ -1451,24 +1433,15 @@ __device__ __forceinline__ Nbr<double> nbr(double up, double mid, double dn) {
   return g;
 }
 
-// U: unscaled, as grad9r / lap9r
-template <bool U = false, typename T>
+template <typename T>
 __device__ __forceinline__ void grad9n(const Nbr<T>& g, T& gx, T& gy) {
-  if constexpr (U) {
-    const T d1 = g.ne - g.sw, d2 = g.nw - g.se;
-    gx = T(4) * (g.e - g.w) + (d1 - d2);
-    gy = T(4) * (g.n - g.s) + (d1 + d2);
-  } else {
-    gx = (T(4) * (g.e - g.w) + ((g.ne - g.nw) + (g.se - g.sw))) * cst<T>(1.0 / 12.0);
-    gy = (T(4) * (g.n - g.s) + ((g.ne - g.se) + (g.nw - g.sw))) * cst<T>(1.0 / 12.0);
-  }
+  gx = (T(4) * (g.e - g.w) + ((g.ne - g.nw) + (g.se - g.sw))) * cst<T>(1.0 / 12.0);
+  gy = (T(4) * (g.n - g.s) + ((g.ne - g.se) + (g.nw - g.sw))) * cst<T>(1.0 / 12.0);
 }
 
-template <bool U = false, typename T>
+template <typename T>
 __device__ __forceinline__ T lap9n(const Nbr<T>& g) {
-  const T s = T(4) * ((g.e + g.w) + (g.n + g.s)) + ((g.ne + g.nw) + (g.se + g.sw)) - T(20) * g.c;
-  if constexpr (U) return s;
-  return s * cst<T>(1.0 / 6.0);
+  return (T(4) * ((g.e + g.w) + (g.n + g.s)) + ((g.ne + g.nw) + (g.se + g.sw)) - T(20) * g.c) * cst<T>(1.0 / 6.0);
 }
 
 template <typename T>
