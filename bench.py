@@ -301,7 +301,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--graph-steps", type=int, default=20)
+    ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--prof-steps", type=int, default=50, help="steps timed per kernel with hipEvents")
     ap.add_argument("--no-variants", action="store_true", help="FP64 2048^2 only")
     ap.add_argument("--path", type=int, default=-1, choices=[-1] + sorted(PATH_NAMES),
