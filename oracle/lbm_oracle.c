@@ -50,6 +50,13 @@
  *    n.grad mu_c = 0).  In the advection stencil the ghost velocity is the
  *    mirror image with u_y reversed (no flow through the plate).  Droplet
  *    distances and centres are not periodic in y.
+ *
+ * Parity unpinned (no printed value, closed form or special case separates
+ * the alternatives; the tests say so where they use these parts):
+ *  - the time level of c in B(c) of the bracket of Eq. (18) (n + 1/2 as
+ *    printed, against n: they differ at second order, not at equilibrium);
+ *  - the source geometry (Rs, r_P) and the droplet-velocity definition, which
+ *    follow the paper's words but have no printed values.
  */
 #ifdef _OPENMP
 #include <omp.h>
