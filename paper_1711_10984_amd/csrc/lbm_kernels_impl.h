@@ -683,8 +683,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fd(int parity, const TileDev* __re
       dbg[12 * nplane + q] = (double)cn;
     }
   }
-  if (MODE == 0 && I.ndrop > 0)
-    tile_cm_sums(I, td.t - I.tile_base[TILING_SPLIT], td.t, kd, vv, vx, vy, sh, part, mask);
+  // the stage-export mode writes the partials too: with its state writes (to the inactive half) it is a
+  // whole step, which the reverse mode's recompute uses
+  if (I.ndrop > 0) tile_cm_sums(I, td.t - I.tile_base[TILING_SPLIT], td.t, kd, vv, vx, vy, sh, part, mask);
 }
 
 // Centre-of-mass partials of the current phi (the first pass at initialisation).
