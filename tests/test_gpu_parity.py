@@ -421,6 +421,31 @@ def test_autotune_over_all_paths_keeps_state():
     s.close()
 
 
+@pytest.mark.parametrize("path", PATHS)
+def test_stage_export_keeps_state(path):
+    """lbm_debug_stage writes only scratch (the inactive halves, the partial sums, the stage planes): the
+    fields, droplets and step counter are unchanged and the run continues bit for bit."""
+    w = W.c5_emulsion(n=200, ndrop=3, R=12.0, seed=34)
+    ref = gpu_sim(w, graph_steps=0, path=path)
+    ref.step(9)
+    want, want_drops = ref.fields(), ref.droplets()
+    ref.close()
+    s = gpu_sim(w, graph_steps=0, path=path)
+    s.step(4)
+    before, drops_before, step_before = s.fields(), s.droplets(), s.step_count
+    s.stages()
+    after = s.fields()
+    for k in FIELDS:
+        assert np.array_equal(before[k], after[k]), k
+    assert s.droplets() == drops_before and s.step_count == step_before
+    s.step(5)
+    f = s.fields()
+    for k in FIELDS:
+        assert np.array_equal(f[k], want[k]), k
+    assert s.droplets() == want_drops
+    s.close()
+
+
 def test_fp32_batched_instances_match_single_runs():
     """Batching does not change any instance's arithmetic (FP32, uneven sizes)."""
     lbm = _lbm()
