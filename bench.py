@@ -425,11 +425,13 @@ def main():
             "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
                                                 args.path, lbm.LBM_FP32),
             "batched_c3": lowp_accuracy(W.c3_batch(), 100000, 500, args.graph_steps, args.path, lbm.LBM_FP32),
+            "emulsion_2048_64_droplets": lowp_accuracy([c5], 100000, 1000, args.graph_steps, args.path,
+                                                       lbm.LBM_FP32),
         }
         out["fp16_accuracy"] = {
             "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
                                                 args.path, lbm.LBM_FP16),
-            "emulsion_2048_64_droplets": lowp_accuracy([c5], 5000, 500, args.graph_steps, args.path,
+            "emulsion_2048_64_droplets": lowp_accuracy([c5], 100000, 1000, args.graph_steps, args.path,
                                                        lbm.LBM_FP16),
         }
     if not args.no_variants:
