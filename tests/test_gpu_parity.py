@@ -114,10 +114,13 @@ def test_c2_active_droplet_256_first_1000_steps(path):
 
 @pytest.mark.parametrize("path", [0, 2])
 def test_c5_emulsion_2048_bench_configuration(path):
-    """Full-size 2048^2 emulsion with 64 droplets, graph replay as the benchmark runs it: every field
-    after a few steps against the oracle on the whole lattice."""
+    """Full-size 2048^2 emulsion with 64 droplets, in the benchmark's launch configuration (the autotuner's
+    strip height for the path, graph replay): every field after a few steps against the oracle on the whole
+    lattice."""
     w = _c5()
     sim = gpu_sim(w, graph_steps=2, path=path)
+    rows, chosen, _ = sim.autotune(3, both_paths=False)
+    assert chosen == path and rows in sim.tune_rows()
     ref = oracle_sim(w)
     sim.step(4)
     ref.run(4)
