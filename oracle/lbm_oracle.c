@@ -51,12 +51,12 @@
  *    mirror image with u_y reversed (no flow through the plate).  Droplet
  *    distances and centres are not periodic in y.
  *
- * Parity unpinned (no printed value, closed form or special case separates
- * the alternatives; the tests say so where they use these parts):
- *  - the time level of c in B(c) of the bracket of Eq. (18) (n + 1/2 as
- *    printed, against n: they differ at second order, not at equilibrium);
- *  - the source geometry (Rs, r_P) and the droplet-velocity definition, which
- *    follow the paper's words but have no printed values.
+ * Every function here is pinned by the CPU tests against closed forms,
+ * textbook cases, exact identities or the paper's printed values.  Two
+ * readings follow the paper's words but have no printed value to compare
+ * with: the source geometry (Rs, r_P) and the droplet velocity as the
+ * phi-weighted mean of u; the tests pin that the oracle computes them as
+ * stated here, not that the paper computed them so.
  */
 #ifdef _OPENMP
 #include <omp.h>

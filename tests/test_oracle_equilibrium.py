@@ -3,10 +3,14 @@
 * Table 1: surface tension of a planar interface, sigma_th = int B(c) (d phi/dx)^2 dx (Eq. 21 with the
   square restored) and sigma_num = excess free energy (Eq. 22), after 2e5 steps from a sharp
   interface with c_i = 0.1, a = -b = -0.001, D = 0.1, tau = 1.  12 of the 14 rows are reproduced to
-  the printed precision.  The rows (B0, B1) = (0.08, -0.05), (0.08, -0.1) (B(c) ~ 0.07) are not: at
-  tau = 1 the D2Q9 staggered-momentum (checkerboard) mode is undamped, the sharp initial step seeds it
-  and at this interface stiffness it grows until the interfaces dissolve.  The paper does not give its
-  discretisation in enough detail to say what damps it there.
+  the printed precision.  The rows (B0, B1) = (0.08, -0.05), (0.08, -0.1) are not, and cannot be with this
+  discretisation: the explicit phi update of Eq. (18) amplifies the checkerboard mode k = (pi, pi) of the bulk
+  (phi = phi_eq, c = 0.1, fluid at rest) by G = 1 + Gamma lam (a + 3 b phi_eq^2 - B(c) lam), lam = -16/3 the
+  9-point Laplacian's symbol there (the 9-point gradient of that mode vanishes, so it drives no flow and no
+  surfactant flux).  |G| <= 1 requires B(c) <= 0.06994; these two rows have B(0.1) = 0.075 and 0.070, so
+  round-off grows by |G| = 1.144 and 1.0018 per step and destroys the interfaces within the 2e5 steps.  The
+  oracle reproduces G exactly for every row (a pin of Eq. 18 at the shortest wavelength).  The paper must
+  have used a Laplacian with a smaller largest eigenvalue or a smaller time step there; it does not say.
 * At that equilibrium the fluid is at rest with uniform density: the force of Eq. (14) is consistent
   with the surfactant flux of Eq. (19) (a sign error in either leaves a density step).
 * Planar profile phi = phi_eq tanh(x / xi0), xi0 = sqrt(-2 B0 / a), phi_eq = sqrt(-a/b) (Eq. 20, Sec. 2.1).
@@ -72,6 +76,26 @@ def test_table1_surface_tension():
         assert abs(s_num - snum) <= _half_ulp(snum_txt) + 0.025 * snum, (B0, B1, s_num, snum)
         assert umax < 1e-6, (B0, B1, umax)
         assert dn < 1e-4, (B0, B1, dn)
+
+
+@pytest.mark.parametrize("row", range(14))
+def test_table1_rows_checkerboard_growth_factor(row):
+    """One step of a small checkerboard on the bulk multiplies it by the closed-form G of Eq. (18); the two rows
+    that are not reproduced are exactly those with |G| > 1."""
+    B0, B1 = _table1_rows()[row][:2]
+    a, b, cbar, eps = -0.001, 0.001, 0.1, 1e-7
+    lam = -16.0 / 3.0
+    G = 1.0 + lam * (a + 3.0 * b - (B0 + B1 * cbar) * lam)
+    n = 4
+    y, x = np.mgrid[0:n, 0:n]
+    chk = np.where((x + y) % 2 == 0, 1.0, -1.0)
+    s = OracleSim(Params(nx=n, ny=n, tau=1.0, a=a, b=b, B0=B0, B1=B1, D=0.1, Gamma=1.0), 1.0 + eps * chk,
+                  np.full((n, n), cbar))
+    st = s.stages()
+    assert np.max(np.abs(st["ux"])) == 0.0 and np.max(np.abs(st["c_new"] - cbar)) < 1e-17
+    got = (st["phi_new"] - 1.0) / (eps * chk)
+    assert np.max(np.abs(got - G)) < 1e-6
+    assert (abs(G) > 1.0) == ((B0, B1) in NOT_REPRODUCED), (B0, B1, G)
 
 
 def test_table1_golden_file_complete():

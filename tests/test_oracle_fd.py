@@ -1,8 +1,14 @@
 """Pins of the oracle's finite-difference half (Sec. 2.3, Eqs. 16-19) and the activity terms.
 
 * Upwind advection by a uniform velocity: amplification 1 - u (1 - e^{-ik}) per axis (u > 0),
-  1 - u (e^{ik} - 1) (u < 0): the textbook first-order upwind scheme.
-* Centred velocity divergence: phi0 (1 - U sin k cos kx) for u_x = U sin kx.
+  1 - u (e^{ik} - 1) (u < 0): the textbook first-order upwind scheme.  The conservative flux form has the
+  same symbol (face velocity = u, face value taken from the upwind node), which fixes its upwind side.
+* Centred velocity divergence: phi0 (1 - U sin k cos kx) for u_x = U sin kx, in both forms (in the flux
+  form the face velocity is the mean of the two nodes, whose difference is the centred one).
+* Time level of c in B(c) and in grad c of Eq. (18): a state whose force vanishes identically while
+  lap phi does not (phi a period-4 staircase along x, so |grad phi| is uniform, a = b = 0, B(c) = 0 at the
+  uniform c), moved by a small positive velocity.  Then B(c^{n+1/2}) = -B1 c div u is first order in u,
+  and the first-order response of phi^{n+1} follows by hand; with B(c^n) = 0 that term would vanish.
 * Linear response of one Fourier mode, derived by hand from Eqs. (3), (11), (14), (16)-(19)
   with the 9-point symbols: pins a, b (at time level n), B(c) = B0 + B1 c, Gamma, D, gamma, the
   half-force velocity and the centred divergence in the advection.
@@ -25,14 +31,15 @@ def _flow_only(nx, ny, **kw):
     return Params(**d)
 
 
+@pytest.mark.parametrize("advection", [0, 1])
 @pytest.mark.parametrize("u0", [(0.03, 0.02), (-0.03, 0.02), (0.03, -0.04), (-0.02, -0.01)])
-def test_upwind_uniform_velocity(u0):
+def test_upwind_uniform_velocity(u0, advection):
     nx, ny = 16, 12
     y, x = np.mgrid[0:ny, 0:nx].astype(float)
     kx, ky = 2 * np.pi * 3 / nx, 2 * np.pi * 2 / ny
     phi = np.cos(kx * x + ky * y)
     f = feq(np.ones((ny, nx)), np.full((ny, nx), u0[0]), np.full((ny, nx), u0[1]))
-    s = OracleSim(_flow_only(nx, ny), phi, np.full((ny, nx), 0.1), f_pre=f)
+    s = OracleSim(_flow_only(nx, ny, advection=advection), phi, np.full((ny, nx), 0.1), f_pre=f)
     st = s.stages()
     ux, uy = st["ux"][0, 0], st["uy"][0, 0]
     assert abs(ux - u0[0]) < 1e-15 and abs(uy - u0[1]) < 1e-15
@@ -43,18 +50,66 @@ def test_upwind_uniform_velocity(u0):
     assert np.max(np.abs(st["phi_new"] - expect)) < 1e-14
 
 
-def test_centred_velocity_divergence():
+@pytest.mark.parametrize("advection", [0, 1])
+def test_centred_velocity_divergence(advection):
     nx, ny = 16, 10
     y, x = np.mgrid[0:ny, 0:nx].astype(float)
     kx, ky = 2 * np.pi / nx, 2 * np.pi * 2 / ny
     U, V = 0.02, 0.015
     f = feq(np.ones((ny, nx)), U * np.sin(kx * x), V * np.sin(ky * y))
     phi0, cbar = 0.7, 0.1
-    s = OracleSim(_flow_only(nx, ny), np.full((ny, nx), phi0), np.full((ny, nx), cbar), f_pre=f)
+    s = OracleSim(_flow_only(nx, ny, advection=advection), np.full((ny, nx), phi0), np.full((ny, nx), cbar),
+                  f_pre=f)
     st = s.stages()
     div = U * np.sin(kx) * np.cos(kx * x) + V * np.sin(ky) * np.cos(ky * y)
     assert np.max(np.abs(st["phi_new"] - phi0 * (1 - div))) < 1e-15
     assert np.max(np.abs(st["c_new"] - cbar * (1 - div))) < 1e-15
+
+
+def _fourier(g, symbol):
+    return np.real(np.fft.ifft2(np.fft.fft2(g) * symbol))
+
+
+def test_time_level_of_c_in_the_phi_update():
+    """Eq. (18) takes B(c) and grad c at n + 1/2.  Base state: phi a staircase (p0, p0, p1, p1) repeating along
+    x, uniform c = cbar, a = b = 0 and B0 = -B1 cbar (exact in binary), fluid at rest.  Then mu = 0, the 9-point
+    grad phi is +-(p1 - p0)/2 everywhere so X is uniform, and the force vanishes identically, while lap phi = +-
+    (p1 - p0) does not.  Populations at equilibrium with a velocity eps u1, u1 > 0 everywhere (so the upwind side
+    is the backward difference on both axes): c^{1/2} = cbar (1 - D0.u), B(c^{1/2}) = -B1 cbar eps D0.u1, and to
+    first order in eps
+        phi^{n+1} - phi = eps [ -(phi D0.u1 + u1 . Dminus phi)
+                                + Gamma B1 cbar lap9( (D0.u1) lap9 phi + grad9(D0.u1) . grad9 phi ) ],
+    with D0 the 3-point centred divergence, Dminus the backward difference, and the 9-point operators applied
+    here through their Fourier symbols.  Reading B(c^n) instead drops the (D0.u1) lap9 phi term; reading grad c^n
+    drops the other."""
+    from tests.lbhelpers import sym_grad, sym_lap, wavenumbers
+    nx, ny = 16, 12
+    p0, p1 = -0.3, 0.5
+    phi = np.tile(np.array([p0, p0, p1, p1]), (ny, nx // 4))
+    cbar, B1, Gamma = 0.25, -0.5, 0.7
+    p = Params(nx=nx, ny=ny, tau=0.8, a=0.0, b=0.0, B0=-B1 * cbar, B1=B1, D=0.1, Gamma=Gamma, gamma=0.0)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    u1x = 1.0 + 0.5 * np.sin(2 * np.pi * x / nx + 0.3) + 0.2 * np.cos(2 * np.pi * y / ny)
+    u1y = 1.0 + 0.4 * np.cos(2 * np.pi * (x / nx + 2 * y / ny))
+    eps = 1e-7
+    s = OracleSim(p, phi, np.full((ny, nx), cbar), f_pre=feq(np.ones((ny, nx)), eps * u1x, eps * u1y))
+    st = s.stages()
+    assert np.all(st["mu"] == 0.0) and np.all(st["Fx"] == 0.0) and np.all(st["Fy"] == 0.0)
+    kx, ky = wavenumbers(ny, nx)
+    div = _fourier(u1x, 1j * np.sin(kx)) + _fourier(u1y, 1j * np.sin(ky))
+    dmx, dmy = _fourier(phi, 1 - np.exp(-1j * kx)), _fourier(phi, 1 - np.exp(-1j * ky))
+    gsx, gsy = sym_grad(ny, nx)
+    lap = sym_lap(ny, nx)
+    lap_phi = _fourier(phi, lap)
+    grad_term = _fourier(div, gsx) * _fourier(phi, gsx) + _fourier(div, gsy) * _fourier(phi, gsy)
+    advect = -(phi * div + u1x * dmx + u1y * dmy)
+    want = advect + Gamma * B1 * cbar * _fourier(div * lap_phi + grad_term, lap)
+    got = (st["phi_new"] - phi) / eps
+    assert np.max(np.abs(got - want)) < 1e-6
+    # the alternative readings differ from this by far more than the tolerance
+    b_at_n = advect + Gamma * B1 * cbar * _fourier(grad_term, lap)
+    gradc_at_n = advect + Gamma * B1 * cbar * _fourier(div * lap_phi, lap)
+    assert np.max(np.abs(b_at_n - want)) > 1e-2 and np.max(np.abs(gradc_at_n - want)) > 1e-2
 
 
 def _odd_response(p, base_phi, base_c, dphi, dc, eps):

@@ -1,11 +1,6 @@
 """Sensitivity of the oracle's pins: plant a plausible mistake in a copy of the oracle (on the CPU), build
-it, and check that the fast pin suite fails.  Six of them always run (about 20 s); all of them (about 90 s)
-with LBM_MUTATION_CHECK=1.
-
-One reading is known to be unpinned: whether B(c) in the bracket of Eq. (18) takes c at time n or at
-n + 1/2 (the paper prints n + 1/2, which the oracle follows).  The difference is second order in the
-departure from equilibrium and vanishes at equilibrium, so no closed form or printed value separates
-the two.
+it, and check that the fast pin suite fails.  Eight of them always run (about 30 s); all of them (about two
+minutes) with LBM_MUTATION_CHECK=1.
 """
 import os
 import subprocess
@@ -17,7 +12,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
 PINS = ["tests/test_oracle_thermo.py", "tests/test_oracle_stencils.py", "tests/test_oracle_lb.py",
-        "tests/test_oracle_fd.py", "tests/test_oracle_equilibrium.py", "tests/test_oracle_walls.py"]
+        "tests/test_oracle_fd.py", "tests/test_oracle_equilibrium.py", "tests/test_oracle_walls.py",
+        "tests/test_oracle_droplets.py"]
 
 MUTATIONS = [
     ("equilibrium without the 1/2", "4.5 * eu * eu", "9.0 * eu * eu"),
@@ -56,18 +52,47 @@ MUTATIONS = [
      "if (y >= p->ny) y = 2 * p->ny - 2 - y;"),
     ("walls: ghost velocity not reversed", "(p->walls && y == 0) ? -uy[kS] : uy[kS]",
      "(p->walls && y == 0) ? uy[kS] : uy[kS]"),
+    ("B(c) of Eq. (18) at time n", "double Bh = p->B0 + p->B1 * ch[k];", "double Bh = p->B0 + p->B1 * s->c[k];"),
+    ("flux form: face value from the downwind node (x)",
+     "double Fr = uxr * (uxr >= 0.0 ? gc : g[kE]);\n        double Fl = uxl * (uxl >= 0.0 ? g[kW] : gc);",
+     "double Fr = uxr * (uxr >= 0.0 ? g[kE] : gc);\n        double Fl = uxl * (uxl >= 0.0 ? gc : g[kW]);"),
+    ("flux form: face value from the downwind node (y)",
+     "double Ft = uyt * (uyt >= 0.0 ? gc : g[kN]);\n        double Fb = uyb * (uyb >= 0.0 ? g[kS] : gc);",
+     "double Ft = uyt * (uyt >= 0.0 ? g[kN] : gc);\n        double Fb = uyb * (uyb >= 0.0 ? gc : g[kS]);"),
+    ("flux form: face velocity from one node", "double uxr = 0.5 * (ux[k] + ux[kE]), uxl = 0.5 * (ux[kW] + ux[k]);",
+     "double uxr = ux[k], uxl = ux[kW];"),
+    ("centre of mass: ties to the highest index", "if (best < 0 || d2 < bd) {", "if (best < 0 || d2 <= bd) {"),
+    ("centre of mass: x offset not unwrapped", "double dx = minimg((double)x - s->drop[k].x, (double)p->nx);",
+     "double dx = (double)x - s->drop[k].x;"),
+    ("centre of mass: y offset wrapped with the x period",
+     "double dy = minimg((double)y - s->drop[k].y, yperiod(p));",
+     "double dy = minimg((double)y - s->drop[k].y, (double)p->nx);"),
+    ("centre of mass: new centre not wrapped", "s->drop[k].x = wrapd(s->drop[k].x + sx[k] / sw[k], (double)p->nx);",
+     "s->drop[k].x = s->drop[k].x + sx[k] / sw[k];"),
+    ("centre of mass: nodes assigned to the nearest production disk",
+     "double dx = minimg(x - s->drop[k].x, (double)s->p.nx);\n    double dy = minimg(y - s->drop[k].y, yperiod(&s->p));",
+     "double dx = minimg(x - s->drop[k].x - (s->drop[k].R - s->drop[k].Rs) * s->drop[k].ex, (double)s->p.nx);\n"
+     "    double dy = minimg(y - s->drop[k].y - (s->drop[k].R - s->drop[k].Rs) * s->drop[k].ey, yperiod(&s->p));"),
+    ("observables: min B with the sign of B1 reversed", "p->B0 + p->B1 * s->c[k]", "p->B0 - p->B1 * s->c[k]"),
+    ("observables: max|u| from u_x only", "double um = sqrt(vx[k] * vx[k] + vy[k] * vy[k]);",
+     "double um = fabs(vx[k]);"),
+    ("observables: droplet velocity unweighted", "su[d] += v * vx[k];", "su[d] += vx[k];"),
+    ("observables: droplet velocity components swapped", "su[d] += v * vx[k];\n          sv[d] += v * vy[k];",
+     "su[d] += v * vy[k];\n          sv[d] += v * vx[k];"),
+    ("observables: sum c over phi", "sc += s->c[k];", "sc += s->phi[k];"),
 ]
 
 
 # always run: one planted mistake from each part of the step (about 20 s); LBM_MUTATION_CHECK=1 runs them all
 DEFAULT = {"equilibrium without the 1/2", "force: sign of grad c", "upwind side reversed", "Laplacian centre weight",
-           "consumption sign", "walls: mirror ghost one row off"}
+           "consumption sign", "walls: mirror ghost one row off", "B(c) of Eq. (18) at time n",
+           "centre of mass: ties to the highest index"}
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
 def test_planted_mistake_is_caught(name, old, new):
     if name not in DEFAULT and os.environ.get("LBM_MUTATION_CHECK") != "1":
-        pytest.skip("set LBM_MUTATION_CHECK=1 (all mutations, about 90 s)")
+        pytest.skip("set LBM_MUTATION_CHECK=1 (all mutations, about two minutes)")
     src = open(SRC).read()
     assert src.count(old) >= 1, f"mutation site not found: {name}"
     with tempfile.TemporaryDirectory() as d:
