@@ -7,9 +7,11 @@ lattice in FP32, and the batched two-droplet sweep (32 lattices from 256 x 256 t
 launch sequence under hipGraph replay.
 
 Timing: W warm-up steps, then exactly K steps bracketed by torch.cuda.synchronize() and hipEvents recorded
-on the library's stream.  MLUPS = lattice nodes x K / seconds / 1e6.  The roofline figure of the dominant
-kernel uses its algorithmic bytes per launch (one read and one write of each value it must move) over its
-average launch duration, measured with hipEvents around each launch of that kernel.
+on the library's stream, replayed from hipGraphs of G steps (G the largest even divisor of K up to
+--graph-steps).  MLUPS = lattice nodes x K / seconds / 1e6; the same K steps are then timed five more times
+and their median reported beside it.  The roofline figure of the dominant kernel uses its algorithmic bytes
+per launch (one read and one write of each value it must move) over its device time per launch, from
+back-to-back launches between two hipEvents on the library's stream (no events between launches).
 """
 import argparse
 import hashlib
@@ -41,6 +43,7 @@ def alg_bytes_per_node(kernel, precision):
     pb, fb = ELEM_BYTES[precision]
     return npop * pb + nfield * fb
 PATH_NAMES = {0: "fused", 1: "split", 2: "wave"}
+PATH_NUMBERS = {v: k for k, v in PATH_NAMES.items()}
 
 
 def kernel_source_hash() -> str:
@@ -99,28 +102,47 @@ def build_sim(workloads, precision, graph_steps, path):
                    [w.drop_dicts() for w in workloads], precision=precision, graph_steps=graph_steps, path=path)
 
 
-def time_steps(sim, steps, warmup):
+def graph_size(steps, graph_steps):
+    """Steps per hipGraph: the largest even divisor of `steps` not above `graph_steps` (0: no graphs), so that
+    every timed step is graph-replayed."""
+    if not graph_steps or steps < 2:
+        return 0
+    for g in range(min(graph_steps, steps), 1, -1):
+        if g % 2 == 0 and steps % g == 0:
+            return g
+    return 0
+
+
+def time_steps(sim, steps, warmup, repeats=0):
+    """ms for exactly `steps` steps after `warmup` steps (hipEvents on the library's stream), the wall time,
+    and the ms of `repeats` further timings of the same number of steps."""
     import torch
+    sim.set_graph(graph_size(steps, sim.graph_steps))  # captured here, outside the timed region
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(sim.stream)
-    sim.step(steps)
-    e1.record(sim.stream)
-    sim.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    return ms, wall
+
+    def once():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(sim.stream)
+        sim.step(steps)
+        e1.record(sim.stream)
+        sim.sync()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), time.perf_counter() - t0
+
+    ms, wall = once()
+    more = [once()[0] for _ in range(repeats)]
+    return ms, wall, more
 
 
 def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps, path=-1, seg_rows=0, strip_w=0):
     """path -1: the autotuner picks the kernel path (fused or wave sweep with its strip width and height, or
     split).  seg_rows / strip_w 0: autotuned (with a given height, width 0 keeps the default)."""
     from paper_1711_10984_amd import lbm
-    sim = build_sim(workloads, precision, graph_steps, 0 if path < 0 else path)
+    gsize = graph_size(steps, graph_steps)
+    sim = build_sim(workloads, precision, gsize, 0 if path < 0 else path)
     tune_ms = {}
     if path != 1 and seg_rows == 0:
         # state-preserving: the trial launches write scratch only
@@ -137,25 +159,32 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
         seg_rows = None
     strip_w = sim.strip_width if seg_rows is not None else None
     nodes = sum(w.nodes for w in workloads)
-    ms, wall = time_steps(sim, steps, warmup)
+    ms, wall, more = time_steps(sim, steps, warmup, repeats=5)
     obs = sim.observables(0)
-    per_kernel = sim.time_kernels(prof_steps)  # hipEvents around each launch on the library's stream
+    # device time per launch of the main kernel(s): back-to-back launches between two events (state unchanged)
+    device_ms = sim.time_launches(prof_steps)
+    per_kernel = sim.time_kernels(prof_steps)  # hipEvents around each eager launch (gaps included)
     sim.close()
     mlups = nodes * steps / (ms * 1e-3) / 1e6
-    dom = max((k for k in per_kernel if k in VALUES_PER_NODE), key=lambda k: per_kernel[k])
+    dom = max(device_ms, key=lambda k: device_ms[k])
     alg_bytes = alg_bytes_per_node(dom, precision) * nodes
-    achieved = alg_bytes / (per_kernel[dom] * 1e-3) / 1e9
+    achieved = alg_bytes / (device_ms[dom] * 1e-3) / 1e9
     step_bytes = alg_bytes_per_node("step", precision) * nodes
     step_gbs = step_bytes / (ms * 1e-3 / steps) / 1e9
     prec = PREC_NAMES[precision]
     traffic = measured_traffic(dom, label, prec, strip_w, seg_rows)
+    med = sorted(more)[len(more) // 2]
     return {
         "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
-        "kernel_ms": per_kernel, "seg_rows": seg_rows, "strip_width": strip_w, "autotune_ms": tune_ms,
-        "path": PATH_NAMES[path],
+        "median_of_5": {"ms_per_step": med / steps, "mlups": nodes * steps / (med * 1e-3) / 1e6,
+                        "ms_per_step_each": [m / steps for m in more]},
+        "graph": {"steps_per_graph": gsize, "graph_replayed_steps": steps - steps % gsize if gsize else 0},
+        "kernel_ms": per_kernel, "device_ms_per_launch": device_ms, "seg_rows": seg_rows, "strip_width": strip_w,
+        "autotune_ms": tune_ms, "path": PATH_NAMES[path],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": per_kernel[dom]},
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": device_ms[dom],
+                     "avg_launch_from": f"{prof_steps} back-to-back launches between two hipEvents"},
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "sanity": {"mass": obs["mass"], "sum_phi": obs["sum_phi"], "min_B": obs["min_B"], "max_u": obs["max_u"],
@@ -184,20 +213,26 @@ def _minimg(d, L):
     return (d + 0.5 * L) % L - 0.5 * L
 
 
-def lowp_accuracy(workloads, steps, log_every, graph_steps, path, low):
+def lowp_accuracy(workloads, steps, log_every, graph_steps, kernel, low):
     """A lower precision (`low`: LBM_FP32 or LBM_FP16) against FP64 on the GPU for the same inputs: largest
     centre-of-mass deviation over the run (trajectories logged every `log_every` steps), drift of the phi
     integral in both precisions, and the relative L2 difference of the velocity field at the end (first
-    lattice).  Lattices whose droplets come within 2R of each other (touching or coalescing, in the FP64 run)
-    are reported apart: once two droplets merge, their tracked centres share one body and follow no defined
-    trajectory, so the deviation there measures the merger, not the arithmetic."""
+    lattice).  `kernel` = (path, seg_rows, strip_width) of the throughput measurement whose accuracy this is:
+    both runs use that kernel, height and width.  Every lattice's deviation is listed; a lattice is marked as
+    merging when its droplets come within R_j + R_k of each other in the FP64 run (decided from the FP64
+    trajectory alone, before comparing): two tracked centres then share one body, and which centre takes a node
+    is a discrete decision that the two precisions may take differently."""
     import numpy as np
     from paper_1711_10984_amd import lbm
+    path, seg_rows, strip_w = kernel
     traj = {}
     end = {}
     phi_sum = {}
     for prec in (lbm.LBM_FP64, low):
-        sim = build_sim(workloads, prec, graph_steps, max(path, 0))
+        sim = build_sim(workloads, prec, graph_steps, path)
+        if path != 1:
+            sim.set_seg_rows(seg_rows)
+            sim.set_strip_width(strip_w)
         t = []
         s0 = [sim.observables(i)["sum_phi"] for i in range(len(workloads))]
         for k in range(steps // log_every):
@@ -207,30 +242,35 @@ def lowp_accuracy(workloads, steps, log_every, graph_steps, path, low):
         end[prec] = sim.fields(0)
         phi_sum[prec] = [sim.observables(i)["sum_phi"] - s0[i] for i in range(len(workloads))]
         sim.close()
-    dev_apart, touching = 0.0, {}
+    per_lattice, merging = {}, []
     for i, w in enumerate(workloads):
         dev, close = 0.0, False
-        for a, b in zip(traj[lbm.LBM_FP64], traj[low]):
-            for (xa, ya), (xb, yb) in zip(a[i], b[i]):
-                dev = max(dev, float(np.hypot(_minimg(xa - xb, w.nx), _minimg(ya - yb, w.ny))))
+        for a in traj[lbm.LBM_FP64]:  # the merge criterion, from the FP64 run only
             for j in range(len(a[i])):
                 for k in range(j + 1, len(a[i])):
                     sep = np.hypot(_minimg(a[i][j][0] - a[i][k][0], w.nx), _minimg(a[i][j][1] - a[i][k][1], w.ny))
                     close = close or sep < w.drops[j].R + w.drops[k].R
+        for a, b in zip(traj[lbm.LBM_FP64], traj[low]):
+            for (xa, ya), (xb, yb) in zip(a[i], b[i]):
+                dev = max(dev, float(np.hypot(_minimg(xa - xb, w.nx), _minimg(ya - yb, w.ny))))
+        per_lattice[w.name] = round(dev, 6)
         if close:
-            touching[w.name] = round(dev, 6)
-        else:
-            dev_apart = max(dev_apart, dev)
+            merging.append(w.name)
     u64, u32 = end[lbm.LBM_FP64], end[low]
     num = np.sqrt(np.sum((u64["ux"] - u32["ux"]) ** 2 + (u64["uy"] - u32["uy"]) ** 2))
     den = np.sqrt(np.sum(u64["ux"] ** 2 + u64["uy"] ** 2))
     out = {"steps": steps, "lattices": len(workloads), "log_every": log_every,
-           "max_cm_deviation_lu": round(dev_apart, 6),
+           "kernel": {"path": PATH_NAMES[path], "seg_rows": seg_rows if path != 1 else None,
+                      "strip_width": strip_w if path != 1 else None},
+           "max_cm_deviation_lu": round(max(per_lattice.values()), 6),
            "phi_integral_drift_fp64": round(float(max(phi_sum[lbm.LBM_FP64], key=abs)), 6),
            f"phi_integral_drift_{PREC_NAMES[low]}": round(float(max(phi_sum[low], key=abs)), 6),
            "velocity_l2_rel_diff": float(num / den) if den > 0 else None}
-    if touching:
-        out["lattices_with_touching_droplets"] = touching
+    if len(workloads) > 1:
+        apart = [v for k, v in per_lattice.items() if k not in merging]
+        out["per_lattice_max_cm_deviation_lu"] = per_lattice
+        out["merging_in_fp64_run"] = merging
+        out["max_cm_deviation_lu_non_merging"] = round(max(apart), 6) if apart else None
     return out
 
 def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
@@ -271,28 +311,95 @@ def oracle_rate(w, budget_s, max_steps=1000):
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= max_steps:
             break
-    return w.nodes * steps / el / 1e6, steps, el, num_threads()
+    return w.nodes * steps / el / 1e6, steps, el, num_threads(w.nx, w.ny)
+
+
+def host_cpu():
+    """CPU model and the number of cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"model": model, "logical_cpus_available": avail, "os_cpu_count": os.cpu_count()}
+
+
+def _oracle_instance(args):
+    """Worker: `steps` single-threaded oracle steps of one lattice; returns node-steps and seconds."""
+    from oracle import OracleSim, Params, Drop
+    nx, ny, params, phi0, c0, drops, steps = args
+    s = OracleSim(Params(nx=nx, ny=ny, **params), phi0, c0, [Drop(**d) for d in drops])
+    t0 = time.perf_counter()
+    s.run(steps)
+    return nx * ny * steps, time.perf_counter() - t0
+
+
+def oracle_parallel_instances(factory, steps, procs):
+    """The lattices of workloads.<factory>() as independent single-threaded oracle runs, `procs` at a time
+    (a process pool; run in a child started with OMP_NUM_THREADS=1): (MLUPS over the whole batch, lattices,
+    steps, seconds)."""
+    from multiprocessing import Pool
+    from paper_1711_10984_amd import workloads as W
+    ws = getattr(W, factory)()
+    jobs = [(w.nx, w.ny, w.params, w.phi0, w.c0, w.drop_dicts(), steps) for w in ws]
+    t0 = time.perf_counter()
+    with Pool(procs) as pool:
+        res = pool.map(_oracle_instance, jobs, chunksize=1)
+    el = time.perf_counter() - t0
+    return sum(r[0] for r in res) / el / 1e6, len(ws), steps, el
+
+
+def _child_json(code, env_extra, timeout=600):
+    import subprocess
+    res = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, **env_extra), capture_output=True,
+                         text=True, timeout=timeout, cwd=ROOT)
+    return json.loads(res.stdout.strip().splitlines()[-1])
 
 
 def cpu_baseline(w, budget_s, single_budget_s=8.0, factory="c5_emulsion"):
-    """The FP64 oracle as it stands on this host's cores, on a bounded sample of workload w; also on one thread
-    (a child process with OMP_NUM_THREADS=1, since OpenMP fixes its thread count at start-up), on the workload
-    that workloads.<factory>() builds (the same one)."""
-    import subprocess
+    """The FP64 oracle as it stands on this host's cores, on bounded samples: the headline workload w (all
+    threads, and one thread in a child process with OMP_NUM_THREADS=1, since OpenMP fixes its thread count at
+    start-up, on workloads.<factory>(), the same lattice), the 64^2 and 256^2 single-lattice configurations, and
+    the 32-lattice batch as independent single-threaded runs across the host's cores."""
+    from paper_1711_10984_amd import workloads as W
     rate, steps, el, threads = oracle_rate(w, budget_s)
+    host = host_cpu()
     out = {"value": round(rate, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-           "sample": f"{w.name}: {steps} FP64 steps of the full {w.nx}x{w.ny} lattice in {el:.1f} s"}
+           "sample": f"{w.name}: {steps} FP64 steps of the full {w.nx}x{w.ny} lattice in {el:.1f} s",
+           "host_cpu": host}
     code = ("import json, sys; sys.path.insert(0, %r); import bench; from paper_1711_10984_amd import workloads as W; "
             "w = W.%s(); r = bench.oracle_rate(w, %r); print(json.dumps(list(r) + [w.nx, w.ny]))"
-            % (os.path.dirname(os.path.abspath(__file__)), factory, single_budget_s))
+            % (ROOT, factory, single_budget_s))
     try:
-        res = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, OMP_NUM_THREADS="1"),
-                             capture_output=True, text=True, timeout=600)
-        r1, s1, e1, t1, nx1, ny1 = json.loads(res.stdout.strip().splitlines()[-1])
+        r1, s1, e1, t1, nx1, ny1 = _child_json(code, {"OMP_NUM_THREADS": "1"})
         out["single_thread"] = {"value": round(r1, 3), "cores": t1,
                                 "sample": f"{s1} FP64 steps of the full {nx1}x{ny1} lattice in {e1:.1f} s"}
-    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+    except Exception as e:  # noqa: BLE001 -- a failed child leaves a note, not a failed benchmark
         out["single_thread"] = {"error": str(e)[:200]}
+    configs = {}
+    for name, wl, budget in (("c1_64x64", W.c1_equilibrium(), 3.0), ("c2_256x256", W.c2_single_active(), 4.0)):
+        r, st, e, t = oracle_rate(wl, budget, max_steps=5000)
+        configs[name] = {"value": round(r, 3), "cores": t, "sample": f"{st} FP64 steps in {e:.1f} s"}
+    procs = min(16, host["logical_cpus_available"] or 1)
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "print(json.dumps(bench.oracle_parallel_instances('c3_batch', 40, %d)))" % (ROOT, procs))
+    try:
+        r3, n3, s3, e3 = _child_json(code, {"OMP_NUM_THREADS": "1"})
+        configs["c3_batch_32_lattices"] = {
+            "value": round(r3, 3), "cores": procs,
+            "sample": f"{n3} lattices as independent single-threaded runs, {procs} at a time, {s3} FP64 steps "
+                      f"each, in {e3:.1f} s"}
+    except Exception as e:  # noqa: BLE001
+        configs["c3_batch_32_lattices"] = {"error": str(e)[:200]}
+    out["configs"] = configs
     return out
 
 
@@ -362,6 +469,8 @@ def main():
         r = measure(wl, prec, args.steps, args.warmup, args.graph_steps, label, args.prof_steps, args.path,
                     args.seg_rows, args.strip_width)
         print(json.dumps({"only": args.only, "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
+                          "median_of_5": r["median_of_5"], "graph": r["graph"],
+                          "device_ms_per_launch": r["device_ms_per_launch"],
                           "roofline": r["roofline"], "kernel_ms": r["kernel_ms"], "seg_rows": r["seg_rows"],
                           "strip_width": r["strip_width"], "path": r["path"]}),
               flush=True)
@@ -404,39 +513,48 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "2048x2048 periodic dilute emulsion, 64 active droplets R=20 (seeded), FP64",
-                   "nx": 2048, "ny": 2048, "droplets": 64, "graph_steps": args.graph_steps,
+                   "nx": 2048, "ny": 2048, "droplets": 64,
+                   "graph_steps": main_res["graph"]["steps_per_graph"],
+                   "graph_replayed_steps": main_res["graph"]["graph_replayed_steps"],
                    "kernel_path": main_res["path"]},
+        "median_of_5": main_res["median_of_5"],
         "roofline": main_res["roofline"],
         "step_roofline": main_res["step_roofline"],
         "kernel_ms": main_res["kernel_ms"],
+        "device_ms_per_launch": main_res["device_ms_per_launch"],
         "autotune": {"seg_rows": main_res["seg_rows"], "strip_width": main_res["strip_width"],
                      "path": main_res["path"],
                      "ms_per_launch": main_res["autotune_ms"]},
         "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 5),
                          "nodes": v["nodes"], "precision": v["precision"], "gain_over_fp64": v["gain_over_fp64"],
                          "roofline": v["roofline"], "step_roofline": v["step_roofline"],
-                         "kernel_ms": v["kernel_ms"], "seg_rows": v["seg_rows"], "strip_width": v["strip_width"],
-                         "path": v["path"]}
+                         "kernel_ms": v["kernel_ms"], "device_ms_per_launch": v["device_ms_per_launch"],
+                         "median_of_5": v["median_of_5"], "graph": v["graph"],
+                         "seg_rows": v["seg_rows"], "strip_width": v["strip_width"], "path": v["path"]}
                      for k, v in variants.items()},
         "kernel_source_hash": kernel_source_hash(),
     }
-    if not args.no_accuracy and not args.no_variants:
+    if not args.no_accuracy and not args.no_variants and args.only is None:
+        # each accuracy run uses the kernel, strip height and width of the throughput variant it qualifies
+        kern = {k: (PATH_NUMBERS[v["path"]], v["seg_rows"], v["strip_width"]) for k, v in variants.items()}
+        gs = args.graph_steps
         out["fp32_accuracy"] = {
-            "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
-                                                args.path, lbm.LBM_FP32),
-            "batched_c3": lowp_accuracy(W.c3_batch(), 100000, 500, args.graph_steps, args.path, lbm.LBM_FP32),
-            "emulsion_2048_64_droplets": lowp_accuracy([c5], 100000, 1000, args.graph_steps, args.path,
-                                                       lbm.LBM_FP32),
+            "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, gs, kern["fp32_2048"],
+                                                lbm.LBM_FP32),
+            "batched_c3_config_length": lowp_accuracy(W.c3_batch(), 20000, 500, gs, kern["batched_c3_fp32"],
+                                                      lbm.LBM_FP32),
+            "batched_c3": lowp_accuracy(W.c3_batch(), 100000, 500, gs, kern["batched_c3_fp32"], lbm.LBM_FP32),
+            "emulsion_2048_64_droplets": lowp_accuracy([c5], 100000, 1000, gs, kern["fp32_2048"], lbm.LBM_FP32),
         }
         out["fp16_accuracy"] = {
-            "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, args.graph_steps,
-                                                args.path, lbm.LBM_FP16),
-            "emulsion_2048_64_droplets": lowp_accuracy([c5], 100000, 1000, args.graph_steps, args.path,
+            "single_droplet_256": lowp_accuracy([W.c2_single_active()], 100000, 1000, gs, kern["fp16_storage_2048"],
+                                                lbm.LBM_FP16),
+            "emulsion_2048_64_droplets": lowp_accuracy([c5], 100000, 1000, gs, kern["fp16_storage_2048"],
                                                        lbm.LBM_FP16),
         }
-    if not args.no_variants:
+    if not args.no_variants and args.only is None:
         out["adjoint"] = {"fp64": adjoint_measure(lbm.LBM_FP64), "fp32": adjoint_measure(lbm.LBM_FP32)}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.only is None:
         out["cpu_baseline"] = cpu_baseline(c5, args.cpu_budget)
     print(json.dumps(out), flush=True)
 

@@ -50,8 +50,9 @@ extern "C" {
 #define LBM_FP64 0 /* populations, fields and arithmetic in FP64 */
 #define LBM_FP32 1 /* populations stored as FP32 deviations f_i - w_i n0 from the rest state, fields and
                       arithmetic in FP32; droplet sums in FP64 */
-#define LBM_FP16 2 /* populations stored as FP16 deviations f_i - w_i n0 from the rest state (round to
-                      nearest even), widened to FP32 on load; fields and arithmetic FP32; sums FP64 */
+#define LBM_FP16 2 /* populations stored as FP16 values of 2^12 (f_i - w_i n0), the deviation from the rest
+                      state scaled by an exact power of two (round to nearest even), widened to FP32 and
+                      scaled back on load; fields and arithmetic FP32; sums FP64 */
 
 /* Boundaries in y (Sec. 2.2 names bounding walls, Sec. 2.3 neutral wetting at them).  LBM_WALLS_Y:
  * solid plates halfway between node rows, at y = -1/2 and y = ny - 1/2, x periodic.  Populations that
@@ -142,7 +143,10 @@ int lbm_init(const lbm_config* cfg, void* workspace, size_t workspace_bytes, voi
 int lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Replay the timestep through hipGraphs of `steps_per_graph` steps (even, >= 2), or launch kernels
- * one by one when 0.  Default: 20 on a non-default stream, 0 on the null stream. */
+ * one by one when 0.  Default: 20 on a non-default stream, 0 on the null stream.  The two graphs (one per
+ * parity of the starting step) are captured by this call; changing the path, strip height or width drops
+ * them, and the next lbm_step captures them again.  lbm_step replays whole graphs while at least
+ * steps_per_graph steps remain and launches the rest one by one. */
 int lbm_set_graph(lbm_ctx* ctx, int32_t steps_per_graph);
 
 /* Wait for the context's stream. */
@@ -223,6 +227,15 @@ int lbm_autotune(lbm_ctx* ctx, int32_t launches, int32_t both_paths, int32_t* ro
  * measured with hipEvents on the context's stream.  Fused path: ms_out = {k_step, k_reduce, 0};
  * wave path: {k_wave, k_reduce, 0}; split path: {k_lb, k_fd, k_reduce}.  Advances the state by n steps.  Synchronous. */
 int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
+
+/* Device time per launch (ms) of the timestep's main kernels, without the gaps that events or host launches
+ * between kernels add: `launches` back-to-back launches of each kernel, captured in a hipGraph, replayed once to
+ * warm up and once between two hipEvents on the context's stream (non-default; LBM_E_STATE otherwise), total
+ * time / launches.  Fused path: ms_out = {k_step, 0}; wave path: {k_wave, 0}; split path: {k_lb, k_fd}.  Like the
+ * autotuner's trials, the launches read the current state and write only scratch (the inactive halves of the
+ * ping-pong buffers, the velocity planes and the centre-of-mass partials): the state, the droplet table and the
+ * step counter are unchanged.  Synchronous. */
+int lbm_time_launches(lbm_ctx* ctx, int32_t launches, double* ms_out);
 
 /* ---- Reverse mode (the derivative of a droplet's displacement; Sec. 4 centre of mass) ----
  * The loss is J = x_CM(n0 + nsteps) - x_CM(n0) of droplet `drop` (minimum image in x, so |J| < nx/2), and the

@@ -517,6 +517,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads the loops of an nx x ny lattice run on (small lattices run on one). */
+int orc_threads_for(int nx, int ny) {
+  orc_params p;
+  memset(&p, 0, sizeof p);
+  p.nx = nx;
+  p.ny = ny;
+  return PAR(&p) ? orc_num_threads() : 1;
+}
+
 void orc_stages(orc_sim* s, double* out) { do_step(s, out); }
 
 int64_t orc_get_step(const orc_sim* s) { return s->step; }

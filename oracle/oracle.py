@@ -90,6 +90,8 @@ def load():
         lib.orc_run.argtypes = [C.c_void_p, C.c_int64]
         lib.orc_stage_count.restype = C.c_int
         lib.orc_num_threads.restype = C.c_int
+        lib.orc_threads_for.restype = C.c_int
+        lib.orc_threads_for.argtypes = [C.c_int, C.c_int]
         lib.orc_stages.argtypes = [C.c_void_p, dp]
         lib.orc_get_step.restype = C.c_int64
         lib.orc_get_step.argtypes = [C.c_void_p]
@@ -209,6 +211,9 @@ def div9(k: np.ndarray, X: np.ndarray):
     return out
 
 
-def num_threads() -> int:
-    """Threads the oracle's OpenMP loops use in this process."""
+def num_threads(nx: int = 0, ny: int = 0) -> int:
+    """Threads the oracle's OpenMP loops use in this process (for an nx x ny lattice if given: small lattices
+    run on one thread)."""
+    if nx and ny:
+        return int(load().orc_threads_for(int(nx), int(ny)))
     return int(load().orc_num_threads())

@@ -95,6 +95,30 @@ int validate(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop) {
   return LBM_OK;
 }
 
+// Model parameters of an instance, derived in double precision (advection form, walls, Eqs. 1-19).
+void set_model(const lbm_config& c, InstDev& d) {
+  d.advection = c.advection;
+  d.walls = c.walls;
+  d.yper = c.walls ? std::numeric_limits<double>::infinity() : (double)c.ny;
+  d.a = c.a;
+  d.b = c.b;
+  d.B0 = c.B0;
+  d.B1 = c.B1;
+  d.halfB1 = 0.5 * c.B1;
+  d.D = c.D;
+  d.Gamma = c.Gamma;
+  d.gamma = c.gamma;
+  d.c0 = c.c0;
+  d.omega = 1.0 / c.tau;
+  d.coef = 1.0 - 1.0 / (2.0 * c.tau);
+  d.A0 = c.A0;
+  d.t_star = c.t_star;
+  d.wn[0] = WGT[0] * c.n0;
+  d.wn[1] = WGT[1] * c.n0;
+  d.wn[2] = WGT[5] * c.n0;
+  d.n0 = c.n0;
+}
+
 void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, Layout& L) {
   L.prec = cfgs[0].precision;
   L.elem = L.prec == LBM_FP64 ? 8 : 4;
@@ -138,26 +162,7 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
     part_elems += (int64_t)d.tiles_x[TILING_SPLIT] * d.tiles_y[TILING_SPLIT] * d.ndrop * 3;
     d.part_base[TILING_FUSED] = part_elems1;
     part_elems1 += (int64_t)d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED] * d.ndrop * 3;
-    d.advection = c.advection;
-    d.walls = c.walls;
-    d.yper = c.walls ? std::numeric_limits<double>::infinity() : (double)c.ny;
-    d.a = c.a;
-    d.b = c.b;
-    d.B0 = c.B0;
-    d.B1 = c.B1;
-    d.halfB1 = 0.5 * c.B1;
-    d.D = c.D;
-    d.Gamma = c.Gamma;
-    d.gamma = c.gamma;
-    d.c0 = c.c0;
-    d.omega = 1.0 / c.tau;
-    d.coef = 1.0 - 1.0 / (2.0 * c.tau);
-    d.A0 = c.A0;
-    d.t_star = c.t_star;
-    d.wn[0] = WGT[0] * c.n0;
-    d.wn[1] = WGT[1] * c.n0;
-    d.wn[2] = WGT[5] * c.n0;
-    d.n0 = c.n0;
+    set_model(c, d);
     tile_base += d.tiles_x[TILING_SPLIT] * d.tiles_y[TILING_SPLIT];
     seg_base += d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED];
     drop_base += d.ndrop;
@@ -206,10 +211,32 @@ void make_layout(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, La
   L.total = off;
 }
 
+// Whether the owned box [x0, x1] x [y0, y1] of a strip segment of instance d comes within R + 2 (minimum
+// image) of a droplet centre, i.e. may hold the droplet's phi >= 0 nodes or its production disk.  Such
+// segments take longer (centre-of-mass sums, disk test) and are dispatched first.
+bool segment_holds_droplet(const InstDev& d, const std::vector<DropDev>& drops, int inst, int x0, int x1, int y0,
+                           int y1) {
+  const double xm = 0.5 * (x0 + x1), ym = 0.5 * (y0 + y1), hx = 0.5 * (x1 - x0), hy = 0.5 * (y1 - y0);
+  for (const DropDev& q : drops) {
+    if (q.inst != inst) continue;
+    double dx = std::fabs(xm - q.x), dy = std::fabs(ym - q.y);
+    if (dx > 0.5 * d.nx) dx = d.nx - dx;
+    if (!d.walls && dy > 0.5 * d.ny) dy = d.ny - dy;
+    dx = std::max(0.0, dx - hx);
+    dy = std::max(0.0, dy - hy);
+    const double r = q.R + 2.0;
+    if (dx * dx + dy * dy <= r * r) return true;
+  }
+  return false;
+}
+
 // Sweeping-kernel strips for a strip width and segment height: per-instance counts, natural indices,
-// partial offsets and the launch list (XCD-aware order).  Fits in the regions sized for STRIP_W_MIN and
-// SEG_ROWS_MIN.
-void set_segments(Layout& L, int seg_rows, int strip_w) {
+// partial offsets and the launch list.  The list is XCD-aware: workgroup b runs on XCD (b mod 8), and each
+// XCD gets a contiguous run of strips in natural order (neighbouring strips share that XCD's L2); within
+// its run, the strips that hold droplets (as of `drops`) are dispatched first, so that the longer-running
+// ones do not end the launch.  The launch order does not change any result (partials are stored by natural
+// index).  Fits in the regions sized for STRIP_W_MIN and SEG_ROWS_MIN.
+void set_segments(Layout& L, int seg_rows, int strip_w, const std::vector<DropDev>& drops) {
   int base = 0;
   int64_t part = 0;
   for (auto& d : L.inst) {
@@ -236,8 +263,22 @@ void set_segments(Layout& L, int seg_rows, int strip_w) {
   const int nxcd = 8;
   const int chunk = (base + nxcd - 1) / nxcd;
   L.segs.assign((size_t)chunk * nxcd, TileDev{-1, 0, 0, -1});
-  for (int t = 0; t < base; ++t) L.segs[(size_t)(t % chunk) * nxcd + t / chunk] = natural[t];
+  std::vector<TileDev> run;
+  for (int j = 0; j < nxcd; ++j) {
+    run.clear();
+    const int t0 = j * chunk, t1 = std::min(base, (j + 1) * chunk);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int t = t0; t < t1; ++t) {
+        const TileDev& s = natural[t];
+        const InstDev& d = L.inst[s.inst];
+        const bool heavy = segment_holds_droplet(d, drops, s.inst, s.x0, std::min(s.x0 + strip_w, d.nx) - 1, s.y0,
+                                                 std::min(s.y0 + seg_rows, d.ny) - 1);
+        if (heavy == (pass == 0)) run.push_back(s);
+      }
+    for (size_t k = 0; k < run.size(); ++k) L.segs[k * nxcd + j] = run[k];
+  }
 }
+
 
 }  // namespace
 
@@ -285,7 +326,8 @@ decltype(auto) with_types(int prec, F&& f) {
 
 // Host side of the population storage (the kernels' lb_moments / lb_collide).  FP64 stores the population.
 // FP32 stores the deviation from the rest population, fp32(f - fp32(w_i n0)), read back as that deviation plus
-// fp32(w_i n0).  FP16 storage keeps fp16(fp32(f) - fp32(w_i n0)), widened back as fp32(stored) + fp32(w_i n0).
+// fp32(w_i n0).  FP16 storage keeps fp16(2^12 (fp32(f) - fp32(w_i n0))), widened back as
+// fp32(stored) 2^-12 + fp32(w_i n0).
 template <typename T, typename P>
 P host_pop_store(double f, double wn) {
   if constexpr (sizeof(T) == 8) {
@@ -294,7 +336,7 @@ P host_pop_store(double f, double wn) {
   } else if constexpr (std::is_same<T, P>::value) {
     return (P)(f - (double)(float)wn);
   } else {
-    return (P)((float)f - (float)wn);
+    return (P)(((float)f - (float)wn) * FP16_SCALE);
   }
 }
 template <typename T, typename P>
@@ -305,7 +347,7 @@ double host_pop_load(P s, double wn) {
   } else if constexpr (std::is_same<T, P>::value) {
     return (double)s + (double)(float)wn;
   } else {
-    return (double)((float)s + (float)wn);
+    return (double)((float)s * (1.0f / FP16_SCALE) + (float)wn);
   }
 }
 
@@ -547,11 +589,24 @@ int read_drops(lbm_ctx* c, int inst, std::vector<DropDev>& out) {
   return LBM_OK;
 }
 
-// Rebuild the strip list for a segment height and strip width and upload it.
+// The droplet table of every instance (device copy).
+int read_all_drops(lbm_ctx* c, std::vector<DropDev>& out) {
+  out.resize(c->L.ndrop_total);
+  if (c->L.ndrop_total == 0) return LBM_OK;
+  HIPCHK(hipMemcpyAsync(out.data(), c->d_drops(), sizeof(DropDev) * out.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+// Rebuild the strip list for a segment height and strip width (launch order from the current droplet
+// centres) and upload it.
 int apply_segments(lbm_ctx* c, int rows, int width) {
   HIPCHK(hipStreamSynchronize(c->stream));
   destroy_graphs(c);
-  set_segments(c->L, rows, width);
+  std::vector<DropDev> drops;
+  int rc = read_all_drops(c, drops);
+  if (rc != LBM_OK) return rc;
+  set_segments(c->L, rows, width, drops);
   HIPCHK(hipMemcpyAsync(c->d_inst(), c->L.inst.data(), sizeof(InstDev) * c->L.inst.size(), hipMemcpyHostToDevice,
                         c->stream));
   HIPCHK(hipMemcpyAsync(c->d_segs(), c->L.segs.data(), sizeof(TileDev) * c->L.segs.size(), hipMemcpyHostToDevice,
@@ -594,9 +649,18 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
         !(d.R >= 0.0) || !(d.Rs >= 0.0))
       return fail(LBM_E_INVAL, "droplet table entries must be finite with R, Rs >= 0");
   }
+  std::vector<DropDev> dd(std::max(1, nd_total));
+  {
+    int k = 0;
+    for (int i = 0; i < ninst; ++i)
+      for (int j = 0; j < ndrop[i]; ++j, ++k) {
+        const lbm_droplet& s = drops[k];
+        dd[k] = DropDev{s.x, s.y, s.R, s.Rs, s.ex, s.ey, s.active ? 1 : 0, i};
+      }
+  }
   lbm_ctx* c = new lbm_ctx();
   make_layout(ninst, cfgs, ndrop, c->L);
-  set_segments(c->L, SEG_ROWS_DEFAULT, FUSED_TX);
+  set_segments(c->L, SEG_ROWS_DEFAULT, FUSED_TX, std::vector<DropDev>(dd.begin(), dd.begin() + nd_total));
   if (workspace_bytes < c->L.total) {
     delete c;
     return fail(LBM_E_NOMEM, "workspace smaller than lbm_workspace_bytes()");
@@ -622,13 +686,6 @@ int lbm_init_batch(int32_t ninst, const lbm_config* cfgs, void* workspace, size_
     if (rc != LBM_OK) return bail(rc);
     off_field += n;
   }
-  std::vector<DropDev> dd(std::max(1, nd_total));
-  int k = 0;
-  for (int i = 0; i < ninst; ++i)
-    for (int j = 0; j < ndrop[i]; ++j, ++k) {
-      const lbm_droplet& s = drops[k];
-      dd[k] = DropDev{s.x, s.y, s.R, s.Rs, s.ex, s.ey, s.active ? 1 : 0, i};
-    }
   hipError_t e;
 #define INIT_CHK(call)                                                                               \
   do {                                                                                               \
@@ -672,6 +729,11 @@ int lbm_set_graph(lbm_ctx* c, int32_t steps_per_graph) {
   if (steps_per_graph > 0 && !c->stream) return fail(LBM_E_STATE, "graph replay needs a non-default stream");
   destroy_graphs(c);
   c->graph_steps = steps_per_graph;
+  // capture both graphs now (one per starting parity), so that no later lbm_step pays for a capture
+  for (int p = 0; p < 2 && steps_per_graph > 0; ++p) {
+    const int rc = build_graph(c, p);
+    if (rc != LBM_OK) return rc;
+  }
   return LBM_OK;
 }
 
@@ -843,6 +905,55 @@ int lbm_time_kernels(lbm_ctx* c, int64_t n, double* ms_out) {
   return LBM_OK;
 }
 
+int lbm_time_launches(lbm_ctx* c, int32_t launches, double* ms_out) {
+  Range range("lbm_time_launches");
+  if (!c || !ms_out) return fail(LBM_E_INVAL, "null argument");
+  if (launches <= 0) return fail(LBM_E_INVAL, "launches must be > 0");
+  if (!c->stream) return fail(LBM_E_STATE, "timing launches in a graph needs a non-default stream");
+  ms_out[0] = ms_out[1] = 0.0;
+  const bool split = c->path == LBM_PATH_SPLIT;
+  // kernel k of the path over the current state, writing scratch only
+  auto one = [&](int k) -> hipError_t {
+    return with_types(c->L.prec, [&](auto t, auto p) -> hipError_t {
+      using T = decltype(t);
+      using P = decltype(p);
+      T* buf = reinterpret_cast<T*>(c->pool());
+      if (!split) return launch_sweep<T, P>(c, c->parity, nullptr, -1);
+      if (k == 0) return launch_lb<T, P>(c->stream, 0, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, nullptr, -1);
+      return launch_fd<T>(c->stream, 0, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(),
+                          c->d_part(), c->d_mask(), c->d_step(), nullptr, -1);
+    });
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int rc = LBM_OK;
+  for (int k = 0; k < (split ? 2 : 1) && rc == LBM_OK; ++k) {
+    // the launches are replayed from a graph, as lbm_step replays the timestep, so that no host launch gap
+    // separates them
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+    for (int r = 0; r < launches && e == hipSuccess; ++r) e = one(k);
+    const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+    if (e == hipSuccess) e = ec;
+    if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(x, c->stream);  // warm-up replay
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(x, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) rc = fail(LBM_E_HIP, std::string("timed launches: ") + hipGetErrorString(e));
+    ms_out[k] = (double)ms / launches;
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
 
 int lbm_set_seg_rows(lbm_ctx* c, int32_t rows) {
   if (!c) return fail(LBM_E_INVAL, "null context");

@@ -183,7 +183,8 @@ __device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k,
     dn = T(0);
     nn = ((d[0] + (d[2] + d[4])) + (d[1] + d[3])) + ((d[5] + d[6]) + (d[7] + d[8]));
   } else {
-    for (int i = 0; i < 9; ++i) d[i] = T(q[i]);
+    // FP16 storage holds 2^12 d_i (exact scaling by a power of two)
+    for (int i = 0; i < 9; ++i) d[i] = sizeof(P) == 2 ? T(q[i]) * T(1.0f / FP16_SCALE) : T(q[i]);
     dn = ((d[0] + (d[2] + d[4])) + (d[1] + d[3])) + ((d[5] + d[6]) + (d[7] + d[8]));
     nn = k.n0 + dn;
   }
@@ -207,12 +208,15 @@ __device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k,
 //   F_i    = 3 (1 - 1/(2 tau)) w_i h_i,   h_i = (e.F - u.F) + 3 (e.u)(e.F)
 //   d*_i   = d_i + omega (d_eq_i - d_i) + F_i
 // so that each moving direction costs nine operations, and u.u, u.F and the per-weight products are shared.
-// A deviation d* in the storage type.  FP16 storage keeps fp16(d*) of the FP32 value d*: the empty asm makes
-// d* opaque, so that the compiler cannot fuse the last FMA of d* with the conversion into one mixed-precision
-// instruction that rounds only once.
+// A deviation d* in the storage type.  FP16 storage keeps fp16(2^12 d*) of the FP32 value d* (the product is
+// exact): the empty asm makes d* opaque, so that the compiler cannot fuse the last FMA of d* with the conversion
+// into one mixed-precision instruction that rounds only once.
 template <typename P>
 __device__ __forceinline__ P store_dev(float ds) {
-  if constexpr (sizeof(P) == 2) asm("" : "+v"(ds));
+  if constexpr (sizeof(P) == 2) {
+    asm("" : "+v"(ds));
+    return P(ds * FP16_SCALE);
+  }
   return P(ds);
 }
 

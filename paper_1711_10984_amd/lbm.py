@@ -29,7 +29,7 @@ STAGES = ["mu", "X", "Fx", "Fy", "n", "ux", "uy", "phi_h", "c_h", "M", "X_h", "p
 ]
 EXPORTED = ["lbm_workspace_bytes", "lbm_init_batch", "lbm_init", "lbm_step", "lbm_set_graph", "lbm_sync",
             "lbm_get_step", "lbm_fields", "lbm_observables", "lbm_droplets", "lbm_debug_stage",
-            "lbm_time_kernels", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_set_seg_rows",
+            "lbm_time_kernels", "lbm_time_launches", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_set_seg_rows",
             "lbm_get_seg_rows", "lbm_set_strip_width", "lbm_get_strip_width", "lbm_tune_rows", "lbm_tune_widths",
             "lbm_autotune", "lbm_adjoint_bytes", "lbm_adjoint_forward",
             "lbm_adjoint_backward", "lbm_destroy", "lbm_last_error"]
@@ -70,6 +70,12 @@ def load_library(path: Optional[str] = None):
     global _lib
     if _lib is not None and path is None:
         return _lib
+    try:
+        # torch first: its HIP runtime (same soname) is then the one the library binds to.  Loaded the other way
+        # round, the process would hold two HIP runtimes and torch's device memory would be foreign to ours.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"HIP library not built: {p} is missing (run __graft_entry__.build())")
@@ -91,6 +97,7 @@ def load_library(path: Optional[str] = None):
     lib.lbm_droplets.argtypes = [vp, C.c_int32, C.POINTER(lbm_droplet)]
     lib.lbm_debug_stage.argtypes = [vp, C.c_int32, dp]
     lib.lbm_time_kernels.argtypes = [vp, C.c_int64, dp]
+    lib.lbm_time_launches.argtypes = [vp, C.c_int32, dp]
     lib.lbm_kernel_name.argtypes = [C.c_int32, C.c_int32]
     lib.lbm_kernel_name.restype = C.c_char_p
     lib.lbm_set_path.argtypes = [vp, C.c_int32]
@@ -217,6 +224,12 @@ def lbm_time_kernels(ctx: int, n: int) -> np.ndarray:
     return out
 
 
+def lbm_time_launches(ctx: int, launches: int) -> np.ndarray:
+    out = np.zeros(2)
+    _check(load_library().lbm_time_launches(C.c_void_p(ctx), int(launches), _dptr(out)))
+    return out
+
+
 def lbm_adjoint_bytes(ctx: int, nsteps: int, every: int) -> int:
     n = C.c_size_t(0)
     _check(load_library().lbm_adjoint_bytes(C.c_void_p(ctx), int(nsteps), int(every), C.byref(n)))
@@ -336,8 +349,10 @@ class Sim:
         self.ctx = lbm_init_batch(self.cfgs, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream, cat(phi0),
                                   cat(c0), fp, self.ndrop, dl, step)
         lbm_set_path(self.ctx, path)
+        # the library's default: 20-step graphs on the (non-default) stream
+        self.graph_steps = 20
         if graph_steps is not None:
-            lbm_set_graph(self.ctx, graph_steps)
+            self.set_graph(graph_steps)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -362,7 +377,9 @@ class Sim:
         lbm_sync(self.ctx)
 
     def set_graph(self, steps_per_graph: int) -> None:
+        """Steps per hipGraph replay (0: eager launches); the graphs are captured by this call."""
         lbm_set_graph(self.ctx, steps_per_graph)
+        self.graph_steps = steps_per_graph
 
     def fields(self, inst: int = 0) -> Dict[str, np.ndarray]:
         ny, nx = self.shapes[inst]
@@ -425,6 +442,13 @@ class Sim:
         path = lbm_get_path(self.ctx)
         return {lbm_kernel_name(path, i): float(ms[i]) for i in range(3) if lbm_kernel_name(path, i)}
 
+    def time_launches(self, launches: int) -> Dict[str, float]:
+        """Device ms per launch of the current path's main kernels from back-to-back launches (state unchanged)."""
+        ms = lbm_time_launches(self.ctx, launches)
+        path = lbm_get_path(self.ctx)
+        names = ("k_lb", "k_fd") if path == LBM_PATH_SPLIT else (lbm_kernel_name(path, 0),)
+        return {k: float(ms[i]) for i, k in enumerate(names)}
+
     def adjoint_forward(self, drop: int, nsteps: int, every: int = 100) -> float:
         """Advance nsteps steps keeping checkpoints every `every` steps (the adjoint workspace is a torch
         uint8 tensor held by this object) and return J = x_CM(end) - x_CM(start) of droplet `drop`."""
@@ -465,8 +489,9 @@ def _make_com_displacement():
 
         @staticmethod
         def backward(ctx, gJ):
+            # the context stays alive with ctx (a second backward, e.g. with retain_graph, repeats the first);
+            # it is released when autograd frees ctx
             dA0, dc0 = ctx.sim.adjoint_backward()
-            ctx.sim.close()
             g = gJ.detach().cpu().double()
             gA0 = (g * dA0).to(torch.float64)
             gpsi = (g * torch.from_numpy(dc0)).to(device=ctx.psi_device, dtype=ctx.psi_dtype)

@@ -215,3 +215,19 @@ def test_torch_autograd_wrapper():
     assert float(J.detach()) == Jr
     assert float(A0.grad) == 3.0 * dA0
     assert np.array_equal(psi.grad.numpy(), 3.0 * dc0)
+
+
+def test_torch_autograd_wrapper_second_backward():
+    """With retain_graph the wrapper's backward can run twice (the library context lives as long as autograd
+    keeps the node): the second pass accumulates exactly the same gradients again."""
+    import torch
+    from paper_1711_10984_amd import lbm
+    w = W.c2_single_active(n=64, seed=49)
+    A0 = torch.tensor(2e-6, dtype=torch.float64, requires_grad=True)
+    psi = torch.tensor(w.c0, dtype=torch.float64, requires_grad=True)
+    J = lbm.com_displacement(A0, psi, w.param_dict(), w.phi0, w.drop_dicts(), nsteps=60, every=20)
+    J.backward(retain_graph=True)
+    g1, p1 = float(A0.grad), psi.grad.clone()
+    J.backward()
+    assert float(A0.grad) == 2.0 * g1
+    assert torch.equal(psi.grad, 2.0 * p1)

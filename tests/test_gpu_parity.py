@@ -108,26 +108,52 @@ def test_c2_active_droplet_256_first_1000_steps(path):
     assert np.max(np.abs(og["com"] - orr["com"])) < 1e-12 * w.nx
     assert abs(og["mass"] - orr["mass"]) < 1e-12 * orr["mass"]
     assert abs(og["sum_phi"] - orr["sum_phi"]) < 1e-12 * abs(orr["sum_phi"])
+    assert abs(og["sum_c"] - orr["sum_c"]) < 1e-12 * abs(orr["sum_c"])
+    assert abs(og["min_B"] - orr["min_B"]) < 1e-12 * abs(orr["min_B"])  # a minimum: the same node's value
+    assert abs(og["max_u"] - orr["max_u"]) < 1e-12 * orr["max_u"]
+    assert og["nonfinite"] == orr["nonfinite"] is False
     assert np.max(np.abs(og["vel"] - orr["vel"])) < 1e-12 * max(1e-8, np.max(np.abs(orr["vel"])))
+    assert np.max(np.abs(og["drop_mass"] - orr["drop_mass"])) < 1e-12 * np.max(orr["drop_mass"])
     sim.close()
 
 
+@functools.lru_cache(maxsize=2)
+def _c5_reference(steps):
+    ref = oracle_sim(_c5())
+    ref.run(steps)
+    return ref.fields(), np.array([[d.x, d.y] for d in ref.drops()])
+
+
 @pytest.mark.parametrize("path", [0, 2])
-def test_c5_emulsion_2048_bench_configuration(path):
-    """Full-size 2048^2 emulsion with 64 droplets, in the benchmark's launch configuration (the autotuner's
-    strip height for the path, graph replay): every field after a few steps against the oracle on the whole
-    lattice."""
+def test_c5_emulsion_2048_every_tuned_height(path):
+    """Full-size 2048^2 emulsion with 64 droplets at every strip height the autotuner may pick (the bench's
+    launch configuration is one of them), graph replay: every field after 4 steps within 1e-12 of the oracle
+    on the whole lattice, centres within 1e-12 nx."""
     w = _c5()
-    sim = gpu_sim(w, graph_steps=2, path=path)
-    rows, chosen, _ = sim.autotune(3, both_paths=False)
-    assert chosen == path and rows in sim.tune_rows()
-    ref = oracle_sim(w)
-    sim.step(4)
-    ref.run(4)
-    compare(sim.fields(), ref.fields(), 1e-12, "c5 4 steps")
+    r, orr = _c5_reference(4)
+    for rows in _lbm().lbm_tune_rows():
+        sim = gpu_sim(w, graph_steps=2, path=path)
+        sim.set_seg_rows(rows)
+        sim.step(4)
+        compare(sim.fields(), r, 1e-12, f"c5 4 steps, height {rows}")
+        og = np.array([[d["x"], d["y"]] for d in sim.droplets()])
+        assert np.max(np.abs(og - orr)) < 1e-12 * w.nx, rows
+        sim.close()
+        del sim
+
+
+def test_c5_emulsion_2048_bench_configuration():
+    """The benchmark's own configuration: the autotuner over every path with 30 launches per candidate, then
+    one 100-step hipGraph replay, against 100 oracle steps of the whole lattice."""
+    w = _c5()
+    r, orr = _c5_reference(100)
+    sim = gpu_sim(w, graph_steps=100, path=0)
+    rows, path, _ = sim.autotune(30, both_paths=True)
+    sim.set_graph(100)
+    sim.step(100)
+    compare(sim.fields(), r, 1e-12, f"c5 100 steps, path {path}, height {rows}, width {sim.strip_width}")
     og = np.array([[d["x"], d["y"]] for d in sim.droplets()])
-    orr = np.array([[d.x, d.y] for d in ref.drops()])
-    assert np.max(np.abs(og - orr)) < 1e-9
+    assert np.max(np.abs(og - orr)) < 1e-12 * w.nx
     sim.close()
 
 
@@ -166,29 +192,57 @@ def test_c5_crop_256_matches_oracle(precision, path):
     sim.close()
 
 
-def test_batched_uneven_instances_match_oracle():
-    lbm = _lbm()
+def _uneven_batch():
+    """Lattices of uneven sizes in one batch: 96^2 active, 64^2 equilibrium, a ragged 110 x 37 pair (one passive
+    droplet), and four of the two-droplet sweep's 256 x 256 .. 512 x 256 lattices (active-active and
+    active-passive, head-on)."""
     ws = [W.c2_single_active(n=96, seed=11), W.c1_equilibrium(seed=12)]
-    # a ragged two-droplet instance
     a = W.DropSpec(30.0, 18.0, 10.0, 2.5, ex=1.0, ey=0.0, active=1)
     b = W.DropSpec(75.0, 22.0, 10.0, 2.5, ex=-1.0, ey=0.0, active=0, psi_front=0.0, psi_back=0.0)
     phi, c = W.droplet_fields(110, 37, [a, b], seed=13)
     ws.append(W.Workload("ragged_110x37", 110, 37, dict(W.ACTIVE, A0=1e-6), phi, c, [a, b]))
-    sim = lbm.Sim([w.param_dict() for w in ws], [w.phi0 for w in ws], [w.c0 for w in ws],
-                  [w.drop_dicts() for w in ws], precision=lbm.LBM_FP64, graph_steps=10)
-    sim.step(300)
-    for i, w in enumerate(ws):
+    c3 = W.c3_batch()
+    ws += [c3[i] for i in (1, 10, 19, 30)]
+    return ws
+
+
+@functools.lru_cache(maxsize=1)
+def _uneven_batch_reference(steps):
+    out = []
+    for w in _uneven_batch():
         ref = oracle_sim(w)
-        ref.run(300)
-        compare(sim.fields(i), ref.fields(), 1e-12, w.name)
+        ref.run(steps)
+        out.append((ref.fields(), np.array([[d.x, d.y] for d in ref.drops()])))
+    return out
+
+
+@pytest.mark.parametrize("path,rows", [(0, 16), (0, 40), (1, None), (2, 16), (2, 44)])
+def test_batched_uneven_instances_match_oracle(path, rows):
+    """FP64 batch of uneven lattices in one launch sequence on every path (and short and tall strip segments):
+    each instance within 1e-12 of its own oracle run after 300 steps, centres within 1e-12 nx."""
+    lbm = _lbm()
+    ws = _uneven_batch()
+    assert len({(w.nx, w.ny) for w in ws}) >= 5
+    sim = lbm.Sim([w.param_dict() for w in ws], [w.phi0 for w in ws], [w.c0 for w in ws],
+                  [w.drop_dicts() for w in ws], precision=lbm.LBM_FP64, graph_steps=10, path=path)
+    if rows is not None:
+        sim.set_seg_rows(rows)
+    sim.step(300)
+    for i, (w, (r, orr)) in enumerate(zip(ws, _uneven_batch_reference(300))):
+        compare(sim.fields(i), r, 1e-12, w.name)
+        og = np.array([[d["x"], d["y"]] for d in sim.droplets(i)])
+        assert np.max(np.abs(og - orr)) < 1e-12 * w.nx, w.name
     sim.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2])
 @pytest.mark.parametrize("other", [1, 2])
-def test_fused_and_other_paths_agree_bitwise(other):
+def test_fused_and_other_paths_agree_bitwise(other, precision):
+    """Every path computes the same arithmetic in every precision (FP32 and FP16 storage contract a * b + c only
+    within a source expression, and the paths share those expressions), so the fields agree bit for bit."""
     w = W.c5_emulsion(n=384, ndrop=6, R=16.0, seed=21)
-    s1 = gpu_sim(w, path=0, graph_steps=10)
-    s2 = gpu_sim(w, path=other, graph_steps=10)
+    s1 = gpu_sim(w, path=0, graph_steps=10, precision=precision)
+    s2 = gpu_sim(w, path=other, graph_steps=10, precision=precision)
     s1.step(120)
     s2.step(120)
     f1, f2 = s1.fields(), s2.fields()
@@ -357,16 +411,17 @@ def test_maximum_droplet_count_matches_oracle(path):
     sim.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2])
 @pytest.mark.parametrize("path", [0, 2])
-def test_segment_heights_agree_bitwise_and_autotune_keeps_state(path):
+def test_segment_heights_agree_bitwise_and_autotune_keeps_state(path, precision):
     """The sweeping kernels' strip width and height change only the work decomposition: every width and
-    height gives the same bits; the autotuner's trial launches leave the state, droplets and step counter
-    untouched."""
+    height gives the same bits, in every precision; the autotuner's trial launches and lbm_time_launches leave the
+    state, droplets and step counter untouched."""
     lbm = _lbm()
     w = W.c5_emulsion(n=300, ndrop=4, R=14.0, seed=31)
     ref = None
     for rows, width in ((16, 54), (32, 48), (64, 32), (128, 41), (256, 54), (20, 48)):
-        s = gpu_sim(w, graph_steps=0, path=path)
+        s = gpu_sim(w, graph_steps=0, path=path, precision=precision)
         s.set_seg_rows(rows)
         s.set_strip_width(width)
         assert s.strip_width == width and s.seg_rows == rows
@@ -381,10 +436,12 @@ def test_segment_heights_agree_bitwise_and_autotune_keeps_state(path):
             with pytest.raises(lbm.LBMError):
                 s.set_strip_width(bad)
         s.close()
-    s = gpu_sim(w, graph_steps=10, path=path)
+    s = gpu_sim(w, graph_steps=10, path=path, precision=precision)
     s.step(5)
     before, drops_before, step_before = s.fields(), s.droplets(), s.step_count
     chosen, chosen_path, times = s.autotune(3, both_paths=False)
+    ms = s.time_launches(4)
+    assert list(ms) == [lbm.lbm_kernel_name(path, 0)] and ms[lbm.lbm_kernel_name(path, 0)] > 0
     assert chosen_path == path and chosen in s.tune_rows() and len(times) >= 3
     assert s.strip_width in lbm.lbm_tune_widths()
     assert {k.split(":")[1].split("x")[0] for k in times} == {str(x) for x in lbm.lbm_tune_widths()}
@@ -449,18 +506,27 @@ def test_stage_export_keeps_state(path):
     s.close()
 
 
-def test_fp32_batched_instances_match_single_runs():
-    """Batching does not change any instance's arithmetic (FP32, uneven sizes)."""
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("path,rows", [(0, 16), (1, None), (2, 16), (2, 26)])
+def test_low_precision_batched_instances_match_single_runs(path, rows, precision):
+    """Batching does not change any instance's arithmetic (FP32 and FP16 storage, uneven sizes, every path):
+    each lattice of a C3-like batch on the given path and height equals its own single run on the fused path at
+    the default height, bit for bit."""
     lbm = _lbm()
     ws = W.c3_batch()[::7]
     sim = lbm.Sim([w.param_dict() for w in ws], [w.phi0 for w in ws], [w.c0 for w in ws],
-                  [w.drop_dicts() for w in ws], precision=lbm.LBM_FP32, graph_steps=10)
+                  [w.drop_dicts() for w in ws], precision=precision, graph_steps=10, path=path)
+    if rows is not None:
+        sim.set_seg_rows(rows)
     sim.step(60)
     for i, w in enumerate(ws):
-        single = gpu_sim(w, precision=1, graph_steps=10)
+        single = gpu_sim(w, precision=precision, graph_steps=10)
         single.step(60)
         a, b = sim.fields(i), single.fields()
         for k in FIELDS:
             assert np.array_equal(a[k], b[k]), (w.name, k)
+        # centres: the per-strip partial sums are added in an order that depends on the strip height
+        for da, db in zip(sim.droplets(i), single.droplets()):
+            assert abs(da["x"] - db["x"]) < 1e-12 * w.nx and abs(da["y"] - db["y"]) < 1e-12 * w.ny
         single.close()
     sim.close()
