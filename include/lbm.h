@@ -237,6 +237,33 @@ int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
  * step counter are unchanged.  Synchronous. */
 int lbm_time_launches(lbm_ctx* ctx, int32_t launches, double* ms_out);
 
+/* ---- For callers that cannot allocate ------------------------------------------------------------------
+ * Code under HIP stream capture, tight serving loops and harnesses that forbid allocation can advance one
+ * lattice with lbm_step_noalloc: no context, no workspace, no graph.  It calls no hipMalloc, hipFree or other
+ * allocating routine and never synchronises; it only enqueues kernels on `stream` (may be NULL).  Its scratch
+ * (instance description, strip list, step counter, droplet table, centre-of-mass partials and masks) is a static
+ * device array of LBM_NOALLOC_SCRATCH_BYTES that each GPU holds until the process ends; lattices whose scratch
+ * would not fit are rejected (LBM_E_NOMEM; e.g. 2048 x 2048 with up to 256 droplets fits).  Calls on one GPU
+ * share that array: calls that overlap in time on one GPU (other streams, other threads) race; calls ordered on
+ * one stream do not.
+ * The caller passes the state (inputs and outputs) in device memory, each buffer 256-byte aligned, rows of nx
+ * values with no padding:
+ *   f[0], f[1]:   [9][ny][nx] post-collision populations stored at the emitting node, f*_i(r), so that the
+ *                 pre-collision population is f_i(r) = f*_i(r - e_i) (with LBM_WALLS_Y, f*_OPP(i)(r) where r - e_i
+ *                 lies behind a plate); LBM_FP64 stores doubles, LBM_FP32 the floats f*_i - (float)(w_i n0),
+ *                 LBM_FP16 the _Float16 values of 2^12 ((float)f*_i - (float)(w_i n0));
+ *   phi[0..1], c[0..1]: [ny][nx] doubles (LBM_FP64) or floats;
+ *   drops:        device array of `ndrop` lbm_droplet, the current centres of mass r_CM (e.g. from
+ *                 lbm_droplets), updated in place with the centres after the run.
+ * The state at step `step` is read from f[0], phi[0], c[0]; after nsteps steps (Secs. 2.2-2.3 and the Sec. 4
+ * centre update, the wave-path kernels of lbm_step at strip width 54 and height 40) the state at step + nsteps is
+ * in index (nsteps mod 2) of each pair, and the other index holds the state one step earlier (nsteps >= 1).
+ * Results equal those of lbm_step on the same state bit for bit.  Errors: LBM_E_INVAL (configuration as for
+ * lbm_init, NULL or misaligned buffers, step or nsteps < 0), LBM_E_NOMEM (scratch too small), LBM_E_HIP. */
+#define LBM_NOALLOC_SCRATCH_BYTES (16u << 20)
+int lbm_step_noalloc(const lbm_config* cfg, void* stream, void* const f[2], void* const phi[2], void* const c[2],
+                     int32_t ndrop, lbm_droplet* drops, int64_t step, int64_t nsteps);
+
 /* ---- Reverse mode (the derivative of a droplet's displacement; Sec. 4 centre of mass) ----
  * The loss is J = x_CM(n0 + nsteps) - x_CM(n0) of droplet `drop` (minimum image in x, so |J| < nx/2), and the
  * derivatives are with respect to the production rate A0 of Sec. 4 (A(n) = A0 min(n, t_star)) and to the

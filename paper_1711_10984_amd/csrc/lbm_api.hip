@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -615,9 +616,167 @@ int apply_segments(lbm_ctx* c, int rows, int width) {
   return LBM_OK;
 }
 
+// ---- Scratch of the entry point that allocates nothing (lbm_step_noalloc) ---------------------------------
+// The instance description, the strip list, the step counter, the droplet table, the centre-of-mass partials
+// and the presence masks of lbm_step_noalloc live in this device array: each GPU the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names the symbol, not a device address; host code
+// uses only the address hipGetSymbolAddress returned on the current device (g_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[LBM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+constexpr int NOALLOC_SEG_ROWS = 40;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Address of `scratch` on the current device, looked up once per device (with that device current).
+int scratch_on_current_device(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(LBM_E_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(LBM_E_HIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+// Byte offsets of the regions of the scratch array for one lattice.
+struct NoallocLayout {
+  size_t inst, step, drops, segs, mask, part, total;
+};
+
+NoallocLayout noalloc_layout(int nsegs, int nslots, int ndrop) {
+  NoallocLayout L;
+  size_t off = 0;
+  L.inst = off;  off = align_up(off + sizeof(InstDev), ALIGN);
+  L.step = off;  off = align_up(off + sizeof(int64_t), ALIGN);
+  L.drops = off; off = align_up(off + sizeof(DropDev) * (size_t)std::max(1, ndrop), ALIGN);
+  L.segs = off;  off = align_up(off + sizeof(TileDev) * (size_t)nslots, ALIGN);
+  L.mask = off;  off = align_up(off + sizeof(uint64_t) * MASK_WORDS * (size_t)nsegs, ALIGN);
+  L.part = off;  off = align_up(off + sizeof(double) * 3 * (size_t)nsegs * (size_t)std::max(1, ndrop), ALIGN);
+  L.total = off;
+  return L;
+}
+
+// Fills the scratch regions: instance description, step counter, droplet table (from the caller's), the strip
+// list in the XCD-aware order of set_segments (natural strip t at slot (t mod chunk) * 8 + t / chunk), and the
+// presence masks cleared.
+__global__ __launch_bounds__(NTHREADS) void k_noalloc_setup(InstDev inst, int64_t step, NoallocLayout L, int nsegs,
+                                                            int nslots, int chunk, int ndrop,
+                                                            const lbm_droplet* __restrict__ drops, char* __restrict__ s) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  if (gid == 0) {
+    *reinterpret_cast<InstDev*>(s + L.inst) = inst;
+    *reinterpret_cast<int64_t*>(s + L.step) = step;
+  }
+  const int tx = inst.tiles_x[TILING_FUSED];
+  TileDev* segs = reinterpret_cast<TileDev*>(s + L.segs);
+  for (int b = gid; b < nslots; b += stride) {
+    const int t = (b % 8) * chunk + b / 8;
+    segs[b] = t < nsegs ? TileDev{0, (t % tx) * inst.strip_w, (t / tx) * inst.seg_rows, t} : TileDev{-1, 0, 0, -1};
+  }
+  uint64_t* mask = reinterpret_cast<uint64_t*>(s + L.mask);
+  for (int m = gid; m < nsegs * MASK_WORDS; m += stride) mask[m] = 0ull;
+  DropDev* dd = reinterpret_cast<DropDev*>(s + L.drops);
+  for (int k = gid; k < ndrop; k += stride) {
+    const lbm_droplet q = drops[k];
+    dd[k] = DropDev{q.x, q.y, q.R, q.Rs, q.ex, q.ey, q.active ? 1 : 0, 0};
+  }
+}
+
+// The new centres back into the caller's droplet table.
+__global__ __launch_bounds__(NTHREADS) void k_noalloc_centres(const DropDev* __restrict__ dd, int ndrop,
+                                                              lbm_droplet* __restrict__ drops) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ndrop) {
+    drops[k].x = dd[k].x;
+    drops[k].y = dd[k].y;
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+int lbm_step_noalloc(const lbm_config* cfg, void* stream, void* const f[2], void* const phi[2], void* const c[2],
+                     int32_t ndrop, lbm_droplet* drops, int64_t step, int64_t nsteps) {
+  if (!cfg) return fail(LBM_E_INVAL, "cfg must not be NULL");
+  int rc = validate(1, cfg, &ndrop);
+  if (rc != LBM_OK) return rc;
+  if (!f || !phi || !c) return fail(LBM_E_INVAL, "f, phi and c must not be NULL");
+  void* const bufs[6] = {f[0], f[1], phi[0], phi[1], c[0], c[1]};
+  for (void* b : bufs)
+    if (!b || reinterpret_cast<uintptr_t>(b) % ALIGN)
+      return fail(LBM_E_INVAL, "state buffers must be non-NULL and 256-byte aligned");
+  if (ndrop > 0 && !drops) return fail(LBM_E_INVAL, "drops must not be NULL when ndrop > 0");
+  if (step < 0 || nsteps < 0) return fail(LBM_E_INVAL, "step and nsteps must be >= 0");
+  const lbm_config& cf = *cfg;
+  const size_t elem = cf.precision == LBM_FP64 ? 8 : 4;
+  InstDev d;
+  memset(&d, 0, sizeof d);
+  d.nx = cf.nx;
+  d.ny = cf.ny;
+  d.pitch = cf.nx;
+  d.pstride = (int64_t)cf.nx * cf.ny;
+  d.ndrop = ndrop;
+  d.strip_w = FUSED_TX;
+  d.seg_rows = NOALLOC_SEG_ROWS;
+  d.tiles_x[TILING_FUSED] = (cf.nx + FUSED_TX - 1) / FUSED_TX;
+  d.tiles_y[TILING_FUSED] = (cf.ny + NOALLOC_SEG_ROWS - 1) / NOALLOC_SEG_ROWS;
+  // element offsets of the caller's buffers from f[0] (the pool base of the kernels); 256-byte alignment makes
+  // every difference a whole number of elements
+  const char* base = static_cast<const char*>(f[0]);
+  auto off = [&](void* b) { return (int64_t)(static_cast<const char*>(b) - base) / (int64_t)elem; };
+  d.off_f[0] = off(f[0]);
+  d.off_f[1] = off(f[1]);
+  d.off_phi[0] = off(phi[0]);
+  d.off_phi[1] = off(phi[1]);
+  d.off_c[0] = off(c[0]);
+  d.off_c[1] = off(c[1]);
+  set_model(cf, d);
+  const int nsegs = d.tiles_x[TILING_FUSED] * d.tiles_y[TILING_FUSED];
+  const int nslots = (nsegs + 7) / 8 * 8;
+  const NoallocLayout L = noalloc_layout(nsegs, nslots, ndrop);
+  if (L.total > LBM_NOALLOC_SCRATCH_BYTES)
+    return fail(LBM_E_NOMEM, "this lattice and droplet count need " + std::to_string(L.total) +
+                                 " bytes of scratch, more than LBM_NOALLOC_SCRATCH_BYTES (" +
+                                 std::to_string((size_t)LBM_NOALLOC_SCRATCH_BYTES) + ")");
+  void* sp = nullptr;
+  if ((rc = scratch_on_current_device(&sp)) != LBM_OK) return rc;
+  char* s = static_cast<char*>(sp);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int work = std::max(std::max(nslots, nsegs * MASK_WORDS), ndrop);
+  hipLaunchKernelGGL(k_noalloc_setup, dim3((work + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), 0, st, d, step, L, nsegs,
+                     nslots, nslots / 8, ndrop, drops, s);
+  HIPCHK(hipGetLastError());
+  const InstDev* di = reinterpret_cast<const InstDev*>(s + L.inst);
+  const TileDev* segs = reinterpret_cast<const TileDev*>(s + L.segs);
+  DropDev* dd = reinterpret_cast<DropDev*>(s + L.drops);
+  double* part = reinterpret_cast<double*>(s + L.part);
+  uint64_t* mask = reinterpret_cast<uint64_t*>(s + L.mask);
+  int64_t* dstep = reinterpret_cast<int64_t*>(s + L.step);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int parity = (int)(k & 1);
+    hipError_t e = with_types(cf.precision, [&](auto t, auto p) {
+      using T = decltype(t);
+      return launch_wave<T, decltype(p)>(st, parity, nslots, segs, di, reinterpret_cast<T*>(const_cast<char*>(base)), dd,
+                                         part, mask, dstep, nullptr, -1);
+    });
+    if (e == hipSuccess) e = launch_reduce(st, TILING_FUSED, ndrop, di, dd, part, mask, dstep, 1);
+    if (e != hipSuccess) return fail(LBM_E_HIP, std::string("timestep launch: ") + hipGetErrorString(e));
+  }
+  if (ndrop > 0) {
+    hipLaunchKernelGGL(k_noalloc_centres, dim3((ndrop + NTHREADS - 1) / NTHREADS), dim3(NTHREADS), 0, st, dd, ndrop,
+                       drops);
+    HIPCHK(hipGetLastError());
+  }
+  return LBM_OK;
+}
 
 int lbm_workspace_bytes(int32_t ninst, const lbm_config* cfgs, const int32_t* ndrop, size_t* bytes) {
   if (!bytes) return fail(LBM_E_INVAL, "bytes must not be NULL");

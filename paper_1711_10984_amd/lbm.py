@@ -31,10 +31,11 @@ EXPORTED = ["lbm_workspace_bytes", "lbm_init_batch", "lbm_init", "lbm_step", "lb
             "lbm_get_step", "lbm_fields", "lbm_observables", "lbm_droplets", "lbm_debug_stage",
             "lbm_time_kernels", "lbm_time_launches", "lbm_kernel_name", "lbm_set_path", "lbm_get_path", "lbm_set_seg_rows",
             "lbm_get_seg_rows", "lbm_set_strip_width", "lbm_get_strip_width", "lbm_tune_rows", "lbm_tune_widths",
-            "lbm_autotune", "lbm_adjoint_bytes", "lbm_adjoint_forward",
+            "lbm_autotune", "lbm_step_noalloc", "lbm_adjoint_bytes", "lbm_adjoint_forward",
             "lbm_adjoint_backward", "lbm_destroy", "lbm_last_error"]
 LBM_SEG_ROWS_MIN, LBM_SEG_ROWS_MAX, LBM_TUNE_NROWS = 16, 4096, 16
 LBM_STRIP_W_MIN, LBM_STRIP_W_MAX, LBM_TUNE_NWIDTHS = 32, 54, 1
+LBM_NOALLOC_SCRATCH_BYTES = 16 << 20
 PATH_NAMES = {LBM_PATH_FUSED: "fused", LBM_PATH_SPLIT: "split", LBM_PATH_WAVE: "wave"}
 
 
@@ -114,6 +115,8 @@ def load_library(path: Optional[str] = None):
     lib.lbm_tune_widths.argtypes = []
     lib.lbm_tune_widths.restype = C.POINTER(C.c_int32)
     lib.lbm_autotune.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
+    lib.lbm_step_noalloc.argtypes = [C.POINTER(lbm_config), vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int32,
+                                     vp, C.c_int64, C.c_int64]
     lib.lbm_adjoint_bytes.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
     lib.lbm_adjoint_forward.argtypes = [vp, vp, C.c_size_t, C.c_int32, C.c_int64, C.c_int32, dp]
     lib.lbm_adjoint_backward.argtypes = [vp, vp, C.c_size_t, dp, dp]
@@ -306,6 +309,16 @@ def lbm_autotune(ctx: int, launches: int, both_paths: bool = True):
     if ms[2 * nw * nr] >= 0:
         times["split"] = float(ms[2 * nw * nr])
     return int(rows.value), int(path.value), times
+
+
+def lbm_step_noalloc(cfg: lbm_config, stream_ptr: int, f_ptrs, phi_ptrs, c_ptrs, ndrop: int, drops_ptr: int,
+                     step: int, nsteps: int) -> int:
+    """The allocation-free step (device pointers in, nothing allocated); returns the error code (no raise), so
+    that callers and tests see LBM_E_INVAL / LBM_E_NOMEM directly."""
+    pair = lambda p: (C.c_void_p * 2)(C.c_void_p(p[0]), C.c_void_p(p[1]))
+    return int(load_library().lbm_step_noalloc(C.byref(cfg), C.c_void_p(stream_ptr), pair(f_ptrs), pair(phi_ptrs),
+                                               pair(c_ptrs), int(ndrop), C.c_void_p(drops_ptr), int(step),
+                                               int(nsteps)))
 
 
 def lbm_destroy(ctx: int) -> None:
