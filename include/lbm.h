@@ -50,9 +50,8 @@ extern "C" {
 #define LBM_FP64 0 /* populations, fields and arithmetic in FP64 */
 #define LBM_FP32 1 /* populations stored as FP32 deviations f_i - w_i n0 from the rest state, fields and
                       arithmetic in FP32; droplet sums in FP64 */
-#define LBM_FP16 2 /* populations stored as FP16 values of 2^12 (f_i - w_i n0), the deviation from the rest
-                      state scaled by an exact power of two (round to nearest even), widened to FP32 and
-                      scaled back on load; fields and arithmetic FP32; sums FP64 */
+#define LBM_FP16 2 /* populations stored as FP16 deviations f_i - w_i n0 from the rest state (round to
+                      nearest even), widened to FP32 on load; fields and arithmetic FP32; sums FP64 */
 
 /* Boundaries in y (Sec. 2.2 names bounding walls, Sec. 2.3 neutral wetting at them).  LBM_WALLS_Y:
  * solid plates halfway between node rows, at y = -1/2 and y = ny - 1/2, x periodic.  Populations that
@@ -231,10 +230,11 @@ int lbm_time_kernels(lbm_ctx* ctx, int64_t n, double* ms_out);
 /* Device time per launch (ms) of the timestep's main kernels, without the gaps that events or host launches
  * between kernels add: `launches` back-to-back launches of each kernel, captured in a hipGraph, replayed once to
  * warm up and once between two hipEvents on the context's stream (non-default; LBM_E_STATE otherwise), total
- * time / launches.  Fused path: ms_out = {k_step, 0}; wave path: {k_wave, 0}; split path: {k_lb, k_fd}.  Like the
- * autotuner's trials, the launches read the current state and write only scratch (the inactive halves of the
- * ping-pong buffers, the velocity planes and the centre-of-mass partials): the state, the droplet table and the
- * step counter are unchanged.  Synchronous. */
+ * time / launches.  Fused path: ms_out = {k_step, k_reduce, 0}; wave path: {k_wave, k_reduce, 0}; split path:
+ * {k_lb, k_fd, k_reduce}.  Like the autotuner's trials, the launches read the current state and write only
+ * scratch (the inactive halves of the ping-pong buffers, the velocity planes and the centre-of-mass partials;
+ * k_reduce runs in a mode that computes the droplet sums and writes nothing): the state, the droplet table and
+ * the step counter are unchanged.  Synchronous. */
 int lbm_time_launches(lbm_ctx* ctx, int32_t launches, double* ms_out);
 
 /* ---- For callers that cannot allocate ------------------------------------------------------------------
@@ -251,7 +251,7 @@ int lbm_time_launches(lbm_ctx* ctx, int32_t launches, double* ms_out);
  *   f[0], f[1]:   [9][ny][nx] post-collision populations stored at the emitting node, f*_i(r), so that the
  *                 pre-collision population is f_i(r) = f*_i(r - e_i) (with LBM_WALLS_Y, f*_OPP(i)(r) where r - e_i
  *                 lies behind a plate); LBM_FP64 stores doubles, LBM_FP32 the floats f*_i - (float)(w_i n0),
- *                 LBM_FP16 the _Float16 values of 2^12 ((float)f*_i - (float)(w_i n0));
+ *                 LBM_FP16 the _Float16 values of (float)f*_i - (float)(w_i n0);
  *   phi[0..1], c[0..1]: [ny][nx] doubles (LBM_FP64) or floats;
  *   drops:        device array of `ndrop` lbm_droplet, the current centres of mass r_CM (e.g. from
  *                 lbm_droplets), updated in place with the centres after the run.

@@ -327,8 +327,7 @@ decltype(auto) with_types(int prec, F&& f) {
 
 // Host side of the population storage (the kernels' lb_moments / lb_collide).  FP64 stores the population.
 // FP32 stores the deviation from the rest population, fp32(f - fp32(w_i n0)), read back as that deviation plus
-// fp32(w_i n0).  FP16 storage keeps fp16(2^12 (fp32(f) - fp32(w_i n0))), widened back as
-// fp32(stored) 2^-12 + fp32(w_i n0).
+// fp32(w_i n0).  FP16 storage keeps fp16(fp32(f) - fp32(w_i n0)), widened back as fp32(stored) + fp32(w_i n0).
 template <typename T, typename P>
 P host_pop_store(double f, double wn) {
   if constexpr (sizeof(T) == 8) {
@@ -337,7 +336,7 @@ P host_pop_store(double f, double wn) {
   } else if constexpr (std::is_same<T, P>::value) {
     return (P)(f - (double)(float)wn);
   } else {
-    return (P)(((float)f - (float)wn) * FP16_SCALE);
+    return (P)((float)f - (float)wn);
   }
 }
 template <typename T, typename P>
@@ -348,7 +347,7 @@ double host_pop_load(P s, double wn) {
   } else if constexpr (std::is_same<T, P>::value) {
     return (double)s + (double)(float)wn;
   } else {
-    return (double)((float)s * (1.0f / FP16_SCALE) + (float)wn);
+    return (double)((float)s + (float)wn);
   }
 }
 
@@ -1069,10 +1068,15 @@ int lbm_time_launches(lbm_ctx* c, int32_t launches, double* ms_out) {
   if (!c || !ms_out) return fail(LBM_E_INVAL, "null argument");
   if (launches <= 0) return fail(LBM_E_INVAL, "launches must be > 0");
   if (!c->stream) return fail(LBM_E_STATE, "timing launches in a graph needs a non-default stream");
-  ms_out[0] = ms_out[1] = 0.0;
+  ms_out[0] = ms_out[1] = ms_out[2] = 0.0;
   const bool split = c->path == LBM_PATH_SPLIT;
-  // kernel k of the path over the current state, writing scratch only
+  // kernel k of the path over the current state, writing scratch only; the last one is the centre-of-mass
+  // reduction in its mode that writes nothing
+  const int nk = split ? 3 : 2;
   auto one = [&](int k) -> hipError_t {
+    if (k == nk - 1)
+      return launch_reduce(c->stream, split ? TILING_SPLIT : TILING_FUSED, c->L.ndrop_total, c->d_inst(), c->d_drops(),
+                           c->d_part(), c->d_mask(), c->d_step(), -1);
     return with_types(c->L.prec, [&](auto t, auto p) -> hipError_t {
       using T = decltype(t);
       using P = decltype(p);
@@ -1087,7 +1091,7 @@ int lbm_time_launches(lbm_ctx* c, int32_t launches, double* ms_out) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   int rc = LBM_OK;
-  for (int k = 0; k < (split ? 2 : 1) && rc == LBM_OK; ++k) {
+  for (int k = 0; k < nk && rc == LBM_OK; ++k) {
     // the launches are replayed from a graph, as lbm_step replays the timestep, so that no host launch gap
     // separates them
     hipGraph_t g = nullptr;

@@ -183,8 +183,7 @@ __device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k,
     dn = T(0);
     nn = ((d[0] + (d[2] + d[4])) + (d[1] + d[3])) + ((d[5] + d[6]) + (d[7] + d[8]));
   } else {
-    // FP16 storage holds 2^12 d_i (exact scaling by a power of two)
-    for (int i = 0; i < 9; ++i) d[i] = sizeof(P) == 2 ? T(q[i]) * T(1.0f / FP16_SCALE) : T(q[i]);
+    for (int i = 0; i < 9; ++i) d[i] = T(q[i]);
     dn = ((d[0] + (d[2] + d[4])) + (d[1] + d[3])) + ((d[5] + d[6]) + (d[7] + d[8]));
     nn = k.n0 + dn;
   }
@@ -208,15 +207,12 @@ __device__ __forceinline__ void lb_moments(const P (&q)[9], const LbConst<T>& k,
 //   F_i    = 3 (1 - 1/(2 tau)) w_i h_i,   h_i = (e.F - u.F) + 3 (e.u)(e.F)
 //   d*_i   = d_i + omega (d_eq_i - d_i) + F_i
 // so that each moving direction costs nine operations, and u.u, u.F and the per-weight products are shared.
-// A deviation d* in the storage type.  FP16 storage keeps fp16(2^12 d*) of the FP32 value d* (the product is
-// exact): the empty asm makes d* opaque, so that the compiler cannot fuse the last FMA of d* with the conversion
-// into one mixed-precision instruction that rounds only once.
+// A deviation d* in the storage type.  FP16 storage keeps fp16(d*) of the FP32 value d*: the empty asm makes
+// d* opaque, so that the compiler cannot fuse the last FMA of d* with the conversion into one mixed-precision
+// instruction that rounds only once.
 template <typename P>
 __device__ __forceinline__ P store_dev(float ds) {
-  if constexpr (sizeof(P) == 2) {
-    asm("" : "+v"(ds));
-    return P(ds * FP16_SCALE);
-  }
+  if constexpr (sizeof(P) == 2) asm("" : "+v"(ds));
   return P(ds);
 }
 
@@ -732,7 +728,8 @@ __global__ __launch_bounds__(NTHREADS) void k_cm_partials(int parity, const Tile
 }
 
 // One workgroup per droplet: fixed-order sum of the tile partials of one tiling, new centre of mass
-// (Sec. 4), and the step counter.
+// (Sec. 4), and the step counter.  increment 1: new centres and step + 1; 0: new centres only (the first pass);
+// -1: computes the sums and writes nothing (timing).
 __global__ __launch_bounds__(NTHREADS) void k_reduce(int tiling, int ndrop_total, const InstDev* __restrict__ insts,
                                                      DropDev* __restrict__ drops,
                                                      const double* __restrict__ part,
@@ -740,7 +737,7 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(int tiling, int ndrop_total
                                                      int64_t* __restrict__ step, int increment) {
   __shared__ double red[NTHREADS / 64][3];
   const int g = blockIdx.x;
-  if (g == 0 && threadIdx.x == 0 && increment) *step = *step + 1;
+  if (g == 0 && threadIdx.x == 0 && increment > 0) *step = *step + 1;
   if (g >= ndrop_total) return;
   const DropDev d = drops[g];
   const InstDev& I = insts[d.inst];
@@ -769,7 +766,7 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(int tiling, int ndrop_total
       }
   }
   block_reduce3(a0, a1, a2, red);
-  if (threadIdx.x == 0 && a0 > 0.0) {
+  if (threadIdx.x == 0 && a0 > 0.0 && increment >= 0) {
     drops[g].x = wrapd(d.x + a1 / a0, (double)I.nx);
     drops[g].y = wrapd(d.y + a2 / a0, I.yper);
   }

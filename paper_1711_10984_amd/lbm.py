@@ -228,7 +228,7 @@ def lbm_time_kernels(ctx: int, n: int) -> np.ndarray:
 
 
 def lbm_time_launches(ctx: int, launches: int) -> np.ndarray:
-    out = np.zeros(2)
+    out = np.zeros(3)
     _check(load_library().lbm_time_launches(C.c_void_p(ctx), int(launches), _dptr(out)))
     return out
 
@@ -459,7 +459,7 @@ class Sim:
         """Device ms per launch of the current path's main kernels from back-to-back launches (state unchanged)."""
         ms = lbm_time_launches(self.ctx, launches)
         path = lbm_get_path(self.ctx)
-        names = ("k_lb", "k_fd") if path == LBM_PATH_SPLIT else (lbm_kernel_name(path, 0),)
+        names = [lbm_kernel_name(path, i) for i in range(3) if lbm_kernel_name(path, i)]
         return {k: float(ms[i]) for i, k in enumerate(names)}
 
     def adjoint_forward(self, drop: int, nsteps: int, every: int = 100) -> float:

@@ -1,10 +1,10 @@
 """FP16 population storage (LBM_FP16): populations kept as the FP16-rounded deviation f_i - w_i n0 from
-the rest state, scaled by 2^12, fields and arithmetic in FP32.
+the rest state, fields and arithmetic in FP32.
 
 * Storage semantics, exactly: from the rest state f_i = fp32(w_i n0) (deviation 0 in both) the FP32 and
   the FP16 runs compute the same post-collision deviations d*_i in FP32, so one step later phi and c agree
-  bit for bit, and every population of the FP16 run is fp16(2^12 d*_i), widened back as
-  fp32(fp16(2^12 d*_i)) 2^-12 + fp32(w_i n0) and pulled along e_i.  d*_i comes from the FP32 run's stage export (d*_i + w_i n0 in double);
+  bit for bit, and every population of the FP16 run is fp16(d*_i), widened back as fp32(fp16(d*_i)) +
+  fp32(w_i n0) and pulled along e_i.  d*_i comes from the FP32 run's stage export (d*_i + w_i n0 in double);
   the storage is emulated with numpy's IEEE float16/float32 arithmetic.  The export comes from a separate
   instantiation of the kernel; FP32 contracts multiply-adds only within a source expression, so it rounds as
   the stepping kernel does.
@@ -57,7 +57,7 @@ def test_storage_rounding_after_one_step_is_exact(path):
     for i, (ex, ey) in enumerate(E):
         dev = np.float32(st[f"fstar{i}"] - np.float64(wn[i]))  # exact: the export is fp32 d* + fp32 w n0
         assert np.array_equal(dev.astype(np.float64) + np.float64(wn[i]), st[f"fstar{i}"])
-        stored = (np.float32(np.float16(dev * np.float32(4096.0))) * np.float32(1.0 / 4096.0) + wn[i]).astype(np.float64)
+        stored = (np.float32(np.float16(dev)) + wn[i]).astype(np.float64)
         emulated[i] = np.roll(stored, (ey, ex), axis=(0, 1))  # pulled: f_i(r) = f*_i(r - e_i)
     assert np.array_equal(b["f"], emulated), int(np.count_nonzero(b["f"] != emulated))
     # the rounding is really there: FP16 differs from FP32 somewhere
