@@ -351,13 +351,20 @@ double host_pop_load(P s, double wn) {
   }
 }
 
+// Whether every instance is periodic in y with the printed advection (the wave kernel's specialised case).
+bool all_plain(const std::vector<InstDev>& inst) {
+  for (const InstDev& d : inst)
+    if (d.walls != LBM_WALLS_NONE || d.advection != LBM_ADV_PAPER) return false;
+  return true;
+}
+
 // The sweeping kernel of a strip path (LBM_PATH_FUSED or LBM_PATH_WAVE) over the strip list.
 template <typename T, typename P>
 hipError_t launch_sweep(lbm_ctx* c, int parity, double* dbg, int dbg_inst) {
   T* buf = reinterpret_cast<T*>(c->pool());
   if (c->path == LBM_PATH_WAVE)
     return launch_wave<T, P>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(),
-                          c->d_part(), c->d_mask(), c->d_step(), dbg, dbg_inst);
+                             c->d_part(), c->d_mask(), c->d_step(), dbg, dbg_inst, all_plain(c->L.inst));
   return launch_step<T, P>(c->stream, parity, c->nseglaunch(), c->d_segs(), c->d_inst(), buf, c->d_drops(),
                            c->d_part(), c->d_mask(), c->d_step(), dbg, dbg_inst);
 }
@@ -764,7 +771,8 @@ int lbm_step_noalloc(const lbm_config* cfg, void* stream, void* const f[2], void
     hipError_t e = with_types(cf.precision, [&](auto t, auto p) {
       using T = decltype(t);
       return launch_wave<T, decltype(p)>(st, parity, nslots, segs, di, reinterpret_cast<T*>(const_cast<char*>(base)), dd,
-                                         part, mask, dstep, nullptr, -1);
+                                         part, mask, dstep, nullptr, -1,
+                                         cf.walls == LBM_WALLS_NONE && cf.advection == LBM_ADV_PAPER);
     });
     if (e == hipSuccess) e = launch_reduce(st, TILING_FUSED, ndrop, di, dd, part, mask, dstep, 1);
     if (e != hipSuccess) return fail(LBM_E_HIP, std::string("timestep launch: ") + hipGetErrorString(e));

@@ -94,10 +94,12 @@ hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev
                        T* buf, const DropDev* drops, double* part, uint64_t* mask, const int64_t* step,
                        double* dbg, int dbg_inst);
 // Same step as launch_step, computed by one 64-lane wavefront per strip segment (no workgroup barriers).
+// plain: every instance is periodic in y (LBM_WALLS_NONE) and uses LBM_ADV_PAPER, which selects a kernel
+// specialised for that case (the general kernel gives the same results).
 template <typename T, typename P>
 hipError_t launch_wave(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst,
                        T* buf, const DropDev* drops, double* part, uint64_t* mask, const int64_t* step,
-                       double* dbg, int dbg_inst);
+                       double* dbg, int dbg_inst, bool plain);
 template <typename T, typename P>
 hipError_t launch_obs(hipStream_t s, int parity, int ntiles_launch, const TileDev* tiles,
                       const InstDev* inst, T* buf, const DropDev* drops, double* obs_part,

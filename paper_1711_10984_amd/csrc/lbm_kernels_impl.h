@@ -1461,10 +1461,15 @@ __device__ __forceinline__ T div9n(const Nbr<T>& c, const Nbr<T>& X, T D) {
 }
 
 
-template <typename T, typename P, bool DBG>
-// Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD; FP32
-// fits four (128 registers, a few bytes spilled) and FP16 storage three.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : sizeof(P) == 4 ? 4 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
+// PLAIN: every lattice of the launch is periodic in y and advects by the printed Eqs. (16)-(17), so the
+// plate mirrors and the flux form compile away.
+template <typename T, typename P, bool DBG, bool PLAIN>
+// Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD; FP16
+// storage takes three; FP32 fits four in the general kernel (128 registers, a few bytes spilled), while the
+// plain kernel, scheduled with more values live, would spill there and runs three.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8       ? 2
+                                                                    : sizeof(P) == 4 && !PLAIN ? 4
+                                                                                               : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
                                              const InstDev* __restrict__ insts, T* __restrict__ buf,
                                              const DropDev* __restrict__ drops, double* __restrict__ part,
                                              uint64_t* __restrict__ mask, const int64_t* __restrict__ step,
@@ -1583,7 +1588,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const T cw0 = coef * w0, cw1 = coef * w1, cw5 = coef * w5;
   const LbConst<T> lbk{w0, w1, w5, cw0, cw1, cw5, omega, wr0, wr1, wr5, T(I.n0)};
   const T Gamma = T(I.Gamma), D = T(I.D), gam = T(I.gamma), c0 = T(I.c0);
-  const int adv = I.advection;
+  const int adv = PLAIN ? 0 : I.advection;
 
   // Register windows.  In the iteration whose stage-0 row is q, stage s works on row q - s; the
   // digit in a window name is the row offset below q (P2 = phi^n of row q - 2, ...).
@@ -1607,7 +1612,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   // Addresses: a wave-uniform row pointer (scalar registers) plus a per-lane 32-bit column byte offset.
   const unsigned bx = (unsigned)gx * sizeof(T);
   const unsigned fx = (unsigned)gx * sizeof(P), fxm = (unsigned)gxm * sizeof(P), fxp = (unsigned)gxp * sizeof(P);
-  const int walls = I.walls;
+  const int walls = PLAIN ? 0 : I.walls;
   auto load_s0 = [&](Pref& p, int r) {
     const int64_t ro = (int64_t)row_of(r, ny, walls) * pitch;
     p.phi = ld_col(phi_in + ro, bx);
@@ -1950,14 +1955,21 @@ hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev
 template <typename T, typename P>
 hipError_t launch_wave(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst, T* buf,
                        const DropDev* drops, double* part, uint64_t* mask, const int64_t* step, double* dbg,
-                       int dbg_inst) {
+                       int dbg_inst, bool plain) {
   if (nseg_launch <= 0) return hipSuccess;
-  if (dbg)
-    hipLaunchKernelGGL((k_wave<T, P, true>), dim3(nseg_launch), dim3(64), 0, s, parity, segs, inst, buf, drops,
-                       part, mask, step, dbg, dbg_inst);
+  const dim3 g(nseg_launch), b(64);
+  if (dbg && plain)
+    hipLaunchKernelGGL((k_wave<T, P, true, true>), g, b, 0, s, parity, segs, inst, buf, drops, part, mask, step, dbg,
+                       dbg_inst);
+  else if (dbg)
+    hipLaunchKernelGGL((k_wave<T, P, true, false>), g, b, 0, s, parity, segs, inst, buf, drops, part, mask, step, dbg,
+                       dbg_inst);
+  else if (plain)
+    hipLaunchKernelGGL((k_wave<T, P, false, true>), g, b, 0, s, parity, segs, inst, buf, drops, part, mask, step,
+                       dbg, dbg_inst);
   else
-    hipLaunchKernelGGL((k_wave<T, P, false>), dim3(nseg_launch), dim3(64), 0, s, parity, segs, inst, buf, drops,
-                       part, mask, step, dbg, dbg_inst);
+    hipLaunchKernelGGL((k_wave<T, P, false, false>), g, b, 0, s, parity, segs, inst, buf, drops, part, mask, step,
+                       dbg, dbg_inst);
   return hipGetLastError();
 }
 
@@ -1976,6 +1988,6 @@ hipError_t launch_wave(hipStream_t s, int parity, int nseg_launch, const TileDev
   template hipError_t launch_step<T, P>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,        \
                                         const DropDev*, double*, uint64_t*, const int64_t*, double*, int); \
   template hipError_t launch_wave<T, P>(hipStream_t, int, int, const TileDev*, const InstDev*, T*,        \
-                                        const DropDev*, double*, uint64_t*, const int64_t*, double*, int);
+                                        const DropDev*, double*, uint64_t*, const int64_t*, double*, int, bool);
 
 }  // namespace lbm
