@@ -1613,13 +1613,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const unsigned bx = (unsigned)gx * sizeof(T);
   const unsigned fx = (unsigned)gx * sizeof(P), fxm = (unsigned)gxm * sizeof(P), fxp = (unsigned)gxp * sizeof(P);
   const int walls = PLAIN ? 0 : I.walls;
-  auto load_s0 = [&](Pref& p, int r) {
-    const int64_t ro = (int64_t)row_of(r, ny, walls) * pitch;
+  // the loads of stage-0 row r (stored row gy) and of the pulls into stage-2 row r (stored rows gym, gy, gyp
+  // for r - 1, r, r + 1)
+  auto load_s0_rows = [&](Pref& p, int gy) {
+    const int64_t ro = (int64_t)gy * pitch;
     p.phi = ld_col(phi_in + ro, bx);
     p.c = ld_col(c_in + ro, bx);
   };
-  auto load_s2 = [&](Pref& p, int r) {
-    const int gy = row_of(r, ny, walls), gym = row_of(r - 1, ny, walls), gyp = row_of(r + 1, ny, walls);
+  auto load_s2_rows = [&](Pref& p, int r, int gym, int gy, int gyp) {
     const int64_t r0 = (int64_t)gy * pitch, rm = (int64_t)gym * pitch, rp = (int64_t)gyp * pitch;
     // behind a plate: the node's own opposite population (halfway bounce-back)
     const bool bb0 = walls && r == 0, bbn = walls && r == ny - 1;
@@ -1633,6 +1634,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     p.f[7] = bbn ? ld_col(fin + 5 * plane + r0, fx) : ld_col(fin + 7 * plane + rp, fxp);
     p.f[8] = bbn ? ld_col(fin + 6 * plane + r0, fx) : ld_col(fin + 8 * plane + rp, fxm);
   };
+  auto load_s0 = [&](Pref& p, int r) { load_s0_rows(p, row_of(r, ny, walls)); };
+  auto load_s2 = [&](Pref& p, int r) {
+    load_s2_rows(p, r, row_of(r - 1, ny, walls), row_of(r, ny, walls), row_of(r + 1, ny, walls));
+  };
   // Set j serves the iterations it = j (mod PFD): stage-0 row y0 - 5 + it, stage-2 row y0 - 7 + it, whose
   // first valid row y0 - 3 comes at it = 4.
   for (int j = 0; j < PFD; ++j) {
@@ -1641,14 +1646,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   }
 
   const int nit = (yend - y0) + 10;
+  // PLAIN lattices are periodic in y: the stored rows of the coming loads advance by one per iteration and
+  // are tracked from one iteration to the next (stage-0 row q + PFD; row r + PFD - 1 of the stage-2 pulls).
+  int nr0 = wrap_idx(y0 - 5 + PFD, ny), nr2 = wrap_idx(y0 - 8 + PFD, ny);
+  auto next_row = [&](int g) { return g + 1 == ny ? 0 : g + 1; };
   // one sweep iteration; `pf` holds the stage-0 row q and the stage-2 row q - 2, and is refilled for
   // the rows PFD further on
   auto sweep = [&](int it, Pref& pf) {
     const int q = y0 - 5 + it;
+    int g0 = 0, g2m = 0, g2 = 0, g2p = 0;
+    if constexpr (PLAIN) {
+      g0 = nr0;
+      nr0 = next_row(nr0);
+      g2m = nr2;
+      g2 = next_row(g2m);
+      g2p = next_row(g2);
+      nr2 = g2;
+    }
     // ---- s0: phi^n, c^n of row q; prefetch row q + PFD
     P0 = pf.phi;
     C0 = pf.c;
-    if (q + PFD < yend + 5) load_s0(pf, q + PFD);
+    if (q + PFD < yend + 5) {
+      if constexpr (PLAIN)
+        load_s0_rows(pf, g0);
+      else
+        load_s0(pf, q + PFD);
+    }
     // ---- s1: mu_phi and X (Eqs. 3, 5) at row q - 1
     if (q - 1 >= y0 - 4 && q - 1 < yend + 4) {
       const Nbr<T> gp = nbr(P0, P1, P2), gc = nbr(C0, C1, C2);
@@ -1699,7 +1722,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + qq] = sv[i];
         }
       }
-      if (r + PFD < yend + 3) load_s2(pf, r + PFD);
+      if (r + PFD < yend + 3) {
+        if constexpr (PLAIN)
+          load_s2_rows(pf, r + PFD, g2m, g2, g2p);
+        else
+          load_s2(pf, r + PFD);
+      }
     }
     // ---- s3: advection half-step (Eqs. 16-17) at row q - 3
     if (q - 3 >= y0 - 2 && q - 3 < yend + 2) {
