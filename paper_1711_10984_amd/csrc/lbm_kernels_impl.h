@@ -1461,6 +1461,99 @@ __device__ __forceinline__ T div9n(const Nbr<T>& c, const Nbr<T>& X, T D) {
 }
 
 
+// The 9-point gradient and Laplacian of a 3 x 3 neighbourhood (rows up, mid, dn) as grad9n and lap9n compute
+// them, the same operations in the same order, from row terms: D = e - w and S = e + w of each row, the
+// vertical difference V = n - s and its neighbours' sum Y = V(east) + V(west), which equals
+// (ne - se) + (nw - sw) exactly (a lane shift commutes with a lane-wise difference).  In FP32 the shift
+// rides on the subtraction or addition itself (a DPP operand), so a row costs three instructions instead of
+// two moves and two operations; FP64 operations take no DPP operand and use the neighbourhood.
+__device__ __forceinline__ void rows_ds(float u, float m, float d, float (&D)[3], float (&S)[3]) {
+  int t[3], r[6];
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %9 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %1, %10 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %2, %11 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %3, %9, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %4, %9, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %5, %10, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %6, %10, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %7, %11, %2 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %8, %11, %2 wave_shl:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]),
+        "=&v"(r[5])
+      : "v"(__float_as_int(u)), "v"(__float_as_int(m)), "v"(__float_as_int(d)));
+  for (int i = 0; i < 3; ++i) {
+    D[i] = __int_as_float(r[2 * i]);
+    S[i] = __int_as_float(r[2 * i + 1]);
+  }
+}
+__device__ __forceinline__ void rows_d(float u, float m, float d, float (&D)[3]) {
+  int t[3], r[3];
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %6 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %1, %7 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %2, %8 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %3, %6, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %4, %7, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %5, %8, %2 wave_shl:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
+      : "v"(__float_as_int(u)), "v"(__float_as_int(m)), "v"(__float_as_int(d)));
+  for (int i = 0; i < 3; ++i) D[i] = __int_as_float(r[i]);
+}
+__device__ __forceinline__ void rows_s(float u, float m, float d, float (&S)[3]) {
+  int t[3], r[3];
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %6 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %1, %7 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_mov_b32_dpp %2, %8 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %3, %6, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %4, %7, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %5, %8, %2 wave_shl:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
+      : "v"(__float_as_int(u)), "v"(__float_as_int(m)), "v"(__float_as_int(d)));
+  for (int i = 0; i < 3; ++i) S[i] = __int_as_float(r[i]);
+}
+// v(east) + v(west)
+__device__ __forceinline__ float pair_sum(float v) {
+  int t, y;
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %2 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_add_f32_dpp %1, %2, %0 wave_shl:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(t), "=&v"(y)
+      : "v"(__float_as_int(v)));
+  return __int_as_float(y);
+}
+// gradient (as grad9n) and, with LAP, Laplacian (as lap9n) of the neighbourhood of rows up, mid, dn
+template <bool LAP, typename T>
+__device__ __forceinline__ void sten(T up, T mid, T dn, T& gx, T& gy, T& lap) {
+  if constexpr (sizeof(T) == 8) {
+    const Nbr<T> g = nbr(up, mid, dn);
+    grad9n(g, gx, gy);
+    if constexpr (LAP) lap = lap9n(g);
+  } else {
+    float D[3], S[3];
+    if constexpr (LAP)
+      rows_ds(up, mid, dn, D, S);
+    else
+      rows_d(up, mid, dn, D);
+    const float V = up - dn;
+    gx = (4.0f * D[1] + (D[0] + D[2])) * cst<float>(1.0 / 12.0);
+    gy = (4.0f * V + pair_sum(V)) * cst<float>(1.0 / 12.0);
+    if constexpr (LAP) lap = (4.0f * (S[1] + (up + dn)) + (S[0] + S[2]) - 20.0f * mid) * cst<float>(1.0 / 6.0);
+  }
+}
+// the Laplacian alone (as lap9n)
+template <typename T>
+__device__ __forceinline__ T sten_lap(T up, T mid, T dn) {
+  if constexpr (sizeof(T) == 8) {
+    return lap9n(nbr(up, mid, dn));
+  } else {
+    float S[3];
+    rows_s(up, mid, dn, S);
+    return (4.0f * (S[1] + (up + dn)) + (S[0] + S[2]) - 20.0f * mid) * cst<float>(1.0 / 6.0);
+  }
+}
+
 // PLAIN: every lattice of the launch is periodic in y and advects by the printed Eqs. (16)-(17), so the
 // plate mirrors and the flux form compile away.
 template <typename T, typename P, bool DBG, bool PLAIN>
@@ -1674,13 +1767,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     // ---- s1: mu_phi and X (Eqs. 3, 5) at row q - 1
     if (q - 1 >= y0 - 4 && q - 1 < yend + 4) {
-      const Nbr<T> gp = nbr(P0, P1, P2), gc = nbr(C0, C1, C2);
-      T gpx, gpy, gcx, gcy;
-      grad9n(gp, gpx, gpy);
-      grad9n(gc, gcx, gcy);
+      T gpx, gpy, gcx, gcy, lp, nolap;
+      sten<true>(P0, P1, P2, gpx, gpy, lp);
+      sten<false>(C0, C1, C2, gcx, gcy, nolap);
       GCX1 = gcx;
       GCY1 = gcy;
-      const T lp = lap9n(gp);
       const T ph = P1;
       const T B = B0 + B1 * C1;
       MU1 = ((a * ph + b * (ph * ph * ph)) - B * lp) - B1 * (gpx * gcx + gpy * gcy);
@@ -1694,10 +1785,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     // ---- s2: force, moments, collision at row q - 2
     if (q - 2 >= y0 - 3 && q - 2 < yend + 3) {
       const int r = q - 2;
-      const Nbr<T> gm = nbr(MU1, MU2, MU3), gX = nbr(X1, X2, X3);
-      T gmx, gmy, gXx, gXy;
-      grad9n(gm, gmx, gmy);
-      grad9n(gX, gXx, gXy);
+      T gmx, gmy, gXx, gXy, nolap;
+      sten<false>(MU1, MU2, MU3, gmx, gmy, nolap);
+      sten<false>(X1, X2, X3, gXx, gXy, nolap);
       const T gcx = GCX2, gcy = GCY2;
       const T ph = P2, cv = C2;
       const T Fx = (-(ph * gmx) - gcx) - cv * gXx;
@@ -1749,11 +1839,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     if (q - 4 >= y0 - 1 && q - 4 < yend + 1) {
       // half-step fields beyond a plate: the mirror image of the boundary row
       const bool top = walls && q - 4 == ny - 1, bot = walls && q - 4 == 0;
-      const Nbr<T> gph = nbr(top ? PH4 : PH3, PH4, bot ? PH4 : PH5), gch = nbr(top ? CH4 : CH3, CH4, bot ? CH4 : CH5);
-      T gphx, gphy, gchx, gchy;
-      grad9n(gph, gphx, gphy);
-      grad9n(gch, gchx, gchy);
-      const T lph = lap9n(gph);
+      T gphx, gphy, gchx, gchy, lph, nolap;
+      sten<true>(top ? PH4 : PH3, PH4, bot ? PH4 : PH5, gphx, gphy, lph);
+      sten<false>(top ? CH4 : CH3, CH4, bot ? CH4 : CH5, gchx, gchy, nolap);
       const T pn = P4;
       const T Bh = B0 + B1 * CH4;
       M4 = ((a * PH4 + b * (pn * pn * pn)) - Bh * lph) - B1 * (gchx * gphx + gchy * gphy);
@@ -1768,9 +1856,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     if (q - 5 >= y0) {
       const int r = q - 5;
       const bool top = walls && r == ny - 1, bot = walls && r == 0;
-      const Nbr<T> gM = nbr(top ? M5 : M4, M5, bot ? M5 : M6), gch = nbr(top ? CH5 : CH4, CH5, bot ? CH5 : CH6),
-                   gXh = nbr(top ? XH5 : XH4, XH5, bot ? XH5 : XH6);
-      const T phn = PH5 + Gamma * lap9n(gM);
+      const Nbr<T> gch = nbr(top ? CH5 : CH4, CH5, bot ? CH5 : CH6), gXh = nbr(top ? XH5 : XH4, XH5, bot ? XH5 : XH6);
+      const T phn = PH5 + Gamma * sten_lap(top ? M5 : M4, M5, bot ? M5 : M6);
       const T ch = CH5;
       const T lch = lap9n(gch);
       const T dv = div9n(gch, gXh, D);
