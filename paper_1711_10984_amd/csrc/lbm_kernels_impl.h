@@ -1513,6 +1513,73 @@ __device__ __forceinline__ void rows_s(float u, float m, float d, float (&S)[3])
       : "v"(__float_as_int(u)), "v"(__float_as_int(m)), "v"(__float_as_int(d)));
   for (int i = 0; i < 3; ++i) S[i] = __int_as_float(r[i]);
 }
+// D, S (with DS) of the rows u, m, d, and V = u - d with Y = V(east) + V(west), in one group: V is
+// written first, so the row operations in between cover the DPP read-after-write of V.
+template <bool DS>
+__device__ __forceinline__ void rows_dvy(float u, float m, float d, float (&D)[3], float (&S)[3], float& V,
+                                         float& Y) {
+  int t[4], r[6], v, y;
+  if constexpr (DS) {
+    asm("s_nop 1\n\t"
+        "v_sub_f32 %10, %12, %14\n\t"
+        "v_mov_b32_dpp %0, %12 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mov_b32_dpp %1, %13 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mov_b32_dpp %2, %14 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_sub_f32_dpp %4, %12, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %5, %12, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_sub_f32_dpp %6, %13, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %7, %13, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_sub_f32_dpp %8, %14, %2 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %9, %14, %2 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mov_b32_dpp %3, %10 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %11, %10, %3 wave_shl:1 row_mask:0xf bank_mask:0xf"
+        : "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(t[3]), "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]),
+          "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(v), "=&v"(y)
+        : "v"(__float_as_int(u)), "v"(__float_as_int(m)), "v"(__float_as_int(d)));
+    for (int i = 0; i < 3; ++i) {
+      D[i] = __int_as_float(r[2 * i]);
+      S[i] = __int_as_float(r[2 * i + 1]);
+    }
+  } else {
+    asm("s_nop 1\n\t"
+        "v_sub_f32 %7, %9, %11\n\t"
+        "v_mov_b32_dpp %0, %9 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mov_b32_dpp %1, %10 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mov_b32_dpp %2, %11 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_sub_f32_dpp %4, %9, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_sub_f32_dpp %5, %10, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_sub_f32_dpp %6, %11, %2 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_mov_b32_dpp %3, %7 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_add_f32_dpp %8, %7, %3 wave_shl:1 row_mask:0xf bank_mask:0xf"
+        : "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(t[3]), "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(v),
+          "=&v"(y)
+        : "v"(__float_as_int(u)), "v"(__float_as_int(m)), "v"(__float_as_int(d)));
+    for (int i = 0; i < 3; ++i) D[i] = __int_as_float(r[i]);
+  }
+  V = __int_as_float(v);
+  Y = __int_as_float(y);
+}
+// The x-differences of the printed advection half-step (Eqs. 16-17) for u, phi and c of one row: ue - uw, and
+// for g = phi, c the backward gc - gw and forward ge - gc differences (the upwind side picks one), with the
+// shifts on the subtractions.
+__device__ __forceinline__ void adv_dx(float u, float p, float c, float& du, float& pb, float& pf, float& cb,
+                                       float& cf) {
+  int t, r[5];
+  asm("s_nop 1\n\t"
+      "v_mov_b32_dpp %0, %6 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %1, %6, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_subrev_f32_dpp %2, %7, %7 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %3, %7, %7 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_subrev_f32_dpp %4, %8, %8 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_sub_f32_dpp %5, %8, %8 wave_shl:1 row_mask:0xf bank_mask:0xf"
+      : "=&v"(t), "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4])
+      : "v"(__float_as_int(u)), "v"(__float_as_int(p)), "v"(__float_as_int(c)));
+  du = __int_as_float(r[0]);
+  pb = __int_as_float(r[1]);
+  pf = __int_as_float(r[2]);
+  cb = __int_as_float(r[3]);
+  cf = __int_as_float(r[4]);
+}
 // v(east) + v(west)
 __device__ __forceinline__ float pair_sum(float v) {
   int t, y;
@@ -1531,14 +1598,10 @@ __device__ __forceinline__ void sten(T up, T mid, T dn, T& gx, T& gy, T& lap) {
     grad9n(g, gx, gy);
     if constexpr (LAP) lap = lap9n(g);
   } else {
-    float D[3], S[3];
-    if constexpr (LAP)
-      rows_ds(up, mid, dn, D, S);
-    else
-      rows_d(up, mid, dn, D);
-    const float V = up - dn;
+    float D[3], S[3], V, Y;
+    rows_dvy<LAP>(up, mid, dn, D, S, V, Y);
     gx = (4.0f * D[1] + (D[0] + D[2])) * cst<float>(1.0 / 12.0);
-    gy = (4.0f * V + pair_sum(V)) * cst<float>(1.0 / 12.0);
+    gy = (4.0f * V + Y) * cst<float>(1.0 / 12.0);
     if constexpr (LAP) lap = (4.0f * (S[1] + (up + dn)) + (S[0] + S[2]) - 20.0f * mid) * cst<float>(1.0 / 6.0);
   }
 }
@@ -1821,14 +1884,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     // ---- s3: advection half-step (Eqs. 16-17) at row q - 3
     if (q - 3 >= y0 - 2 && q - 3 < yend + 2) {
-      T ue, uw, pe, pw, ce, cw;
-      shift_ew(UX3, ue, uw);
-      shift_ew(P3, pe, pw);
-      shift_ew(C3, ce, cw);
-      // u^n beyond a plate is not computed: its mirror image with u_y reversed
-      const T vn = (walls && q - 3 == ny - 1) ? -UY3 : UY2, vs = (walls && q - 3 == 0) ? -UY3 : UY4;
-      PH3 = advect_n(P3, pe, pw, P2, P4, UX3, ue, uw, UY3, vn, vs, adv);
-      CH3 = advect_n(C3, ce, cw, C2, C4, UX3, ue, uw, UY3, vn, vs, adv);
+      if constexpr (PLAIN && sizeof(T) == 4) {
+        // advect_n's printed form with the x-differences from adv_dx (same operations, same order)
+        float du, pb, pfw, cb, cfw;
+        adv_dx(UX3, P3, C3, du, pb, pfw, cb, cfw);
+        const T uc = UX3, vc = UY3, vn = UY2, vs = UY4;
+        const T divu = T(0.5) * du + T(0.5) * (vn - vs);
+        const T dpx = uc > T(0) ? pb : pfw, dcx = uc > T(0) ? cb : cfw;
+        const T dpy = vc > T(0) ? P3 - P4 : P2 - P3, dcy = vc > T(0) ? C3 - C4 : C2 - C3;
+        PH3 = P3 - ((P3 * divu + uc * dpx) + vc * dpy);
+        CH3 = C3 - ((C3 * divu + uc * dcx) + vc * dcy);
+      } else {
+        T ue, uw, pe, pw, ce, cw;
+        shift_ew(UX3, ue, uw);
+        shift_ew(P3, pe, pw);
+        shift_ew(C3, ce, cw);
+        // u^n beyond a plate is not computed: its mirror image with u_y reversed
+        const T vn = (walls && q - 3 == ny - 1) ? -UY3 : UY2, vs = (walls && q - 3 == 0) ? -UY3 : UY4;
+        PH3 = advect_n(P3, pe, pw, P2, P4, UX3, ue, uw, UY3, vn, vs, adv);
+        CH3 = advect_n(C3, ce, cw, C2, C4, UX3, ue, uw, UY3, vn, vs, adv);
+      }
       if (DBG && own_col && q - 3 >= y0 && q - 3 < yend) {
         const int64_t qq = (int64_t)(q - 3) * nx + (x0 + col);
         dbg[7 * nplane + qq] = (double)PH3;
