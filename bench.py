@@ -8,10 +8,10 @@ launch sequence under hipGraph replay.
 
 Timing: W warm-up steps, then exactly K steps bracketed by torch.cuda.synchronize() and hipEvents recorded
 on the library's stream, replayed from hipGraphs of G steps (G the largest even divisor of K up to
---graph-steps).  MLUPS = lattice nodes x K / seconds / 1e6; the same K steps are then timed five more times
-and their median reported beside it.  The roofline figure of the dominant kernel uses its algorithmic bytes
-per launch (one read and one write of each value it must move) over its device time per launch, from
-back-to-back launches between two hipEvents on the library's stream (no events between launches).
+--graph-steps), once and then five more times; MLUPS = lattice nodes x K / seconds / 1e6 from the median of
+the five.  The roofline figure of the dominant kernel uses its algorithmic bytes per launch (one read and one
+write of each value it must move) over its device time per launch: back-to-back launches replayed from a
+graph between two hipEvents on the library's stream, divided by their number.
 """
 import argparse
 import hashlib
@@ -159,7 +159,8 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
         seg_rows = None
     strip_w = sim.strip_width if seg_rows is not None else None
     nodes = sum(w.nodes for w in workloads)
-    ms, wall, more = time_steps(sim, steps, warmup, repeats=5)
+    first_ms, wall, more = time_steps(sim, steps, warmup, repeats=5)
+    ms = sorted(more)[len(more) // 2]  # the median of five timings of exactly `steps` steps
     obs = sim.observables(0)
     # device time per launch of each kernel: back-to-back launches replayed from a graph (state unchanged)
     device_ms = sim.time_launches(prof_steps)
@@ -168,31 +169,26 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     mlups = nodes * steps / (ms * 1e-3) / 1e6
     dom = max((k for k in device_ms if k in VALUES_PER_NODE), key=lambda k: device_ms[k])
     alg_bytes = alg_bytes_per_node(dom, precision) * nodes
-    # A sweeping path runs one main kernel and the small reduction per step: the main kernel's time per launch
-    # in the timed region is the step time less the reduction's.  (Back-to-back trials of the main kernel read
-    # the same input every time, so they miss in the last-level cache where a step reads what the step before
-    # wrote: they run a few per cent slower.)  The split path's two kernels are taken from their trials.
-    if len(device_ms) == 2:
-        dom_ms, dom_from = ms / steps - device_ms["k_reduce"], ("timed steps less the reduction's graph-timed launches")
-    else:
-        dom_ms, dom_from = device_ms[dom], f"{prof_steps} back-to-back launches replayed from a graph"
+    # The dominant kernel's device time per launch: back-to-back launches replayed from a graph, divided by their
+    # number.  They read the same input every time, so where a step reads what the step before wrote (partly
+    # from the last-level cache) it runs up to a few per cent faster; the step time gives that bound
+    # (step_roofline).
+    dom_ms, dom_from = device_ms[dom], f"{prof_steps} back-to-back launches replayed from a graph"
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     step_bytes = alg_bytes_per_node("step", precision) * nodes
     step_gbs = step_bytes / (ms * 1e-3 / steps) / 1e9
     prec = PREC_NAMES[precision]
     traffic = measured_traffic(dom, label, prec, strip_w, seg_rows)
-    med = sorted(more)[len(more) // 2]
     return {
         "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
-        "median_of_5": {"ms_per_step": med / steps, "mlups": nodes * steps / (med * 1e-3) / 1e6,
-                        "ms_per_step_each": [m / steps for m in more]},
+        "median_of_5": {"ms_per_step": ms / steps, "mlups": mlups, "ms_per_step_each": [m / steps for m in more],
+                        "first_timing_ms_per_step": first_ms / steps},
         "graph": {"steps_per_graph": gsize, "graph_replayed_steps": steps - steps % gsize if gsize else 0},
         "kernel_ms": per_kernel, "device_ms_per_launch": device_ms, "seg_rows": seg_rows, "strip_width": strip_w,
         "autotune_ms": tune_ms, "path": PATH_NAMES[path],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": dom_ms, "avg_launch_from": dom_from,
-                     "trial_launch_ms": device_ms[dom]},
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": dom_ms, "avg_launch_from": dom_from},
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "sanity": {"mass": obs["mass"], "sum_phi": obs["sum_phi"], "min_B": obs["min_B"], "max_u": obs["max_u"],
