@@ -46,6 +46,11 @@ PATH_NAMES = {0: "fused", 1: "split", 2: "wave"}
 PATH_NUMBERS = {v: k for k, v in PATH_NAMES.items()}
 
 
+def note(msg: str) -> None:
+    """A progress line on stderr (the JSON line goes to stdout)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("lbm_kernels_impl.h", "lbm_kernels_f64.hip", "lbm_kernels_f32.hip", "lbm_kernels_f16.hip",
@@ -179,6 +184,7 @@ def measure(workloads, precision, steps, warmup, graph_steps, label, prof_steps,
     step_gbs = step_bytes / (ms * 1e-3 / steps) / 1e9
     prec = PREC_NAMES[precision]
     traffic = measured_traffic(dom, label, prec, strip_w, seg_rows)
+    note(f"{label} {prec}: {mlups:.0f} MLUPS, {PATH_NAMES[path]} kernel, height {seg_rows}")
     return {
         "mlups": mlups, "ms_per_step": ms / steps, "wall_s": wall, "nodes": nodes, "precision": prec,
         "median_of_5": {"ms_per_step": ms / steps, "mlups": mlups, "ms_per_step_each": [m / steps for m in more],
@@ -275,6 +281,8 @@ def lowp_accuracy(workloads, steps, log_every, graph_steps, kernel, low):
         out["per_lattice_max_cm_deviation_lu"] = per_lattice
         out["merging_in_fp64_run"] = merging
         out["max_cm_deviation_lu_non_merging"] = round(max(apart), 6) if apart else None
+    note(f"{PREC_NAMES[low]} accuracy over {steps} steps on {len(workloads)} lattice(s): "
+         f"{out['max_cm_deviation_lu']} lu")
     return out
 
 def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
@@ -295,6 +303,7 @@ def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
         t2 = time.perf_counter()
         sim.close()
         best_f, best_b = min(best_f, t1 - t0), min(best_b, t2 - t1)
+    note(f"reverse mode {PREC_NAMES[precision]}: backward {best_b / nsteps * 1e3:.3f} ms/step")
     return {"workload": f"{w.name}, {nsteps} steps, checkpoint every {every}", "nodes": w.nodes,
             "path": PATH_NAMES[path], "seg_rows": rows if path != 1 else None,
             "strip_width": width if path != 1 else None,
@@ -375,6 +384,7 @@ def cpu_baseline(w, budget_s, single_budget_s=8.0, factory="c5_emulsion"):
     the 32-lattice batch as independent single-threaded runs across the host's cores."""
     from paper_1711_10984_amd import workloads as W
     rate, steps, el, threads = oracle_rate(w, budget_s)
+    note(f"CPU oracle, {w.name}: {rate:.1f} MLUPS on {threads} threads")
     host = host_cpu()
     out = {"value": round(rate, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
            "sample": f"{w.name}: {steps} FP64 steps of the full {w.nx}x{w.ny} lattice in {el:.1f} s",
@@ -404,6 +414,7 @@ def cpu_baseline(w, budget_s, single_budget_s=8.0, factory="c5_emulsion"):
     except Exception as e:  # noqa: BLE001
         configs["c3_batch_32_lattices"] = {"error": str(e)[:200]}
     out["configs"] = configs
+    note("CPU oracle configurations done")
     return out
 
 
