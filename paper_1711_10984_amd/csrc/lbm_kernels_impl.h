@@ -1621,11 +1621,8 @@ __device__ __forceinline__ T sten_lap(T up, T mid, T dn) {
 // plate mirrors and the flux form compile away.
 template <typename T, typename P, bool DBG, bool PLAIN>
 // Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD; FP16
-// storage takes three; FP32 fits four in the general kernel (128 registers, a few bytes spilled), while the
-// plain kernel, scheduled with more values live, would spill there and runs three.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8       ? 2
-                                                                    : sizeof(P) == 4 && !PLAIN ? 4
-                                                                                               : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
+// storage takes three; FP32 (one prefetch set, scalar-base addresses) fits four.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : sizeof(P) == 4 ? 4 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
                                              const InstDev* __restrict__ insts, T* __restrict__ buf,
                                              const DropDev* __restrict__ drops, double* __restrict__ part,
                                              uint64_t* __restrict__ mask, const int64_t* __restrict__ step,
@@ -1767,8 +1764,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   };
   Pref pfs[PFD];
   // Addresses: a wave-uniform row pointer (scalar registers) plus a per-lane 32-bit column byte offset.
-  const unsigned bx = (unsigned)gx * sizeof(T);
-  const unsigned fx = (unsigned)gx * sizeof(P), fxm = (unsigned)gxm * sizeof(P), fxp = (unsigned)gxp * sizeof(P);
+  unsigned bx = (unsigned)gx * sizeof(T);
+  unsigned fx = (unsigned)gx * sizeof(P), fxm = (unsigned)gxm * sizeof(P), fxp = (unsigned)gxp * sizeof(P);
   const int walls = PLAIN ? 0 : I.walls;
   // the loads of stage-0 row r (stored row gy) and of the pulls into stage-2 row r (stored rows gym, gy, gyp
   // for r - 1, r, r + 1)
@@ -1811,6 +1808,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   // the rows PFD further on
   auto sweep = [&](int it, Pref& pf) {
     const int q = y0 - 5 + it;
+    // FP32: the column offsets pass an empty asm each iteration, so that the compiler cannot hoist a 64-bit
+    // per-lane address (row-independent base + offset) out of the loop and keeps the scalar-base form; this
+    // frees about 30 VGPRs, enough for four wavefronts per SIMD.  (FP64 and FP16 storage ran slower with it.)
+    if constexpr (sizeof(T) == 4 && sizeof(P) == 4) asm volatile("" : "+v"(bx), "+v"(fx), "+v"(fxm), "+v"(fxp));
     int g0 = 0, g2m = 0, g2 = 0, g2p = 0;
     if constexpr (PLAIN) {
       g0 = nr0;
