@@ -1467,39 +1467,7 @@ __device__ __forceinline__ T div9n(const Nbr<T>& c, const Nbr<T>& X, T D) {
 // (ne - se) + (nw - sw) exactly (a lane shift commutes with a lane-wise difference).  In FP32 the shift
 // rides on the subtraction or addition itself (a DPP operand), so a row costs three instructions instead of
 // two moves and two operations; FP64 operations take no DPP operand and use the neighbourhood.
-__device__ __forceinline__ void rows_ds(float u, float m, float d, float (&D)[3], float (&S)[3]) {
-  int t[3], r[6];
-  asm("s_nop 1\n\t"
-      "v_mov_b32_dpp %0, %9 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_mov_b32_dpp %1, %10 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_mov_b32_dpp %2, %11 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_sub_f32_dpp %3, %9, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_add_f32_dpp %4, %9, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_sub_f32_dpp %5, %10, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_add_f32_dpp %6, %10, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_sub_f32_dpp %7, %11, %2 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_add_f32_dpp %8, %11, %2 wave_shl:1 row_mask:0xf bank_mask:0xf"
-      : "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]),
-        "=&v"(r[5])
-      : "v"(__float_as_int(u)), "v"(__float_as_int(m)), "v"(__float_as_int(d)));
-  for (int i = 0; i < 3; ++i) {
-    D[i] = __int_as_float(r[2 * i]);
-    S[i] = __int_as_float(r[2 * i + 1]);
-  }
-}
-__device__ __forceinline__ void rows_d(float u, float m, float d, float (&D)[3]) {
-  int t[3], r[3];
-  asm("s_nop 1\n\t"
-      "v_mov_b32_dpp %0, %6 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_mov_b32_dpp %1, %7 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_mov_b32_dpp %2, %8 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_sub_f32_dpp %3, %6, %0 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_sub_f32_dpp %4, %7, %1 wave_shl:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_sub_f32_dpp %5, %8, %2 wave_shl:1 row_mask:0xf bank_mask:0xf"
-      : "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
-      : "v"(__float_as_int(u)), "v"(__float_as_int(m)), "v"(__float_as_int(d)));
-  for (int i = 0; i < 3; ++i) D[i] = __int_as_float(r[i]);
-}
+// S of the rows u, m, d (the Laplacian alone)
 __device__ __forceinline__ void rows_s(float u, float m, float d, float (&S)[3]) {
   int t[3], r[3];
   asm("s_nop 1\n\t"
@@ -1579,16 +1547,6 @@ __device__ __forceinline__ void adv_dx(float u, float p, float c, float& du, flo
   pf = __int_as_float(r[2]);
   cb = __int_as_float(r[3]);
   cf = __int_as_float(r[4]);
-}
-// v(east) + v(west)
-__device__ __forceinline__ float pair_sum(float v) {
-  int t, y;
-  asm("s_nop 1\n\t"
-      "v_mov_b32_dpp %0, %2 wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_add_f32_dpp %1, %2, %0 wave_shl:1 row_mask:0xf bank_mask:0xf"
-      : "=&v"(t), "=&v"(y)
-      : "v"(__float_as_int(v)));
-  return __int_as_float(y);
 }
 // gradient (as grad9n) and, with LAP, Laplacian (as lap9n) of the neighbourhood of rows up, mid, dn
 template <bool LAP, typename T>
