@@ -474,6 +474,7 @@ def main():
                            "fp32_4096": ([emulsion_4096()], lbm.LBM_FP32, "c5_4096"),
                            "fp16_4096": ([emulsion_4096()], lbm.LBM_FP16, "c5_4096")}[only]
         print(json.dumps({"sweep": label, "precision": PREC_NAMES[prec], "prof_steps": args.prof_steps,
+                          "kernel_source_hash": kernel_source_hash(),
                           "order": sweep_heights(wl, prec, args.prof_steps)}), flush=True)
         return
     if args.only in ("fp32", "fp16", "c3", "fp32_4096", "fp16_4096"):
