@@ -285,11 +285,12 @@ def lowp_accuracy(workloads, steps, log_every, graph_steps, kernel, low):
          f"{out['max_cm_deviation_lu']} lu")
     return out
 
-def adjoint_measure(precision, nsteps=2000, every=100, repeats=2):
-    """Reverse mode on the 256^2 single-active-droplet workload: wall time of the checkpointed forward pass and
-    of the backward sweep (both synchronous library calls), best of `repeats`, on the autotuned kernel path."""
+def adjoint_measure(precision, nsteps=2000, every=100, repeats=2, n=256):
+    """Reverse mode on the n^2 single-active-droplet workload (256^2 by default; the droplet scales with n): wall
+    time of the checkpointed forward pass and of the backward sweep (both synchronous library calls), best of
+    `repeats`, on the autotuned kernel path."""
     from paper_1711_10984_amd import lbm, workloads as W
-    w = W.c2_single_active()
+    w = W.c2_single_active(n=n)
     best_f, best_b = 1e300, 1e300
     for _ in range(repeats):
         sim = lbm.Sim([w.param_dict()], [w.phi0], [w.c0], [w.drop_dicts()], precision=precision, graph_steps=20)
@@ -433,7 +434,7 @@ def main():
     ap.add_argument("--strip-width", type=int, default=0,
                     help="sweeping-kernel strip width with --seg-rows (0: the library default)")
     ap.add_argument("--only", default=None,
-                    choices=["fp64", "fp32", "fp16", "c3", "fp32_4096", "fp16_4096", "adjoint"],
+                    choices=["fp64", "fp32", "fp16", "c3", "fp32_4096", "fp16_4096", "adjoint", "adjoint_1024"],
                     help="run one configuration (for profiling); the JSON line then reports that one")
     ap.add_argument("--sweep-heights", action="store_true",
                     help="with --only (default fp64): launch both sweeping kernels at every autotuner height, "
@@ -466,6 +467,10 @@ def main():
     c5 = W.c5_emulsion()
     if args.only == "adjoint":
         print(json.dumps({"only": "adjoint", "fp64": adjoint_measure(lbm.LBM_FP64, repeats=1)}), flush=True)
+        return
+    if args.only == "adjoint_1024":
+        print(json.dumps({"only": "adjoint_1024", "fp64": adjoint_measure(lbm.LBM_FP64, 200, 20, 1, n=1024)}),
+              flush=True)
         return
     if args.sweep_heights:
         only = args.only or "fp64"
@@ -569,7 +574,8 @@ def main():
                                                        lbm.LBM_FP16),
         }
     if not args.no_variants and args.only is None:
-        out["adjoint"] = {"fp64": adjoint_measure(lbm.LBM_FP64), "fp32": adjoint_measure(lbm.LBM_FP32)}
+        out["adjoint"] = {"fp64": adjoint_measure(lbm.LBM_FP64), "fp32": adjoint_measure(lbm.LBM_FP32),
+                          "fp64_1024": adjoint_measure(lbm.LBM_FP64, 200, 20, 1, n=1024)}
     if not args.no_cpu_baseline and args.only is None:
         out["cpu_baseline"] = cpu_baseline(c5, args.cpu_budget)
     print(json.dumps(out), flush=True)
