@@ -1576,10 +1576,10 @@ __device__ __forceinline__ T sten_lap(T up, T mid, T dn) {
 }
 
 // PLAIN: every lattice of the launch is periodic in y and advects by the printed Eqs. (16)-(17), so the
-// plate mirrors and the flux form compile away.
+// plate mirrors and the flux form compile away.  Occupancy targets: FP64 keeps its windows and two prefetch
+// sets in registers at two waves per SIMD; FP16 storage takes three; FP32 (one prefetch set, scalar-base
+// addresses) fits four.
 template <typename T, typename P, bool DBG, bool PLAIN>
-// Occupancy targets: FP64 keeps its windows and two prefetch sets in registers at two waves per SIMD; FP16
-// storage takes three; FP32 (one prefetch set, scalar-base addresses) fits four.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : sizeof(P) == 4 ? 4 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
                                              const InstDev* __restrict__ insts, T* __restrict__ buf,
                                              const DropDev* __restrict__ drops, double* __restrict__ part,
@@ -1713,8 +1713,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 
   // Prefetch sets: phi, c of a coming stage-0 row and the pulled populations of a coming stage-2 row,
   // PFD rows ahead.  With PFD = 2 the sweep is unrolled by two and the sets alternate, so that no
-  // register holding an outstanding load is ever copied.  Two sets in FP64 and with FP16 storage (whose
-  // registers allow them); FP32 keeps one, which measured faster on the short segments of small lattices.
+  // register holding an outstanding load is ever copied.  Two sets in FP64 and with FP16 storage; FP32 keeps
+  // one (two, at four waves per SIMD, were 1.4 % slower on the 2048^2 emulsion, 1-3 % faster on the batch of
+  // small lattices and at 4096^2).
   constexpr int PFD = sizeof(T) == 8 || sizeof(P) == 2 ? 2 : 1;
   struct Pref {
     T phi, c;
