@@ -22,9 +22,9 @@ struct AdjPlanes {
   const T *fb1, *pb1, *cb1;  // adjoint of f (9 planes), phi, c at n + 1
   T *fb, *pb, *cb;           // adjoint at n (outputs)
   // gradient planes of the forward fields
-  T *gpx, *gpy, *gcx, *gcy, *lp, *gphx, *gphy, *gchx, *gchy, *lph, *gmx, *gmy, *gXx, *gXy;
+  T *gpx, *gpy, *gcx, *gcy, *gphx, *gphy, *gchx, *gchy;
   // intermediate adjoints
-  T *Mb, *Xhb, *phb, *chb, *uxb, *uyb, *Fxb, *Fyb, *mub, *Xb;
+  T *Mb, *Xhb, *phb, *chb, *Fxb, *Fyb, *mub, *Xb;
 };
 
 struct AdjModel {
@@ -35,8 +35,8 @@ struct AdjModel {
 };
 
 // One backward step: the adjoint at n + 1 -> the adjoint at n.  Each block adds its partial sum of
-// sum_r cb1(r) * ramp * count_n(r) (the step's contribution to d/dA0) to part[block]; part holds
-// adj_blocks(nx * ny) running totals, zeroed before the first step.
+// sum_r cb1(r) * ramp * count_n(r) over its tile (the step's contribution to d/dA0) to part[tile]; part holds
+// adj_blocks(nx, ny) running totals, zeroed before the first step.
 template <typename T>
 hipError_t launch_adjoint_step(hipStream_t s, const AdjModel& m, const AdjFwd& f, const AdjPlanes<T>& p,
                                const DropDev* drops_n, int ndrop, double* part);
@@ -49,6 +49,11 @@ hipError_t launch_adjoint_seed(hipStream_t s, int pass, const AdjModel& m, const
                                const DropDev* drops_prev, int ndrop, int drop, double delta, double sw, T* fb,
                                T* pb, T* cb, double* part);
 
-inline int adj_blocks(int64_t nodes) { return (int)((nodes + 255) / 256); }
+// Blocks of the adjoint kernels: one per tile of ADJ_TILE_X x ADJ_TILE_Y nodes (at least one per 256 nodes,
+// which the seed kernel's one-dimensional blocks need).
+constexpr int ADJ_TILE_X = 64, ADJ_TILE_Y = 4;
+inline int adj_blocks(int nx, int ny) {
+  return ((nx + ADJ_TILE_X - 1) / ADJ_TILE_X) * ((ny + ADJ_TILE_Y - 1) / ADJ_TILE_Y);
+}
 
 }  // namespace lbm

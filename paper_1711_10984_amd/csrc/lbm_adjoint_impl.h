@@ -24,26 +24,91 @@
 namespace lbm {
 namespace {
 
-constexpr int ADJ_THREADS = 256;  // adj_blocks() in lbm_adjoint.h assumes this size
+// A block of the stepping kernels covers a tile of ADJ_TILE_X x ADJ_TILE_Y nodes, one wavefront per tile row.
+// The planes that a kernel reads across the 3 x 3 neighbourhood are first copied to LDS, the tile with a
+// one-node halo (ADJ_HN values per plane, at most two per thread), so that each value is loaded from memory
+// once per block instead of once per neighbour.
+constexpr int ADJ_THREADS = ADJ_TILE_X * ADJ_TILE_Y;
+constexpr int ADJ_HX = ADJ_TILE_X + 2, ADJ_HN = ADJ_HX * (ADJ_TILE_Y + 2);
+static_assert(ADJ_TILE_X == 64, "one wavefront per tile row");
+static_assert(ADJ_HN <= 2 * ADJ_THREADS, "two staged values per thread");
 
-// 3 x 3 neighbourhood of node (x, y) of a dense plane: periodic in x, and in y without walls.  With walls a
-// row beyond a plate is the mirror image of the boundary row (the forward's ghost rows), and odd(dy) is -1 for
-// such a row: a field that is odd under the mirror (u_y in the forward; the adjoint operand of a transposed
-// y-gradient, see below) changes sign there.
+// Workgroups are dealt to the eight XCDs in turn (workgroup b runs on XCD b mod 8), and each XCD has an L2 of
+// its own.  Relabelled so that each XCD takes one contiguous run of the lattice's tiles, a tile's rows above
+// and below are mostly read by blocks of the same XCD, from its L2.  A bijection of [0, gridDim.x).
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+// This thread's node (x, y) and frame index l, and the plane offsets of the (one or two) values it stages.
+// Frame row j + 1, column i + 1 holds node (x0 + i, y0 + j) of the tile at (x0, y0); the halo holds the
+// periodic neighbours in x, and in y the periodic neighbours or, with walls, the boundary rows that mirror the
+// rows beyond the plates (frame rows past the last lattice row that only nodes outside the lattice read are
+// clamped to it).
+struct Tile {
+  int x, y, l;
+  bool valid, two;
+  int so[2], sp[2];  // dense ([ny][nx]) and pitched offsets of the staged values
+};
+
+__device__ __forceinline__ Tile make_tile(const AdjModel& m, int pitch) {
+  const int nbx = (m.nx + ADJ_TILE_X - 1) / ADJ_TILE_X;
+  const int b = xcd_block();
+  const int by = b / nbx, bx = b - by * nbx;
+  const int x0 = bx * ADJ_TILE_X, y0 = by * ADJ_TILE_Y;
+  const int tx = threadIdx.x % ADJ_TILE_X, ty = threadIdx.x / ADJ_TILE_X;
+  Tile t;
+  t.x = x0 + tx;
+  t.y = y0 + ty;
+  t.l = (ty + 1) * ADJ_HX + tx + 1;
+  t.valid = t.x < m.nx && t.y < m.ny;
+  t.two = threadIdx.x + ADJ_THREADS < ADJ_HN;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int i = j == 0 || t.two ? threadIdx.x + j * ADJ_THREADS : threadIdx.x;
+    const int ly = i / ADJ_HX, lx = i - ly * ADJ_HX;
+    const int gx = (x0 + lx - 1 + m.nx) % m.nx;
+    int gy = y0 + ly - 1;
+    if (m.walls)
+      gy = gy < 0 ? 0 : gy >= m.ny ? m.ny - 1 : gy;
+    else
+      gy = (gy + m.ny) % m.ny;
+    t.so[j] = gy * m.nx + gx;
+    t.sp[j] = gy * pitch + gx;
+  }
+  return t;
+}
+
+// Copies a plane's values for the tile frame into s; src(dense offset, pitched offset) reads one value.
+template <typename T, class S>
+__device__ __forceinline__ void stage(T* s, const Tile& t, S src) {
+  s[threadIdx.x] = src(t.so[0], t.sp[0]);
+  if (t.two) s[threadIdx.x + ADJ_THREADS] = src(t.so[1], t.sp[1]);
+}
+
+// 3 x 3 neighbourhood of node (x, y): dense and pitched plane offsets, periodic in x, and in y without walls,
+// and s(dx, dy), the index in a staged frame.  With walls a row beyond a plate is the mirror image of the
+// boundary row (the forward's ghost rows), and odd(dy) is -1 for such a row: a field that is odd under the
+// mirror (u_y in the forward; the adjoint operand of a transposed y-gradient, see below) changes sign there.
 struct Nbh {
-  int x, y, nx;
+  int x, y, nx, l;
   int xs[3], ys[3];
   int sg[3];
   __device__ int d(int dx, int dy) const { return ys[dy + 1] * nx + xs[dx + 1]; }
   __device__ int p(int dx, int dy, int pitch) const { return ys[dy + 1] * pitch + xs[dx + 1]; }
+  __device__ int s(int dx, int dy) const { return l + dy * ADJ_HX + dx; }
   __device__ int odd(int dy) const { return sg[dy + 1]; }
 };
 
-__device__ __forceinline__ Nbh make_nbh(int idx, int nx, int ny, int walls) {
+__device__ __forceinline__ Nbh make_nbh(const Tile& t, const AdjModel& m) {
+  const int nx = m.nx, ny = m.ny, walls = m.walls;
   Nbh k;
   k.nx = nx;
-  k.y = idx / nx;
-  k.x = idx - k.y * nx;
+  k.y = t.y;
+  k.x = t.x;
+  k.l = t.l;
   k.xs[0] = k.x == 0 ? nx - 1 : k.x - 1;
   k.xs[1] = k.x;
   k.xs[2] = k.x == nx - 1 ? 0 : k.x + 1;
@@ -55,17 +120,6 @@ __device__ __forceinline__ Nbh make_nbh(int idx, int nx, int ny, int walls) {
   k.sg[1] = 1;
   k.sg[2] = walls && top ? -1 : 1;
   return k;
-}
-
-// Transposes of the 9-point operators with the mirror ghost rows of the walls.  On a periodic lattice
-// G9x^T = -G9x, G9y^T = -G9y and L9^T = L9.  With walls, the outputs at a boundary row also read the ghost row,
-// which is the boundary row itself, and there are no outputs beyond the plate.  Gathering at node j, both
-// effects together amount to evaluating the same periodic formula with the adjoint operand continued across
-// the plate by its mirror image: even for L9 and G9x (symmetric in y), odd for G9y (antisymmetric in y).
-template <typename T, class V>
-__device__ __forceinline__ T G9y_T(const Nbh& k, V v) {
-  auto w = [&](int dx, int dy) { return T(k.odd(dy)) * v(dx, dy); };
-  return G9y<T>(w);
 }
 
 // 9-point stencils of a value function v(dx, dy), grouped as in the forward kernels.
@@ -82,6 +136,17 @@ __device__ __forceinline__ T L9(V v) {
   return (T(4) * ((v(1, 0) + v(-1, 0)) + (v(0, 1) + v(0, -1))) + ((v(1, 1) + v(-1, 1)) + (v(1, -1) + v(-1, -1))) -
           T(20) * v(0, 0)) *
          cst<T>(1.0 / 6.0);
+}
+
+// Transposes of the 9-point operators with the mirror ghost rows of the walls.  On a periodic lattice
+// G9x^T = -G9x, G9y^T = -G9y and L9^T = L9.  With walls, the outputs at a boundary row also read the ghost row,
+// which is the boundary row itself, and there are no outputs beyond the plate.  Gathering at node j, both
+// effects together amount to evaluating the same periodic formula with the adjoint operand continued across
+// the plate by its mirror image: even for L9 and G9x (symmetric in y), odd for G9y (antisymmetric in y).
+template <typename T, class V>
+__device__ __forceinline__ T G9y_T(const Nbh& k, V v) {
+  auto w = [&](int dx, int dy) { return T(k.odd(dy)) * v(dx, dy); };
+  return G9y<T>(w);
 }
 
 // Number of active production disks containing node (x, y) (the forward's source count at step n).
@@ -101,39 +166,40 @@ template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj1(AdjModel m, AdjFwd f, AdjPlanes<T> p, const DropDev* drops,
                                                       int ndrop, double* part) {
   __shared__ double red[ADJ_THREADS / 64];
-  const int N = m.nx * m.ny;
-  const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
+  __shared__ T s_phi[ADJ_HN], s_c[ADJ_HN], s_ph[ADJ_HN], s_ch[ADJ_HN], s_pb1[ADJ_HN], s_cb1[ADJ_HN], s_Xh[ADJ_HN];
+  const Tile t = make_tile(m, p.pitch);
+  stage(s_phi, t, [&](int, int q) { return p.phi[q]; });
+  stage(s_c, t, [&](int, int q) { return p.c[q]; });
+  stage(s_ph, t, [&](int o, int) { return T(f.ph[o]); });
+  stage(s_ch, t, [&](int o, int) { return T(f.ch[o]); });
+  stage(s_pb1, t, [&](int o, int) { return p.pb1[o]; });
+  stage(s_cb1, t, [&](int o, int) { return p.cb1[o]; });
+  stage(s_Xh, t, [&](int o, int) { return T(f.Xh[o]); });
+  __syncthreads();
   double src = 0.0;
-  if (idx < N) {
-    const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
-    const int pitch = p.pitch;
-    auto phi = [&](int dx, int dy) { return p.phi[k.p(dx, dy, pitch)]; };
-    auto cc = [&](int dx, int dy) { return p.c[k.p(dx, dy, pitch)]; };
-    auto ph = [&](int dx, int dy) { return T(f.ph[k.d(dx, dy)]); };
-    auto ch = [&](int dx, int dy) { return T(f.ch[k.d(dx, dy)]); };
-    auto mu = [&](int dx, int dy) { return T(f.mu[k.d(dx, dy)]); };
-    auto X = [&](int dx, int dy) { return T(f.X[k.d(dx, dy)]); };
-    // gradient planes of the forward fields (used by the later launches at neighbouring nodes)
+  if (t.valid) {
+    const Nbh k = make_nbh(t, m);
+    const int idx = t.y * m.nx + t.x;
+    auto phi = [&](int dx, int dy) { return s_phi[k.s(dx, dy)]; };
+    auto cc = [&](int dx, int dy) { return s_c[k.s(dx, dy)]; };
+    auto ph = [&](int dx, int dy) { return s_ph[k.s(dx, dy)]; };
+    auto ch = [&](int dx, int dy) { return s_ch[k.s(dx, dy)]; };
+    // gradient planes of the forward fields that the later launches read at neighbouring nodes (those needed
+    // only at the node itself are formed where they are used)
     p.gpx[idx] = G9x<T>(phi);
     p.gpy[idx] = G9y<T>(phi);
     p.gcx[idx] = G9x<T>(cc);
     p.gcy[idx] = G9y<T>(cc);
-    p.lp[idx] = L9<T>(phi);
     p.gphx[idx] = G9x<T>(ph);
     p.gphy[idx] = G9y<T>(ph);
     p.gchx[idx] = G9x<T>(ch);
     p.gchy[idx] = G9y<T>(ch);
-    p.lph[idx] = L9<T>(ph);
-    p.gmx[idx] = G9x<T>(mu);
-    p.gmy[idx] = G9y<T>(mu);
-    p.gXx[idx] = G9x<T>(X);
-    p.gXy[idx] = G9y<T>(X);
 
     const T D = T(m.D), a = T(m.a);
-    auto pb1 = [&](int dx, int dy) { return p.pb1[k.d(dx, dy)]; };
-    auto cb1 = [&](int dx, int dy) { return p.cb1[k.d(dx, dy)]; };
-    auto Xh = [&](int dx, int dy) { return T(f.Xh[k.d(dx, dy)]); };
-    auto kD = [&](int dx, int dy) { return D * T(f.ch[k.d(dx, dy)]); };
+    auto pb1 = [&](int dx, int dy) { return s_pb1[k.s(dx, dy)]; };
+    auto cb1 = [&](int dx, int dy) { return s_cb1[k.s(dx, dy)]; };
+    auto Xh = [&](int dx, int dy) { return s_Xh[k.s(dx, dy)]; };
+    auto kD = [&](int dx, int dy) { return D * ch(dx, dy); };
     // phi^{n+1} = phi^{n+1/2} + Gamma lap9(M)  ->  M_bar = Gamma lap9(phi_bar')
     const T Mb = T(m.Gamma) * L9<T>(pb1);
     p.Mb[idx] = Mb;
@@ -174,43 +240,64 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj1(AdjModel m, AdjFwd f, AdjP
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < ADJ_THREADS / 64; ++w) s += red[w];
-    part[blockIdx.x] += s;
+    part[xcd_block()] += s;
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj2(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
-  const int N = m.nx * m.ny;
-  const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
-  if (idx >= N) return;
-  const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
+  __shared__ T s_Mb[ADJ_HN], s_ch[ADJ_HN], s_ph[ADJ_HN], s_Xhb[ADJ_HN];
+  __shared__ T s_gchx[ADJ_HN], s_gchy[ADJ_HN], s_gphx[ADJ_HN], s_gphy[ADJ_HN];
+  const Tile t = make_tile(m, p.pitch);
+  stage(s_Mb, t, [&](int o, int) { return p.Mb[o]; });
+  stage(s_ch, t, [&](int o, int) { return T(f.ch[o]); });
+  stage(s_ph, t, [&](int o, int) { return T(f.ph[o]); });
+  stage(s_Xhb, t, [&](int o, int) { return p.Xhb[o]; });
+  stage(s_gchx, t, [&](int o, int) { return p.gchx[o]; });
+  stage(s_gchy, t, [&](int o, int) { return p.gchy[o]; });
+  stage(s_gphx, t, [&](int o, int) { return p.gphx[o]; });
+  stage(s_gphy, t, [&](int o, int) { return p.gphy[o]; });
+  __syncthreads();
+  if (!t.valid) return;
+  const Nbh k = make_nbh(t, m);
+  const int idx = t.y * m.nx + t.x;
   const T B0 = T(m.B0), B1 = T(m.B1), b = T(m.b);
-  auto BM = [&](int dx, int dy) { const int q = k.d(dx, dy); return (B0 + B1 * T(f.ch[q])) * p.Mb[q]; };
-  auto gchxM = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gchx[q] * p.Mb[q]; };
-  auto gchyM = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gchy[q] * p.Mb[q]; };
-  auto gphxX = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gphx[q] * p.Xhb[q]; };
-  auto gphyX = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gphy[q] * p.Xhb[q]; };
-  auto gphxM = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gphx[q] * p.Mb[q]; };
-  auto gphyM = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gphy[q] * p.Mb[q]; };
+  auto ph = [&](int dx, int dy) { return s_ph[k.s(dx, dy)]; };
+  auto BM = [&](int dx, int dy) { const int q = k.s(dx, dy); return (B0 + B1 * s_ch[q]) * s_Mb[q]; };
+  auto gchxM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gchx[q] * s_Mb[q]; };
+  auto gchyM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gchy[q] * s_Mb[q]; };
+  auto gphxX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphx[q] * s_Xhb[q]; };
+  auto gphyX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphy[q] * s_Xhb[q]; };
+  auto gphxM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphx[q] * s_Mb[q]; };
+  auto gphyM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphy[q] * s_Mb[q]; };
   // M = a phi^{1/2} + b (phi^n)^3 - B(c^{1/2}) lap9(phi^{1/2}) - B1 grad9 c^{1/2} . grad9 phi^{1/2};
   // X^{1/2} = (B1/2) |grad9 phi^{1/2}|^2
   p.phb[idx] = ((p.phb[idx] - L9<T>(BM)) + B1 * (G9x<T>(gchxM) + G9y_T<T>(k, gchyM))) -
                B1 * (G9x<T>(gphxX) + G9y_T<T>(k, gphyX));
-  p.chb[idx] = (p.chb[idx] - B1 * p.lph[idx] * p.Mb[idx]) + B1 * (G9x<T>(gphxM) + G9y_T<T>(k, gphyM));
+  const T Mb0 = s_Mb[k.l];
+  p.chb[idx] = (p.chb[idx] - B1 * L9<T>(ph) * Mb0) + B1 * (G9x<T>(gphxM) + G9y_T<T>(k, gphyM));
   const T ph0 = p.phi[k.p(0, 0, p.pitch)];
-  p.pb[idx] = T(3) * b * (ph0 * ph0) * p.Mb[idx];
+  p.pb[idx] = T(3) * b * (ph0 * ph0) * Mb0;
 }
 
 template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
+  __shared__ T s_ux[ADJ_HN], s_uy[ADJ_HN], s_g[2][ADJ_HN], s_o[2][ADJ_HN];
+  const Tile t = make_tile(m, p.pitch);
+  stage(s_ux, t, [&](int o, int) { return T(f.ux[o]); });
+  stage(s_uy, t, [&](int o, int) { return T(f.uy[o]); });
+  stage(s_g[0], t, [&](int, int q) { return p.phi[q]; });
+  stage(s_g[1], t, [&](int, int q) { return p.c[q]; });
+  stage(s_o[0], t, [&](int o, int) { return p.phb[o]; });
+  stage(s_o[1], t, [&](int o, int) { return p.chb[o]; });
+  __syncthreads();
+  if (!t.valid) return;
   const int N = m.nx * m.ny;
-  const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
-  if (idx >= N) return;
-  const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
-  const int pitch = p.pitch;
-  auto ux = [&](int dx, int dy) { return T(f.ux[k.d(dx, dy)]); };
+  const Nbh k = make_nbh(t, m);
+  const int idx = t.y * m.nx + t.x;
+  auto ux = [&](int dx, int dy) { return s_ux[k.s(dx, dy)]; };
   // beyond a plate the forward's advection stencil sees u_y reversed
-  auto uy = [&](int dx, int dy) { return T(k.odd(dy)) * T(f.uy[k.d(dx, dy)]); };
+  auto uy = [&](int dx, int dy) { return T(k.odd(dy)) * s_uy[k.s(dx, dy)]; };
   // With walls the gathered formula below holds as written once ob, g and u_x are continued across a plate by
   // their mirror images and u_y by its negative mirror image (the outputs at a boundary row read the ghost row,
   // and no outputs lie beyond the plate).
@@ -218,11 +305,10 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjP
   // (uy(N) - uy(S))/2, dgx = g - g(W) if ux > 0 else g(E) - g (same in y); gathered at node q.
   T uxb = T(0), uyb = T(0);
   T gb[2];
+#pragma unroll
   for (int which = 0; which < 2; ++which) {
-    const T* g = which == 0 ? p.phi : p.c;
-    const T* ob = which == 0 ? p.phb : p.chb;
-    auto G = [&](int dx, int dy) { return g[k.p(dx, dy, pitch)]; };
-    auto O = [&](int dx, int dy) { return ob[k.d(dx, dy)]; };
+    auto G = [&](int dx, int dy) { return s_g[which][k.s(dx, dy)]; };
+    auto O = [&](int dx, int dy) { return s_o[which][k.s(dx, dy)]; };
     const T u0 = ux(0, 0), v0 = uy(0, 0), g0 = G(0, 0), o0 = O(0, 0);
     const T divu = T(0.5) * (ux(1, 0) - ux(-1, 0)) + T(0.5) * (uy(0, 1) - uy(0, -1));
     const T sx = u0 > T(0) ? T(1) : T(-1), sy = v0 > T(0) ? T(1) : T(-1);
@@ -284,46 +370,66 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjP
 }
 
 template <typename T>
-__global__ __launch_bounds__(ADJ_THREADS) void k_adj4(AdjModel m, AdjPlanes<T> p) {
-  const int N = m.nx * m.ny;
-  const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
-  if (idx >= N) return;
-  const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
-  const int pitch = p.pitch;
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj4(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
+  __shared__ T s_Fxb[ADJ_HN], s_Fyb[ADJ_HN], s_phi[ADJ_HN], s_c[ADJ_HN], s_mu[ADJ_HN], s_X[ADJ_HN];
+  const Tile t = make_tile(m, p.pitch);
+  stage(s_Fxb, t, [&](int o, int) { return p.Fxb[o]; });
+  stage(s_Fyb, t, [&](int o, int) { return p.Fyb[o]; });
+  stage(s_phi, t, [&](int, int q) { return p.phi[q]; });
+  stage(s_c, t, [&](int, int q) { return p.c[q]; });
+  stage(s_mu, t, [&](int o, int) { return T(f.mu[o]); });
+  stage(s_X, t, [&](int o, int) { return T(f.X[o]); });
+  __syncthreads();
+  if (!t.valid) return;
+  const Nbh k = make_nbh(t, m);
+  const int idx = t.y * m.nx + t.x;
   // F = -phi grad9 mu - grad9 c - c grad9 X (Eq. 14)
-  auto Fxb = [&](int dx, int dy) { return p.Fxb[k.d(dx, dy)]; };
-  auto Fyb = [&](int dx, int dy) { return p.Fyb[k.d(dx, dy)]; };
-  auto phFx = [&](int dx, int dy) { return p.phi[k.p(dx, dy, pitch)] * p.Fxb[k.d(dx, dy)]; };
-  auto phFy = [&](int dx, int dy) { return p.phi[k.p(dx, dy, pitch)] * p.Fyb[k.d(dx, dy)]; };
-  auto cFx = [&](int dx, int dy) { return p.c[k.p(dx, dy, pitch)] * p.Fxb[k.d(dx, dy)]; };
-  auto cFy = [&](int dx, int dy) { return p.c[k.p(dx, dy, pitch)] * p.Fyb[k.d(dx, dy)]; };
-  const T fx = p.Fxb[idx], fy = p.Fyb[idx];
-  p.pb[idx] -= fx * p.gmx[idx] + fy * p.gmy[idx];
-  p.cb[idx] += (G9x<T>(Fxb) + G9y_T<T>(k, Fyb)) - (fx * p.gXx[idx] + fy * p.gXy[idx]);
+  auto Fxb = [&](int dx, int dy) { return s_Fxb[k.s(dx, dy)]; };
+  auto Fyb = [&](int dx, int dy) { return s_Fyb[k.s(dx, dy)]; };
+  auto phFx = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_phi[q] * s_Fxb[q]; };
+  auto phFy = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_phi[q] * s_Fyb[q]; };
+  auto cFx = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_c[q] * s_Fxb[q]; };
+  auto cFy = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_c[q] * s_Fyb[q]; };
+  auto mu = [&](int dx, int dy) { return s_mu[k.s(dx, dy)]; };
+  auto X = [&](int dx, int dy) { return s_X[k.s(dx, dy)]; };
+  const T fx = Fxb(0, 0), fy = Fyb(0, 0);
+  p.pb[idx] -= fx * G9x<T>(mu) + fy * G9y<T>(mu);
+  p.cb[idx] += (G9x<T>(Fxb) + G9y_T<T>(k, Fyb)) - (fx * G9x<T>(X) + fy * G9y<T>(X));
   p.mub[idx] = G9x<T>(phFx) + G9y_T<T>(k, phFy);
   p.Xb[idx] = G9x<T>(cFx) + G9y_T<T>(k, cFy);
 }
 
 template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj5(AdjModel m, AdjPlanes<T> p) {
-  const int N = m.nx * m.ny;
-  const int idx = blockIdx.x * ADJ_THREADS + threadIdx.x;
-  if (idx >= N) return;
-  const Nbh k = make_nbh(idx, m.nx, m.ny, m.walls);
-  const int pitch = p.pitch;
+  __shared__ T s_c[ADJ_HN], s_phi[ADJ_HN], s_mub[ADJ_HN], s_Xb[ADJ_HN];
+  __shared__ T s_gcx[ADJ_HN], s_gcy[ADJ_HN], s_gpx[ADJ_HN], s_gpy[ADJ_HN];
+  const Tile t = make_tile(m, p.pitch);
+  stage(s_c, t, [&](int, int q) { return p.c[q]; });
+  stage(s_phi, t, [&](int, int q) { return p.phi[q]; });
+  stage(s_mub, t, [&](int o, int) { return p.mub[o]; });
+  stage(s_Xb, t, [&](int o, int) { return p.Xb[o]; });
+  stage(s_gcx, t, [&](int o, int) { return p.gcx[o]; });
+  stage(s_gcy, t, [&](int o, int) { return p.gcy[o]; });
+  stage(s_gpx, t, [&](int o, int) { return p.gpx[o]; });
+  stage(s_gpy, t, [&](int o, int) { return p.gpy[o]; });
+  __syncthreads();
+  if (!t.valid) return;
+  const Nbh k = make_nbh(t, m);
+  const int idx = t.y * m.nx + t.x;
   const T a = T(m.a), b = T(m.b), B0 = T(m.B0), B1 = T(m.B1);
   // mu = a phi + b phi^3 - B(c) lap9 phi - B1 grad9 phi . grad9 c;  X = (B1/2) |grad9 phi|^2 (Eqs. 3, 5)
-  auto BMu = [&](int dx, int dy) { return (B0 + B1 * p.c[k.p(dx, dy, pitch)]) * p.mub[k.d(dx, dy)]; };
-  auto gcxMu = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gcx[q] * p.mub[q]; };
-  auto gcyMu = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gcy[q] * p.mub[q]; };
-  auto gpxMu = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gpx[q] * p.mub[q]; };
-  auto gpyMu = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gpy[q] * p.mub[q]; };
-  auto gpxX = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gpx[q] * p.Xb[q]; };
-  auto gpyX = [&](int dx, int dy) { const int q = k.d(dx, dy); return p.gpy[q] * p.Xb[q]; };
-  const T ph = p.phi[k.p(0, 0, pitch)], mb = p.mub[idx];
+  auto BMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return (B0 + B1 * s_c[q]) * s_mub[q]; };
+  auto gcxMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gcx[q] * s_mub[q]; };
+  auto gcyMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gcy[q] * s_mub[q]; };
+  auto gpxMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gpx[q] * s_mub[q]; };
+  auto gpyMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gpy[q] * s_mub[q]; };
+  auto gpxX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gpx[q] * s_Xb[q]; };
+  auto gpyX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gpy[q] * s_Xb[q]; };
+  auto phi = [&](int dx, int dy) { return s_phi[k.s(dx, dy)]; };
+  const T ph = phi(0, 0), mb = s_mub[k.l];
   p.pb[idx] += (((a + T(3) * b * (ph * ph)) * mb - L9<T>(BMu)) + B1 * (G9x<T>(gcxMu) + G9y_T<T>(k, gcyMu))) -
                B1 * (G9x<T>(gpxX) + G9y_T<T>(k, gpyX));
-  p.cb[idx] += B1 * (G9x<T>(gpxMu) + G9y_T<T>(k, gpyMu)) - B1 * p.lp[idx] * mb;
+  p.cb[idx] += B1 * (G9x<T>(gpxMu) + G9y_T<T>(k, gpyMu)) - B1 * L9<T>(phi) * mb;
 }
 
 template <typename T>
@@ -377,11 +483,11 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj_seed(int pass, AdjModel m, 
 template <typename T>
 hipError_t launch_adjoint_step(hipStream_t s, const AdjModel& m, const AdjFwd& f, const AdjPlanes<T>& p,
                                const DropDev* drops_n, int ndrop, double* part) {
-  const int nb = adj_blocks((int64_t)m.nx * m.ny);
+  const int nb = adj_blocks(m.nx, m.ny);
   hipLaunchKernelGGL((k_adj1<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p, drops_n, ndrop, part);
   hipLaunchKernelGGL((k_adj2<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
   hipLaunchKernelGGL((k_adj3<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
-  hipLaunchKernelGGL((k_adj4<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, p);
+  hipLaunchKernelGGL((k_adj4<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
   hipLaunchKernelGGL((k_adj5<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, p);
   return hipGetLastError();
 }
@@ -390,7 +496,7 @@ template <typename T>
 hipError_t launch_adjoint_seed(hipStream_t s, int pass, const AdjModel& m, const T* phi, int pitch,
                                const DropDev* drops_prev, int ndrop, int drop, double delta, double sw, T* fb,
                                T* pb, T* cb, double* part) {
-  const int nb = adj_blocks((int64_t)m.nx * m.ny);
+  const int nb = adj_blocks(m.nx, m.ny);
   hipLaunchKernelGGL((k_adj_seed<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, pass, m, phi, pitch, drops_prev, ndrop, drop,
                      delta, sw, fb, pb, cb, part);
   return hipGetLastError();

@@ -1312,7 +1312,7 @@ struct AdjLayout {
   size_t off_cp = 0, off_seg = 0, off_final = 0, off_fwd = 0, off_adj = 0, off_part = 0, total = 0;
 };
 
-constexpr int ADJ_TMP_PLANES = 24;  // gradient planes and intermediate adjoints of one backward step
+constexpr int ADJ_TMP_PLANES = 16;  // gradient planes and intermediate adjoints of one backward step
 // The adjoint step reads the first ADJ_FWD_PLANES stage planes of the forward step (mu .. X^{n+1/2}).  The
 // stage export writes twice as many, so the exports of the steps of an interval are laid out
 // ADJ_FWD_PLANES planes apart: the later step's export overwrites only the unread second half of the earlier.
@@ -1367,7 +1367,7 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int every) {
   AdjLayout A;
   const InstDev& d = c->L.inst[0];
   A.nodes = (int64_t)d.nx * d.ny;
-  A.nb = adj_blocks(A.nodes);
+  A.nb = adj_blocks(d.nx, d.ny);
   A.every = every;
   A.ncp = (nsteps + every - 1) / every;
   A.pop = (size_t)9 * d.pstride * c->L.elem;
@@ -1483,8 +1483,8 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
     p.fb = out;
     p.pb = out + 9 * M;
     p.cb = out + 10 * M;
-    T** t[] = {&p.gpx, &p.gpy, &p.gcx, &p.gcy, &p.lp, &p.gphx, &p.gphy, &p.gchx, &p.gchy, &p.lph, &p.gmx, &p.gmy,
-               &p.gXx, &p.gXy, &p.Mb, &p.Xhb, &p.phb, &p.chb, &p.uxb, &p.uyb, &p.Fxb, &p.Fyb, &p.mub, &p.Xb};
+    T** t[] = {&p.gpx, &p.gpy, &p.gcx, &p.gcy, &p.gphx, &p.gphy, &p.gchx, &p.gchy,
+               &p.Mb,  &p.Xhb, &p.phb, &p.chb, &p.Fxb,  &p.Fyb,  &p.mub,  &p.Xb};
     static_assert(sizeof(t) / sizeof(t[0]) == ADJ_TMP_PLANES, "temporary planes");
     for (int i = 0; i < ADJ_TMP_PLANES; ++i) *t[i] = tmp + (size_t)i * M;
     return p;
