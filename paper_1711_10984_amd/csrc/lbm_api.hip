@@ -1499,12 +1499,11 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
     for (int64_t k = k0; k < k1; ++k) {
       if ((rc = adj_save_seg(c, A, w + A.off_seg + (size_t)(k - k0) * A.sslot)) != LBM_OK) return rc;
       HIPCHK((debug_launch<T, T>(c, 0, fwd_rec(k - k0))));
-      // on the split path the stage-export pair has also written the next state and the centre-of-mass
-      // partials, so only the reduction is left of the step
-      hipError_t e = c->path == LBM_PATH_SPLIT
-                         ? launch_reduce(c->stream, TILING_SPLIT, c->L.ndrop_total, c->d_inst(), c->d_drops(),
-                                         c->d_part(), c->d_mask(), c->d_step(), 1)
-                         : enqueue_step_any(c, c->parity);
+      // the stage-export launch has also written the next state and the centre-of-mass partials, so only
+      // the reduction is left of the step
+      hipError_t e = launch_reduce(c->stream, c->path == LBM_PATH_SPLIT ? TILING_SPLIT : TILING_FUSED,
+                                   c->L.ndrop_total, c->d_inst(), c->d_drops(), c->d_part(), c->d_mask(),
+                                   c->d_step(), 1);
       if (e != hipSuccess) return fail(LBM_E_HIP, std::string("adjoint recompute: ") + hipGetErrorString(e));
       c->parity ^= 1;
       c->step += 1;

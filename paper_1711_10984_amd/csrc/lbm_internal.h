@@ -87,8 +87,9 @@ hipError_t launch_cm_partials(hipStream_t s, int parity, int ntiles_launch, cons
                               uint64_t* mask);
 hipError_t launch_reduce(hipStream_t s, int tiling, int ndrop_total, const InstDev* inst, DropDev* drops,
                          const double* part, const uint64_t* mask, int64_t* step, int increment);
-// Fused timestep (one launch per step over the strip list); dbg != nullptr exports stage planes of
-// instance dbg_inst instead of advancing.
+// Fused timestep (one launch per step over the strip list); dbg != nullptr also exports the stage planes of
+// instance dbg_inst and steps only that instance (its next state in the inactive half, and its centre-of-mass
+// partials).
 template <typename T, typename P>
 hipError_t launch_step(hipStream_t s, int parity, int nseg_launch, const TileDev* segs, const InstDev* inst,
                        T* buf, const DropDev* drops, double* part, uint64_t* mask, const int64_t* step,

@@ -936,6 +936,9 @@ __device__ __forceinline__ T advect_n(T gc, T ge, T gw, T gn, T gs, T uc, T ue, 
   return gc - ((Fr - Fl) + (Ft - Fb));
 }
 
+// DBG: also export the stage planes of instance dbg_inst (the other instances are skipped).  The state writes and
+// the centre-of-mass partials are those of a step either way: they go to the inactive half, so an export leaves
+// the state as it was, and followed by the reduction it is a whole step (the reverse mode's recompute).
 template <typename T, typename P, bool DBG>
 __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __restrict__ segs,
                                                    const InstDev* __restrict__ insts, T* __restrict__ buf,
@@ -1225,16 +1228,15 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
         const double src = A * (double)cnt;
         const T cn = (((ch + D * lch) + dv) - gam * (ch - c0)) + T(src);
         const int64_t o = (int64_t)r * pitch + gx;
-        if (!DBG) {
-          phi_out[o] = phn;
-          c_out[o] = cn;
-        } else {
+        phi_out[o] = phn;
+        c_out[o] = cn;
+        if (DBG) {
           const int64_t q = (int64_t)r * nx + (x0 + col);
           dbg[11 * nplane + q] = (double)phn;
           dbg[12 * nplane + q] = (double)cn;
         }
         const double v = (double)phn;
-        if (!DBG && nd > 0 && v >= 0.0) {
+        if (nd > 0 && v >= 0.0) {
           // nearest centre among the candidates (a single candidate is the nearest)
           int best = -1;
           if (ncand == 1) {
@@ -1273,7 +1275,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
     }
     // other candidates (rare): deterministic per-sweep workgroup sums of their contributions, added to the
     // strip's partials in global memory (with a single candidate there are none, and no barrier is needed)
-    if (!DBG && ncand > 1 && __syncthreads_or(kd >= 0)) {
+    if (ncand > 1 && __syncthreads_or(kd >= 0)) {
       if (tid < MASK_WORDS) sh.it_mask[tid] = 0ull;
       __syncthreads();
       if (kd >= 0) atomicOr(&sh.it_mask[kd >> 6], 1ull << (kd & 63));
@@ -1303,7 +1305,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
       }
     }
   }
-  if (DBG || nd == 0) return;
+  if (nd == 0) return;
   // the slot's workgroup sum (fixed order), and the presence mask
   if (__syncthreads_or(met0)) {
     double s0 = sh.slot[0][tid], s1 = sh.slot[1][tid], s2 = sh.slot[2][tid];
@@ -1575,12 +1577,12 @@ __device__ __forceinline__ T sten_lap(T up, T mid, T dn) {
   }
 }
 
-// PLAIN: every lattice of the launch is periodic in y and advects by the printed Eqs. (16)-(17), so the
+// DBG as for k_step.  PLAIN: every lattice of the launch is periodic in y and advects by the printed Eqs. (16)-(17), so the
 // plate mirrors and the flux form compile away.  Occupancy targets: FP64 keeps its windows and two prefetch
 // sets in registers at two waves per SIMD; FP16 storage takes three; FP32 (one prefetch set, scalar-base
-// addresses) fits four.
+// addresses) fits four, its export instance three.
 template <typename T, typename P, bool DBG, bool PLAIN>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : sizeof(P) == 4 ? 4 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : sizeof(P) == 4 && !DBG ? 4 : 3))) void k_wave(int parity, const TileDev* __restrict__ segs,
                                              const InstDev* __restrict__ insts, T* __restrict__ buf,
                                              const DropDev* __restrict__ drops, double* __restrict__ part,
                                              uint64_t* __restrict__ mask, const int64_t* __restrict__ step,
@@ -1915,16 +1917,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       int kd = -1;
       double cv0 = 0.0, cv1 = 0.0, cv2 = 0.0;
       if (own_col) {
-        if (!DBG) {
-          st_col(phi_out + (int64_t)r * pitch, bx, phn);
-          st_col(c_out + (int64_t)r * pitch, bx, cn);
-        } else {
+        st_col(phi_out + (int64_t)r * pitch, bx, phn);
+        st_col(c_out + (int64_t)r * pitch, bx, cn);
+        if (DBG) {
           const int64_t qq = (int64_t)r * nx + (x0 + col);
           dbg[11 * nplane + qq] = (double)phn;
           dbg[12 * nplane + qq] = (double)cn;
         }
         const double v = (double)phn;
-        if (!DBG && nd > 0 && v >= 0.0) {
+        if (nd > 0 && v >= 0.0) {
           // nearest centre among the candidates (a single candidate is the nearest)
           int best = -1;
           if (ncand == 1) {
@@ -1965,7 +1966,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       // centre-of-mass contributions: candidate number r of the segment (in droplet order) has slot r; a lane
       // adds its node to its slot.  Candidates beyond the slots (rare) take the row's wave sum (fixed
       // butterfly order) straight into the strip's partials.
-      if (!DBG && nd > 0 && __ballot(kd >= 0) != 0ull) {
+      if (nd > 0 && __ballot(kd >= 0) != 0ull) {
         const int slot = kd >= 0 ? (int)s_slot[kd] : CM_SLOTS;
         if (slot < CM_SLOTS) {
           acc[slot][0][lane] += cv0;
@@ -2016,7 +2017,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     for (int j = 0; j < PFD; ++j)
       if (it + j < nit) sweep(it + j, pfs[j]);
   }
-  if (DBG || nd == 0) return;
+  if (nd == 0) return;
   // the slots' wave sums (fixed butterfly order), for the candidates that received nodes
   for (int s = 0; s < CM_SLOTS; ++s) {
     if (!(slots_met & (1u << s))) continue;
