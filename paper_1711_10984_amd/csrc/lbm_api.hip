@@ -542,15 +542,17 @@ int fields_impl(lbm_ctx* c, int inst, double* f_pre, double* phi, double* cc, do
   return LBM_OK;
 }
 
-// Stage planes of the next step of instance `inst` from the kernels of the current path.
+// Stage planes of the next step of instance `inst` from the kernels of the current path: all LBM_NSTAGE, or only
+// the first ADJ_EXPORT_PLANES (all = false).
 template <typename T, typename P>
-hipError_t debug_launch(lbm_ctx* c, int inst, double* dbg) {
+hipError_t debug_launch(lbm_ctx* c, int inst, double* dbg, bool all = true) {
   T* buf = reinterpret_cast<T*>(c->pool());
-  if (c->path != LBM_PATH_SPLIT) return launch_sweep<T, P>(c, c->parity, dbg, inst);
-  hipError_t e = launch_lb<T, P>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, dbg, inst);
+  const int di = export_planes(inst, all);
+  if (c->path != LBM_PATH_SPLIT) return launch_sweep<T, P>(c, c->parity, dbg, di);
+  hipError_t e = launch_lb<T, P>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, dbg, di);
   if (e != hipSuccess) return e;
   return launch_fd<T>(c->stream, 1, c->parity, c->nlaunch(), c->d_tiles(), c->d_inst(), buf, c->d_drops(), c->d_part(),
-                      c->d_mask(), c->d_step(), dbg, inst);
+                      c->d_mask(), c->d_step(), dbg, di);
 }
 
 // One eager step with hipEvents between its kernels: ev[0..nk] bracket nk launches.
@@ -1313,11 +1315,10 @@ struct AdjLayout {
 };
 
 constexpr int ADJ_TMP_PLANES = 16;  // gradient planes and intermediate adjoints of one backward step
-// The adjoint step reads the first ADJ_FWD_PLANES stage planes of the forward step (mu .. X^{n+1/2}).  The
-// stage export writes twice as many, so the exports of the steps of an interval are laid out
-// ADJ_FWD_PLANES planes apart: the later step's export overwrites only the unread second half of the earlier.
-constexpr int ADJ_FWD_PLANES = 11;
-static_assert(2 * ADJ_FWD_PLANES == LBM_NSTAGE, "stage planes of the adjoint's forward record");
+// The adjoint step reads the first ADJ_FWD_PLANES stage planes of the forward step (mu .. X^{n+1/2}), and the
+// recompute exports only those: the record of an interval holds ADJ_FWD_PLANES planes per step.
+constexpr int ADJ_FWD_PLANES = ADJ_EXPORT_PLANES;
+static_assert(ADJ_FWD_PLANES <= LBM_NSTAGE, "stage planes of the adjoint's forward record");
 
 // Up to five byte ranges (multiples of 8 bytes) copied by one launch.
 struct CopyList {
@@ -1380,7 +1381,7 @@ AdjLayout adj_layout(const lbm_ctx* c, int64_t nsteps, int every) {
   A.off_seg = off;   off += A.sslot * (size_t)every;
   A.off_final = off; off += A.slot;
   A.off_fwd = off;
-  off = align_up(off + sizeof(double) * ADJ_FWD_PLANES * (size_t)(every + 1) * (size_t)A.nodes, ALIGN);
+  off = align_up(off + sizeof(double) * ADJ_FWD_PLANES * (size_t)every * (size_t)A.nodes, ALIGN);
   A.off_adj = off;   off = align_up(off + c->L.elem * (size_t)(22 + ADJ_TMP_PLANES) * A.nodes, ALIGN);
   A.off_part = off;  off = align_up(off + sizeof(double) * (size_t)A.nb * 2, ALIGN);  // seed sums, dA0 totals
   A.total = off;
@@ -1498,7 +1499,7 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
     if ((rc = adj_load(c, A, w + A.off_cp + (size_t)s * A.slot, n0 + k0)) != LBM_OK) return rc;
     for (int64_t k = k0; k < k1; ++k) {
       if ((rc = adj_save_seg(c, A, w + A.off_seg + (size_t)(k - k0) * A.sslot)) != LBM_OK) return rc;
-      HIPCHK((debug_launch<T, T>(c, 0, fwd_rec(k - k0))));
+      HIPCHK((debug_launch<T, T>(c, 0, fwd_rec(k - k0), false)));
       // the stage-export launch has also written the next state and the centre-of-mass partials, so only
       // the reduction is left of the step
       hipError_t e = launch_reduce(c->stream, c->path == LBM_PATH_SPLIT ? TILING_SPLIT : TILING_FUSED,

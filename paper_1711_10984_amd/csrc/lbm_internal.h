@@ -73,7 +73,11 @@ struct TileDev {
 // Launch helpers, instantiated in lbm_kernels_f64.hip, lbm_kernels_f32.hip and lbm_kernels_f16.hip.
 // T is the arithmetic (and field) type, P the population storage type (T itself, or _Float16 deviations
 // from w_i n0 with T = float).  `buf` is the typed base pointer of the field pool, `parity` selects the
-// current buffers.  Modes: 0 step, 1 step + stage export, 2 diagnostics only.
+// current buffers.  Modes: 0 step, 1 step + stage export, 2 diagnostics only.  An export names its instance
+// in dbg_inst: inst exports all LBM_NSTAGE planes, -2 - inst (export_planes()) only the first ADJ_EXPORT_PLANES
+// (mu .. X^{n+1/2}), which the reverse mode reads.
+constexpr int ADJ_EXPORT_PLANES = 11;
+inline int export_planes(int inst, bool all) { return all ? inst : -2 - inst; }
 template <typename T, typename P>
 hipError_t launch_lb(hipStream_t s, int mode, int parity, int ntiles_launch, const TileDev* tiles,
                      const InstDev* inst, T* buf, double* dbg, int dbg_inst);

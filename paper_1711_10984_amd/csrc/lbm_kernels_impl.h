@@ -449,6 +449,11 @@ __device__ void tile_cm_sums(const InstDev& I, int t_local, int t_global, const 
 
 // ------------------------------------------------------------------------------------------------
 // k_lb: mu, X, F; pull + moments; collision.  MODE 0: step, 1: step + stage planes, 2: n and u only.
+// Export launches name their instance in dbg_inst: inst for all LBM_NSTAGE stage planes, -2 - inst for the
+// first eleven (mu .. X^{n+1/2}) only, which is what the reverse mode reads.
+__device__ __forceinline__ int export_inst(int dbg_inst) { return dbg_inst >= 0 ? dbg_inst : -2 - dbg_inst; }
+__device__ __forceinline__ bool export_all(int dbg_inst) { return dbg_inst >= 0; }
+
 template <typename T, typename P, int MODE>
 __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __restrict__ tiles,
                                                  const InstDev* __restrict__ insts, T* __restrict__ buf,
@@ -460,7 +465,7 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
 
   const TileDev td = tiles[blockIdx.x];
   if (td.inst < 0) return;
-  if (MODE == 1 && td.inst != dbg_inst) return;
+  if (MODE == 1 && td.inst != export_inst(dbg_inst)) return;
   const InstDev& I = insts[td.inst];
   const int nx = I.nx, ny = I.ny, pitch = I.pitch;
   const int tid = threadIdx.x;
@@ -557,7 +562,8 @@ __global__ __launch_bounds__(NTHREADS) void k_lb(int parity, const TileDev* __re
       dbg[4 * nplane + q] = (double)nn;
       dbg[5 * nplane + q] = (double)ux;
       dbg[6 * nplane + q] = (double)uy;
-      for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = sv[i];
+      if (export_all(dbg_inst))
+        for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = sv[i];
     }
   }
 }
@@ -580,7 +586,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fd(int parity, const TileDev* __re
 
   const TileDev td = tiles[blockIdx.x];
   if (td.inst < 0) return;
-  if (MODE == 1 && td.inst != dbg_inst) return;
+  if (MODE == 1 && td.inst != export_inst(dbg_inst)) return;
   const InstDev& I = insts[td.inst];
   const int nx = I.nx, ny = I.ny, pitch = I.pitch;
   const int tid = threadIdx.x;
@@ -679,8 +685,10 @@ __global__ __launch_bounds__(NTHREADS) void k_fd(int parity, const TileDev* __re
       dbg[8 * nplane + q] = (double)ch;
       dbg[9 * nplane + q] = (double)s_M[i1];
       dbg[10 * nplane + q] = (double)s_Xh[i1];
-      dbg[11 * nplane + q] = (double)phn;
-      dbg[12 * nplane + q] = (double)cn;
+      if (export_all(dbg_inst)) {
+        dbg[11 * nplane + q] = (double)phn;
+        dbg[12 * nplane + q] = (double)cn;
+      }
     }
   }
   // the stage-export mode writes the partials too: with its state writes (to the inactive half) it is a
@@ -952,7 +960,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
 
   const TileDev sd = segs[blockIdx.x];
   if (sd.inst < 0) return;
-  if (DBG && sd.inst != dbg_inst) return;
+  if (DBG && sd.inst != export_inst(dbg_inst)) return;
   const InstDev& I = insts[sd.inst];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nx = I.nx, ny = I.ny, pitch = I.pitch, nd = I.ndrop;
@@ -1141,7 +1149,8 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
             dbg[4 * nplane + q] = (double)nn;
             dbg[5 * nplane + q] = (double)ux;
             dbg[6 * nplane + q] = (double)uy;
-            for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = sv[i];
+            if (export_all(dbg_inst))
+              for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + q] = sv[i];
           }
         }
       }
@@ -1230,7 +1239,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(int parity, const TileDev* __
         const int64_t o = (int64_t)r * pitch + gx;
         phi_out[o] = phn;
         c_out[o] = cn;
-        if (DBG) {
+        if (DBG && export_all(dbg_inst)) {
           const int64_t q = (int64_t)r * nx + (x0 + col);
           dbg[11 * nplane + q] = (double)phn;
           dbg[12 * nplane + q] = (double)cn;
@@ -1599,7 +1608,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 
   const TileDev sd = segs[blockIdx.x];
   if (sd.inst < 0) return;
-  if (DBG && sd.inst != dbg_inst) return;
+  if (DBG && sd.inst != export_inst(dbg_inst)) return;
   const InstDev& I = insts[sd.inst];
   const int lane = threadIdx.x;
   const int nx = I.nx, ny = I.ny, pitch = I.pitch, nd = I.ndrop;
@@ -1835,7 +1844,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           dbg[4 * nplane + qq] = (double)nn;
           dbg[5 * nplane + qq] = (double)ux;
           dbg[6 * nplane + qq] = (double)uy;
-          for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + qq] = sv[i];
+          if (export_all(dbg_inst))
+            for (int i = 0; i < 9; ++i) dbg[(13 + i) * nplane + qq] = sv[i];
         }
       }
       if (r + PFD < yend + 3) {
@@ -1919,7 +1929,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       if (own_col) {
         st_col(phi_out + (int64_t)r * pitch, bx, phn);
         st_col(c_out + (int64_t)r * pitch, bx, cn);
-        if (DBG) {
+        if (DBG && export_all(dbg_inst)) {
           const int64_t qq = (int64_t)r * nx + (x0 + col);
           dbg[11 * nplane + qq] = (double)phn;
           dbg[12 * nplane + qq] = (double)cn;
