@@ -24,7 +24,7 @@
 namespace lbm {
 namespace {
 
-// A block of the stepping kernels covers a tile of ADJ_TILE_X x ADJ_TILE_Y nodes, one wavefront per tile row.
+// A block of the kernels K1-K5 covers a tile of ADJ_TILE_X x ADJ_TILE_Y nodes, one wavefront per tile row.
 // The planes that a kernel reads across the 3 x 3 neighbourhood are first copied to LDS, the tile with a
 // one-node halo (ADJ_HN values per plane, at most two per thread), so that each value is loaded from memory
 // once per block instead of once per neighbour.
