@@ -21,8 +21,8 @@ struct AdjPlanes {
   int pitch;
   const T *fb1, *pb1, *cb1;  // adjoint of f (9 planes), phi, c at n + 1
   T *fb, *pb, *cb;           // adjoint at n (outputs)
-  // gradient planes of the forward fields
-  T *gpx, *gpy, *gcx, *gcy, *gphx, *gphy, *gchx, *gchy;
+  // gradient planes of phi^{n+1/2}, c^{n+1/2}
+  T *gphx, *gphy, *gchx, *gchy;
   // intermediate adjoints
   T *Mb, *Xhb, *phb, *chb, *Fxb, *Fyb, *mub, *Xb;
 };

@@ -9,8 +9,8 @@
 // Held fixed (non-differentiable): the membership of each node in the production disks, the upwind side chosen
 // by the sign of u in Eqs. (16)-(17), and the droplet masks.
 //
-// Five launches per step, each one stencil layer deep over dense [ny][nx] planes:
-//   K1  gradient planes of the forward fields; adjoint of Eq. (19) (c update, link divergence, production
+// Four launches per step (K4 and K5 share one), each one stencil layer deep over dense [ny][nx] planes:
+//   K1  gradient planes of phi^{n+1/2}, c^{n+1/2}; adjoint of Eq. (19) (c update, link divergence, production
 //       rate) and of the phi update of Eq. (18) down to the bracket M
 //   K2  adjoint of M (Eq. 18) and of X^{n+1/2} down to phi^{n+1/2}, c^{n+1/2}
 //   K3  adjoint of the advection half-step (Eqs. 16-17), then of streaming and collision (Eqs. 10-13)
@@ -143,8 +143,8 @@ __device__ __forceinline__ T L9(V v) {
 // which is the boundary row itself, and there are no outputs beyond the plate.  Gathering at node j, both
 // effects together amount to evaluating the same periodic formula with the adjoint operand continued across
 // the plate by its mirror image: even for L9 and G9x (symmetric in y), odd for G9y (antisymmetric in y).
-template <typename T, class V>
-__device__ __forceinline__ T G9y_T(const Nbh& k, V v) {
+template <typename T, class K, class V>
+__device__ __forceinline__ T G9y_T(const K& k, V v) {
   auto w = [&](int dx, int dy) { return T(k.odd(dy)) * v(dx, dy); };
   return G9y<T>(w);
 }
@@ -166,10 +166,8 @@ template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj1(AdjModel m, AdjFwd f, AdjPlanes<T> p, const DropDev* drops,
                                                       int ndrop, double* part) {
   __shared__ double red[ADJ_THREADS / 64];
-  __shared__ T s_phi[ADJ_HN], s_c[ADJ_HN], s_ph[ADJ_HN], s_ch[ADJ_HN], s_pb1[ADJ_HN], s_cb1[ADJ_HN], s_Xh[ADJ_HN];
+  __shared__ T s_ph[ADJ_HN], s_ch[ADJ_HN], s_pb1[ADJ_HN], s_cb1[ADJ_HN], s_Xh[ADJ_HN];
   const Tile t = make_tile(m, p.pitch);
-  stage(s_phi, t, [&](int, int q) { return p.phi[q]; });
-  stage(s_c, t, [&](int, int q) { return p.c[q]; });
   stage(s_ph, t, [&](int o, int) { return T(f.ph[o]); });
   stage(s_ch, t, [&](int o, int) { return T(f.ch[o]); });
   stage(s_pb1, t, [&](int o, int) { return p.pb1[o]; });
@@ -180,16 +178,10 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj1(AdjModel m, AdjFwd f, AdjP
   if (t.valid) {
     const Nbh k = make_nbh(t, m);
     const int idx = t.y * m.nx + t.x;
-    auto phi = [&](int dx, int dy) { return s_phi[k.s(dx, dy)]; };
-    auto cc = [&](int dx, int dy) { return s_c[k.s(dx, dy)]; };
     auto ph = [&](int dx, int dy) { return s_ph[k.s(dx, dy)]; };
     auto ch = [&](int dx, int dy) { return s_ch[k.s(dx, dy)]; };
-    // gradient planes of the forward fields that the later launches read at neighbouring nodes (those needed
-    // only at the node itself are formed where they are used)
-    p.gpx[idx] = G9x<T>(phi);
-    p.gpy[idx] = G9y<T>(phi);
-    p.gcx[idx] = G9x<T>(cc);
-    p.gcy[idx] = G9y<T>(cc);
+    // gradient planes of phi^{n+1/2}, c^{n+1/2} that K2 reads at neighbouring nodes (those of phi^n, c^n are formed
+    // by K45, and those needed only at the node itself where they are used)
     p.gphx[idx] = G9x<T>(ph);
     p.gphy[idx] = G9y<T>(ph);
     p.gchx[idx] = G9x<T>(ch);
@@ -369,67 +361,129 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjP
   p.cb[idx] = cbv;
 }
 
-template <typename T>
-__global__ __launch_bounds__(ADJ_THREADS) void k_adj4(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
-  __shared__ T s_Fxb[ADJ_HN], s_Fyb[ADJ_HN], s_phi[ADJ_HN], s_c[ADJ_HN], s_mu[ADJ_HN], s_X[ADJ_HN];
-  const Tile t = make_tile(m, p.pitch);
-  stage(s_Fxb, t, [&](int o, int) { return p.Fxb[o]; });
-  stage(s_Fyb, t, [&](int o, int) { return p.Fyb[o]; });
-  stage(s_phi, t, [&](int, int q) { return p.phi[q]; });
-  stage(s_c, t, [&](int, int q) { return p.c[q]; });
-  stage(s_mu, t, [&](int o, int) { return T(f.mu[o]); });
-  stage(s_X, t, [&](int o, int) { return T(f.X[o]); });
-  __syncthreads();
-  if (!t.valid) return;
-  const Nbh k = make_nbh(t, m);
-  const int idx = t.y * m.nx + t.x;
-  // F = -phi grad9 mu - grad9 c - c grad9 X (Eq. 14)
-  auto Fxb = [&](int dx, int dy) { return s_Fxb[k.s(dx, dy)]; };
-  auto Fyb = [&](int dx, int dy) { return s_Fyb[k.s(dx, dy)]; };
-  auto phFx = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_phi[q] * s_Fxb[q]; };
-  auto phFy = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_phi[q] * s_Fyb[q]; };
-  auto cFx = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_c[q] * s_Fxb[q]; };
-  auto cFy = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_c[q] * s_Fyb[q]; };
-  auto mu = [&](int dx, int dy) { return s_mu[k.s(dx, dy)]; };
-  auto X = [&](int dx, int dy) { return s_X[k.s(dx, dy)]; };
-  const T fx = Fxb(0, 0), fy = Fyb(0, 0);
-  p.pb[idx] -= fx * G9x<T>(mu) + fy * G9y<T>(mu);
-  p.cb[idx] += (G9x<T>(Fxb) + G9y_T<T>(k, Fyb)) - (fx * G9x<T>(X) + fy * G9y<T>(X));
-  p.mub[idx] = G9x<T>(phFx) + G9y_T<T>(k, phFy);
-  p.Xb[idx] = G9x<T>(cFx) + G9y_T<T>(k, cFy);
+// K4 and K5 in one launch.  The adjoint of the force (K4) gives mu_bar and X_bar, which the adjoint of mu_phi and
+// X (K5) reads at the 3 x 3 neighbourhood: they are computed on the tile with a one-node ring and kept in LDS, from
+// F_bar, phi and c on the tile with a two-node ring.  A ring node takes the values of the node it stands for (its
+// periodic image; with walls, a ring row beyond a plate takes the boundary row's, as a plane read at the mirrored
+// row gives).  Then K4's and K5's updates of phi_bar and c_bar at the tile, in that order.
+constexpr int ADJ_W2 = ADJ_TILE_X + 4, ADJ_N2 = ADJ_W2 * (ADJ_TILE_Y + 4);
+static_assert(ADJ_N2 <= 3 * ADJ_THREADS, "three staged values per thread");
+
+// Neighbourhood of a point in the frame with the two-node ring: index l in that frame, and the mirror signs.
+struct Nbh2 {
+  int l;
+  int sg[3];
+  __device__ int s(int dx, int dy) const { return l + dy * ADJ_W2 + dx; }
+  __device__ int odd(int dy) const { return sg[dy + 1]; }
+};
+
+__device__ __forceinline__ Nbh2 make_nbh2(int l, int y, const AdjModel& m) {
+  Nbh2 k;
+  k.l = l;
+  k.sg[0] = m.walls && y == 0 ? -1 : 1;
+  k.sg[1] = 1;
+  k.sg[2] = m.walls && y == m.ny - 1 ? -1 : 1;
+  return k;
 }
 
 template <typename T>
-__global__ __launch_bounds__(ADJ_THREADS) void k_adj5(AdjModel m, AdjPlanes<T> p) {
-  __shared__ T s_c[ADJ_HN], s_phi[ADJ_HN], s_mub[ADJ_HN], s_Xb[ADJ_HN];
-  __shared__ T s_gcx[ADJ_HN], s_gcy[ADJ_HN], s_gpx[ADJ_HN], s_gpy[ADJ_HN];
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj45(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
+  __shared__ T s_Fxb[ADJ_N2], s_Fyb[ADJ_N2], s_phi[ADJ_N2], s_c[ADJ_N2];
+  __shared__ T s_mu[ADJ_HN], s_X[ADJ_HN], s_mub[ADJ_HN], s_Xb[ADJ_HN];
+  __shared__ T s_gcx[ADJ_HN], s_gcy[ADJ_HN], s_gpx[ADJ_HN], s_gpy[ADJ_HN];  // gradients of phi^n, c^n
   const Tile t = make_tile(m, p.pitch);
-  stage(s_c, t, [&](int, int q) { return p.c[q]; });
-  stage(s_phi, t, [&](int, int q) { return p.phi[q]; });
-  stage(s_mub, t, [&](int o, int) { return p.mub[o]; });
-  stage(s_Xb, t, [&](int o, int) { return p.Xb[o]; });
-  stage(s_gcx, t, [&](int o, int) { return p.gcx[o]; });
-  stage(s_gcy, t, [&](int o, int) { return p.gcy[o]; });
-  stage(s_gpx, t, [&](int o, int) { return p.gpx[o]; });
-  stage(s_gpy, t, [&](int o, int) { return p.gpy[o]; });
+  const int nbx = (m.nx + ADJ_TILE_X - 1) / ADJ_TILE_X;
+  const int b = xcd_block(), by = b / nbx, bx = b - by * nbx;
+  const int x0 = bx * ADJ_TILE_X, y0 = by * ADJ_TILE_Y;
+  // the frame with the two-node ring: periodic images, or with walls the mirrored rows (clamped for lattices of
+  // fewer rows than the ring reaches; only ring nodes that are not computed read those)
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj) {
+    const int i = threadIdx.x + jj * ADJ_THREADS;
+    if (i < ADJ_N2) {
+      const int ly = i / ADJ_W2, lx = i - ly * ADJ_W2;
+      const int gx = (x0 + lx - 2 + 2 * m.nx) % m.nx;
+      int gy = y0 + ly - 2;
+      if (m.walls) {
+        gy = gy < 0 ? -1 - gy : gy >= m.ny ? 2 * m.ny - 1 - gy : gy;
+        gy = gy < 0 ? 0 : gy >= m.ny ? m.ny - 1 : gy;
+      } else {
+        gy = (gy + 2 * m.ny) % m.ny;
+      }
+      const int o = gy * m.nx + gx, q = gy * p.pitch + gx;
+      s_Fxb[i] = p.Fxb[o];
+      s_Fyb[i] = p.Fyb[o];
+      s_phi[i] = p.phi[q];
+      s_c[i] = p.c[q];
+    }
+  }
+  stage(s_mu, t, [&](int o, int) { return T(f.mu[o]); });
+  stage(s_X, t, [&](int o, int) { return T(f.X[o]); });
   __syncthreads();
+  // mu_bar, X_bar (Eq. 14 transposed) and the gradients of phi^n, c^n on the tile and its one-node ring
+  for (int i = threadIdx.x; i < ADJ_HN; i += ADJ_THREADS) {
+    const int ly = i / ADJ_HX, lx = i - ly * ADJ_HX;
+    const int gy = y0 + ly - 1;
+    if (m.walls && (gy < 0 || gy >= m.ny)) continue;  // beyond a plate: copied below
+    const Nbh2 k = make_nbh2((ly + 1) * ADJ_W2 + lx + 1, (gy + m.ny) % m.ny, m);
+    auto phFx = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_phi[q] * s_Fxb[q]; };
+    auto phFy = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_phi[q] * s_Fyb[q]; };
+    auto cFx = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_c[q] * s_Fxb[q]; };
+    auto cFy = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_c[q] * s_Fyb[q]; };
+    auto phi = [&](int dx, int dy) { return s_phi[k.s(dx, dy)]; };
+    auto cc = [&](int dx, int dy) { return s_c[k.s(dx, dy)]; };
+    s_mub[i] = G9x<T>(phFx) + G9y_T<T>(k, phFy);
+    s_Xb[i] = G9x<T>(cFx) + G9y_T<T>(k, cFy);
+    s_gpx[i] = G9x<T>(phi);
+    s_gpy[i] = G9y<T>(phi);
+    s_gcx[i] = G9x<T>(cc);
+    s_gcy[i] = G9y<T>(cc);
+  }
+  __syncthreads();
+  if (m.walls) {
+    for (int i = threadIdx.x; i < ADJ_HN; i += ADJ_THREADS) {
+      const int ly = i / ADJ_HX, lx = i - ly * ADJ_HX;
+      const int gy = y0 + ly - 1;
+      if (gy >= 0 && gy < m.ny) continue;
+      const int src = ((gy < 0 ? 0 : m.ny - 1) - y0 + 1) * ADJ_HX + lx;
+      s_mub[i] = s_mub[src];
+      s_Xb[i] = s_Xb[src];
+      s_gpx[i] = s_gpx[src];
+      s_gpy[i] = s_gpy[src];
+      s_gcx[i] = s_gcx[src];
+      s_gcy[i] = s_gcy[src];
+    }
+    __syncthreads();
+  }
   if (!t.valid) return;
   const Nbh k = make_nbh(t, m);
+  const Nbh2 k2 = make_nbh2((threadIdx.x / ADJ_TILE_X + 2) * ADJ_W2 + threadIdx.x % ADJ_TILE_X + 2, t.y, m);
   const int idx = t.y * m.nx + t.x;
-  const T a = T(m.a), b = T(m.b), B0 = T(m.B0), B1 = T(m.B1);
-  // mu = a phi + b phi^3 - B(c) lap9 phi - B1 grad9 phi . grad9 c;  X = (B1/2) |grad9 phi|^2 (Eqs. 3, 5)
-  auto BMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return (B0 + B1 * s_c[q]) * s_mub[q]; };
+  // K4: F = -phi grad9 mu - grad9 c - c grad9 X (Eq. 14)
+  auto Fxb = [&](int dx, int dy) { return s_Fxb[k2.s(dx, dy)]; };
+  auto Fyb = [&](int dx, int dy) { return s_Fyb[k2.s(dx, dy)]; };
+  auto mu = [&](int dx, int dy) { return s_mu[k.s(dx, dy)]; };
+  auto X = [&](int dx, int dy) { return s_X[k.s(dx, dy)]; };
+  const T fx = Fxb(0, 0), fy = Fyb(0, 0);
+  T pb = p.pb[idx], cb = p.cb[idx];
+  pb -= fx * G9x<T>(mu) + fy * G9y<T>(mu);
+  cb += (G9x<T>(Fxb) + G9y_T<T>(k2, Fyb)) - (fx * G9x<T>(X) + fy * G9y<T>(X));
+  // K5: mu = a phi + b phi^3 - B(c) lap9 phi - B1 grad9 phi . grad9 c;  X = (B1/2) |grad9 phi|^2 (Eqs. 3, 5)
+  const T a = T(m.a), b3 = T(m.b), B0 = T(m.B0), B1 = T(m.B1);
+  auto BMu = [&](int dx, int dy) { return (B0 + B1 * s_c[k2.s(dx, dy)]) * s_mub[k.s(dx, dy)]; };
   auto gcxMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gcx[q] * s_mub[q]; };
   auto gcyMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gcy[q] * s_mub[q]; };
   auto gpxMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gpx[q] * s_mub[q]; };
   auto gpyMu = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gpy[q] * s_mub[q]; };
   auto gpxX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gpx[q] * s_Xb[q]; };
   auto gpyX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gpy[q] * s_Xb[q]; };
-  auto phi = [&](int dx, int dy) { return s_phi[k.s(dx, dy)]; };
+  auto phi = [&](int dx, int dy) { return s_phi[k2.s(dx, dy)]; };
   const T ph = phi(0, 0), mb = s_mub[k.l];
-  p.pb[idx] += (((a + T(3) * b * (ph * ph)) * mb - L9<T>(BMu)) + B1 * (G9x<T>(gcxMu) + G9y_T<T>(k, gcyMu))) -
-               B1 * (G9x<T>(gpxX) + G9y_T<T>(k, gpyX));
-  p.cb[idx] += B1 * (G9x<T>(gpxMu) + G9y_T<T>(k, gpyMu)) - B1 * L9<T>(phi) * mb;
+  pb += (((a + T(3) * b3 * (ph * ph)) * mb - L9<T>(BMu)) + B1 * (G9x<T>(gcxMu) + G9y_T<T>(k, gcyMu))) -
+        B1 * (G9x<T>(gpxX) + G9y_T<T>(k, gpyX));
+  cb += B1 * (G9x<T>(gpxMu) + G9y_T<T>(k, gpyMu)) - B1 * L9<T>(phi) * mb;
+  p.pb[idx] = pb;
+  p.cb[idx] = cb;
 }
 
 template <typename T>
@@ -487,8 +541,7 @@ hipError_t launch_adjoint_step(hipStream_t s, const AdjModel& m, const AdjFwd& f
   hipLaunchKernelGGL((k_adj1<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p, drops_n, ndrop, part);
   hipLaunchKernelGGL((k_adj2<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
   hipLaunchKernelGGL((k_adj3<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
-  hipLaunchKernelGGL((k_adj4<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
-  hipLaunchKernelGGL((k_adj5<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, p);
+  hipLaunchKernelGGL((k_adj45<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
   return hipGetLastError();
 }
 
