@@ -389,8 +389,16 @@ __device__ __forceinline__ Nbh2 make_nbh2(int l, int y, const AdjModel& m) {
 template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj45(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
   __shared__ T s_Fxb[ADJ_N2], s_Fyb[ADJ_N2], s_phi[ADJ_N2], s_c[ADJ_N2];
-  __shared__ T s_mu[ADJ_HN], s_X[ADJ_HN], s_mub[ADJ_HN], s_Xb[ADJ_HN];
-  __shared__ T s_gcx[ADJ_HN], s_gcy[ADJ_HN], s_gpx[ADJ_HN], s_gpy[ADJ_HN];  // gradients of phi^n, c^n
+  __shared__ T s_mub[ADJ_HN], s_Xb[ADJ_HN];
+  // the gradients of phi^n, c^n; mu and X, which only K4's update at the tile reads, before the ring pass, occupy
+  // two of them until then (43 KB of LDS per workgroup would leave three workgroups per compute unit, 36 KB four)
+  __shared__ T s_g[4][ADJ_HN];
+  T* const s_gpx = s_g[0];
+  T* const s_gpy = s_g[1];
+  T* const s_gcx = s_g[2];
+  T* const s_gcy = s_g[3];
+  T* const s_mu = s_g[2];
+  T* const s_X = s_g[3];
   const Tile t = make_tile(m, p.pitch);
   const int nbx = (m.nx + ADJ_TILE_X - 1) / ADJ_TILE_X;
   const int b = xcd_block(), by = b / nbx, bx = b - by * nbx;
@@ -419,6 +427,23 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj45(AdjModel m, AdjFwd f, Adj
   }
   stage(s_mu, t, [&](int o, int) { return T(f.mu[o]); });
   stage(s_X, t, [&](int o, int) { return T(f.X[o]); });
+  __syncthreads();
+  const Nbh k = make_nbh(t, m);
+  const Nbh2 k2 = make_nbh2((threadIdx.x / ADJ_TILE_X + 2) * ADJ_W2 + threadIdx.x % ADJ_TILE_X + 2, t.y, m);
+  const int idx = t.y * m.nx + t.x;
+  auto Fxb = [&](int dx, int dy) { return s_Fxb[k2.s(dx, dy)]; };
+  auto Fyb = [&](int dx, int dy) { return s_Fyb[k2.s(dx, dy)]; };
+  T pb = T(0), cb = T(0), fx = T(0), fy = T(0);
+  if (t.valid) {  // K4: F = -phi grad9 mu - grad9 c - c grad9 X (Eq. 14)
+    auto mu = [&](int dx, int dy) { return s_mu[k.s(dx, dy)]; };
+    auto X = [&](int dx, int dy) { return s_X[k.s(dx, dy)]; };
+    fx = Fxb(0, 0);
+    fy = Fyb(0, 0);
+    pb = p.pb[idx];
+    cb = p.cb[idx];
+    pb -= fx * G9x<T>(mu) + fy * G9y<T>(mu);
+    cb += (G9x<T>(Fxb) + G9y_T<T>(k2, Fyb)) - (fx * G9x<T>(X) + fy * G9y<T>(X));
+  }
   __syncthreads();
   // mu_bar, X_bar (Eq. 14 transposed) and the gradients of phi^n, c^n on the tile and its one-node ring
   for (int i = threadIdx.x; i < ADJ_HN; i += ADJ_THREADS) {
@@ -456,18 +481,6 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj45(AdjModel m, AdjFwd f, Adj
     __syncthreads();
   }
   if (!t.valid) return;
-  const Nbh k = make_nbh(t, m);
-  const Nbh2 k2 = make_nbh2((threadIdx.x / ADJ_TILE_X + 2) * ADJ_W2 + threadIdx.x % ADJ_TILE_X + 2, t.y, m);
-  const int idx = t.y * m.nx + t.x;
-  // K4: F = -phi grad9 mu - grad9 c - c grad9 X (Eq. 14)
-  auto Fxb = [&](int dx, int dy) { return s_Fxb[k2.s(dx, dy)]; };
-  auto Fyb = [&](int dx, int dy) { return s_Fyb[k2.s(dx, dy)]; };
-  auto mu = [&](int dx, int dy) { return s_mu[k.s(dx, dy)]; };
-  auto X = [&](int dx, int dy) { return s_X[k.s(dx, dy)]; };
-  const T fx = Fxb(0, 0), fy = Fyb(0, 0);
-  T pb = p.pb[idx], cb = p.cb[idx];
-  pb -= fx * G9x<T>(mu) + fy * G9y<T>(mu);
-  cb += (G9x<T>(Fxb) + G9y_T<T>(k2, Fyb)) - (fx * G9x<T>(X) + fy * G9y<T>(X));
   // K5: mu = a phi + b phi^3 - B(c) lap9 phi - B1 grad9 phi . grad9 c;  X = (B1/2) |grad9 phi|^2 (Eqs. 3, 5)
   const T a = T(m.a), b3 = T(m.b), B0 = T(m.B0), B1 = T(m.B1);
   auto BMu = [&](int dx, int dy) { return (B0 + B1 * s_c[k2.s(dx, dy)]) * s_mub[k.s(dx, dy)]; };
