@@ -273,7 +273,7 @@ int lbm_step_noalloc(const lbm_config* cfg, void* stream, void* const f[2], void
  * differentiable.  Contexts of one lattice (periodic, or with LBM_WALLS_Y), LBM_FP64 or LBM_FP32,
  * LBM_ADV_PAPER (LBM_E_INVAL otherwise).
  * Memory: a checkpoint of the state every `every` steps (9 population planes, phi, c), and for the interval
- * being reversed phi, c and 11 FP64 stage planes of each step, plus 34 planes of one backward step, live
+ * being reversed phi, c and 11 FP64 stage planes of each step, plus 26 planes of one backward step, live
  * in a caller-owned device workspace of lbm_adjoint_bytes bytes (the library allocates nothing); it must stay
  * untouched between the forward and the backward call.  An interval near sqrt(nsteps) keeps it smallest. */
 int lbm_adjoint_bytes(const lbm_ctx* ctx, int64_t nsteps, int32_t every, size_t* bytes);

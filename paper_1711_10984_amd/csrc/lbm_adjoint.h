@@ -21,10 +21,8 @@ struct AdjPlanes {
   int pitch;
   const T *fb1, *pb1, *cb1;  // adjoint of f (9 planes), phi, c at n + 1
   T *fb, *pb, *cb;           // adjoint at n (outputs)
-  // gradient planes of phi^{n+1/2}, c^{n+1/2}
-  T *gphx, *gphy, *gchx, *gchy;
-  // intermediate adjoints
-  T *Mb, *Xhb, *phb, *chb, *Fxb, *Fyb, *mub, *Xb;
+  // intermediate adjoints: of phi^{n+1/2}, c^{n+1/2} (K12 -> K3) and of the force (K3 -> K45)
+  T *phb, *chb, *Fxb, *Fyb;
 };
 
 struct AdjModel {

@@ -9,14 +9,14 @@
 // Held fixed (non-differentiable): the membership of each node in the production disks, the upwind side chosen
 // by the sign of u in Eqs. (16)-(17), and the droplet masks.
 //
-// Four launches per step (K4 and K5 share one), each one stencil layer deep over dense [ny][nx] planes:
-//   K1  gradient planes of phi^{n+1/2}, c^{n+1/2}; adjoint of Eq. (19) (c update, link divergence, production
-//       rate) and of the phi update of Eq. (18) down to the bracket M
-//   K2  adjoint of M (Eq. 18) and of X^{n+1/2} down to phi^{n+1/2}, c^{n+1/2}
-//   K3  adjoint of the advection half-step (Eqs. 16-17), then of streaming and collision (Eqs. 10-13)
-//       and of the velocity with half the force (Eq. 11) down to f^n, F
-//   K4  adjoint of the force (Eq. 14) down to mu_phi, X, phi^n, c^n
-//   K5  adjoint of mu_phi and X (Eqs. 3, 5) down to phi^n, c^n
+// Three launches per step, each one stencil layer deep over dense [ny][nx] planes except where two steps share a
+// launch (on the tile with a ring, see k_adj12 and k_adj45):
+//   K12 (K1, K2)  adjoint of Eq. (19) (c update, link divergence, production rate) and of the phi update of
+//                 Eq. (18) down to the bracket M, then of M (Eq. 18) and of X^{n+1/2} down to phi^{n+1/2}, c^{n+1/2}
+//   K3            adjoint of the advection half-step (Eqs. 16-17), then of streaming and collision (Eqs. 10-13)
+//                 and of the velocity with half the force (Eq. 11) down to f^n, F
+//   K45 (K4, K5)  adjoint of the force (Eq. 14) down to mu_phi, X, phi^n, c^n, then of mu_phi and X (Eqs. 3, 5)
+//                 down to phi^n, c^n
 #pragma once
 #include "lbm_adjoint.h"
 #include "lbm_kernels_impl.h"
@@ -24,7 +24,7 @@
 namespace lbm {
 namespace {
 
-// A block of the kernels K1-K5 covers a tile of ADJ_TILE_X x ADJ_TILE_Y nodes, one wavefront per tile row.
+// A block of the adjoint kernels covers a tile of ADJ_TILE_X x ADJ_TILE_Y nodes, one wavefront per tile row.
 // The planes that a kernel reads across the 3 x 3 neighbourhood are first copied to LDS, the tile with a
 // one-node halo (ADJ_HN values per plane, at most two per thread), so that each value is loaded from memory
 // once per block instead of once per neighbour.
@@ -162,67 +162,193 @@ __device__ int source_count_at(double x, double y, const DropDev* drops, int ndr
   return cnt;
 }
 
+// Kernels that need a stencil's result across the 3 x 3 neighbourhood form it on the tile with a one-node ring,
+// from their inputs on the tile with a two-node ring (ADJ_N2 values per plane).
+constexpr int ADJ_W2 = ADJ_TILE_X + 4, ADJ_N2 = ADJ_W2 * (ADJ_TILE_Y + 4);
+static_assert(ADJ_N2 <= 3 * ADJ_THREADS, "three staged values per thread");
+
+// Neighbourhood of a point in the frame with the two-node ring: index l in that frame, and the mirror signs.
+struct Nbh2 {
+  int l;
+  int sg[3];
+  __device__ int s(int dx, int dy) const { return l + dy * ADJ_W2 + dx; }
+  __device__ int odd(int dy) const { return sg[dy + 1]; }
+};
+
+__device__ __forceinline__ Nbh2 make_nbh2(int l, int y, const AdjModel& m) {
+  Nbh2 k;
+  k.l = l;
+  k.sg[0] = m.walls && y == 0 ? -1 : 1;
+  k.sg[1] = 1;
+  k.sg[2] = m.walls && y == m.ny - 1 ? -1 : 1;
+  return k;
+}
+
+// This block's tile origin (x0, y0).
+__device__ __forceinline__ void tile_origin(const AdjModel& m, int& x0, int& y0) {
+  const int nbx = (m.nx + ADJ_TILE_X - 1) / ADJ_TILE_X;
+  const int b = xcd_block(), by = b / nbx, bx = b - by * nbx;
+  x0 = bx * ADJ_TILE_X;
+  y0 = by * ADJ_TILE_Y;
+}
+
+// Calls put(i, dense offset, pitched offset) for the values of the frame with the two-node ring that this thread
+// stages: periodic images, or with walls the mirrored rows (clamped for lattices of fewer rows than the ring
+// reaches; only ring nodes that are not computed read those).
+template <class F>
+__device__ __forceinline__ void stage2(const AdjModel& m, int pitch, int x0, int y0, F put) {
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj) {
+    const int i = threadIdx.x + jj * ADJ_THREADS;
+    if (i < ADJ_N2) {
+      const int ly = i / ADJ_W2, lx = i - ly * ADJ_W2;
+      const int gx = (x0 + lx - 2 + 2 * m.nx) % m.nx;
+      int gy = y0 + ly - 2;
+      if (m.walls) {
+        gy = gy < 0 ? -1 - gy : gy >= m.ny ? 2 * m.ny - 1 - gy : gy;
+        gy = gy < 0 ? 0 : gy >= m.ny ? m.ny - 1 : gy;
+      } else {
+        gy = (gy + 2 * m.ny) % m.ny;
+      }
+      put(i, gy * m.nx + gx, gy * pitch + gx);
+    }
+  }
+}
+
+// With walls, the ring rows beyond a plate take the values of the boundary row (as a plane read at the mirrored
+// row gives): copy(i, src) for each such entry i of the one-node-ring frame.  Call after the ring pass, followed
+// by a barrier.
+template <class F>
+__device__ __forceinline__ void ring_ghosts(const AdjModel& m, int y0, F copy) {
+  if (!m.walls) return;
+  for (int i = threadIdx.x; i < ADJ_HN; i += ADJ_THREADS) {
+    const int ly = i / ADJ_HX, lx = i - ly * ADJ_HX;
+    const int gy = y0 + ly - 1;
+    if (gy >= 0 && gy < m.ny) continue;
+    copy(i, ((gy < 0 ? 0 : m.ny - 1) - y0 + 1) * ADJ_HX + lx);
+  }
+}
+
+// Transpose of the link divergence Div(D c, X) of Eq. (19) at one node, gathered from the links of its
+// neighbourhood k: kb (the part multiplying k = D c at the node) and Xb (the part multiplying X).
+// Div(k, X)(q) = sum_i W_i (k(q) + k(q + e_i)) (X(q + e_i) - X(q)) / 12, W = 4 on axis links, 1 on diagonals:
+// node r enters as q (all links) and as q + e_i of its neighbour q = r - e_i.
+template <typename T, class CB, class XH, class KD>
+__device__ __forceinline__ void link_adj(CB cb1, XH Xh, KD kD, T& kb, T& Xb) {
+  const int EXs[8] = {1, 0, -1, 0, 1, -1, -1, 1}, EYs[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+  T kb_ax = T(0), kb_dg = T(0), Xb_ax = T(0), Xb_dg = T(0);
+  const T cb0 = cb1(0, 0), Xh0 = Xh(0, 0), k0 = kD(0, 0);
+  for (int i = 0; i < 8; ++i) {
+    const int ex = EXs[i], ey = EYs[i];
+    const T cbm = cb1(-ex, -ey);
+    const T tk = cb0 * (Xh(ex, ey) - Xh0) + cbm * (Xh0 - Xh(-ex, -ey));
+    const T tX = cbm * (kD(-ex, -ey) + k0) - cb0 * (k0 + kD(ex, ey));
+    if (i < 4) {
+      kb_ax += tk;
+      Xb_ax += tX;
+    } else {
+      kb_dg += tk;
+      Xb_dg += tX;
+    }
+  }
+  kb = (T(4) * kb_ax + kb_dg) * cst<T>(1.0 / 12.0);
+  Xb = (T(4) * Xb_ax + Xb_dg) * cst<T>(1.0 / 12.0);
+}
+
+// K1 and K2 in one launch.  K1: the adjoint of Eq. (19) (c update, link divergence, production rate) and of
+// the phi update of Eq. (18) down to the bracket M; K2: the adjoint of M and X^{n+1/2} down to phi^{n+1/2},
+// c^{n+1/2}.  K2 reads K1's M_bar and X^{n+1/2}_bar and the gradients of phi^{n+1/2}, c^{n+1/2} across the 3 x 3
+// neighbourhood: they are formed on the tile with a one-node ring.
 template <typename T>
-__global__ __launch_bounds__(ADJ_THREADS) void k_adj1(AdjModel m, AdjFwd f, AdjPlanes<T> p, const DropDev* drops,
-                                                      int ndrop, double* part) {
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj12(AdjModel m, AdjFwd f, AdjPlanes<T> p, const DropDev* drops,
+                                                       int ndrop, double* part) {
   __shared__ double red[ADJ_THREADS / 64];
-  __shared__ T s_ph[ADJ_HN], s_ch[ADJ_HN], s_pb1[ADJ_HN], s_cb1[ADJ_HN], s_Xh[ADJ_HN];
+  __shared__ T s_ph[ADJ_N2], s_ch[ADJ_N2], s_pb1[ADJ_N2], s_cb1[ADJ_N2], s_Xh[ADJ_N2];
+  __shared__ T s_Mb[ADJ_HN], s_Xhb[ADJ_HN], s_gphx[ADJ_HN], s_gphy[ADJ_HN], s_gchx[ADJ_HN], s_gchy[ADJ_HN];
   const Tile t = make_tile(m, p.pitch);
-  stage(s_ph, t, [&](int o, int) { return T(f.ph[o]); });
-  stage(s_ch, t, [&](int o, int) { return T(f.ch[o]); });
-  stage(s_pb1, t, [&](int o, int) { return p.pb1[o]; });
-  stage(s_cb1, t, [&](int o, int) { return p.cb1[o]; });
-  stage(s_Xh, t, [&](int o, int) { return T(f.Xh[o]); });
+  int x0, y0;
+  tile_origin(m, x0, y0);
+  stage2(m, p.pitch, x0, y0, [&](int i, int o, int) {
+    s_ph[i] = T(f.ph[o]);
+    s_ch[i] = T(f.ch[o]);
+    s_pb1[i] = p.pb1[o];
+    s_cb1[i] = p.cb1[o];
+    s_Xh[i] = T(f.Xh[o]);
+  });
   __syncthreads();
-  double src = 0.0;
-  if (t.valid) {
-    const Nbh k = make_nbh(t, m);
-    const int idx = t.y * m.nx + t.x;
+  const T D = T(m.D), a = T(m.a), Gamma = T(m.Gamma);
+  // on the tile and its one-node ring: M_bar, X^{n+1/2}_bar and the gradients of phi^{n+1/2}, c^{n+1/2}
+  for (int i = threadIdx.x; i < ADJ_HN; i += ADJ_THREADS) {
+    const int ly = i / ADJ_HX, lx = i - ly * ADJ_HX;
+    const int gy = y0 + ly - 1;
+    if (m.walls && (gy < 0 || gy >= m.ny)) continue;  // beyond a plate: copied below
+    const Nbh2 k = make_nbh2((ly + 1) * ADJ_W2 + lx + 1, (gy + m.ny) % m.ny, m);
     auto ph = [&](int dx, int dy) { return s_ph[k.s(dx, dy)]; };
     auto ch = [&](int dx, int dy) { return s_ch[k.s(dx, dy)]; };
-    // gradient planes of phi^{n+1/2}, c^{n+1/2} that K2 reads at neighbouring nodes (those of phi^n, c^n are formed
-    // by K45, and those needed only at the node itself where they are used)
-    p.gphx[idx] = G9x<T>(ph);
-    p.gphy[idx] = G9y<T>(ph);
-    p.gchx[idx] = G9x<T>(ch);
-    p.gchy[idx] = G9y<T>(ch);
-
-    const T D = T(m.D), a = T(m.a);
     auto pb1 = [&](int dx, int dy) { return s_pb1[k.s(dx, dy)]; };
     auto cb1 = [&](int dx, int dy) { return s_cb1[k.s(dx, dy)]; };
     auto Xh = [&](int dx, int dy) { return s_Xh[k.s(dx, dy)]; };
     auto kD = [&](int dx, int dy) { return D * ch(dx, dy); };
+    s_gphx[i] = G9x<T>(ph);
+    s_gphy[i] = G9y<T>(ph);
+    s_gchx[i] = G9x<T>(ch);
+    s_gchy[i] = G9y<T>(ch);
     // phi^{n+1} = phi^{n+1/2} + Gamma lap9(M)  ->  M_bar = Gamma lap9(phi_bar')
-    const T Mb = T(m.Gamma) * L9<T>(pb1);
-    p.Mb[idx] = Mb;
-    p.phb[idx] = pb1(0, 0) + a * Mb;  // the rest of phi_bar^{n+1/2} needs M_bar at the neighbours
+    s_Mb[i] = Gamma * L9<T>(pb1);
+    T kb, Xhb;
+    link_adj<T>(cb1, Xh, kD, kb, Xhb);
+    s_Xhb[i] = Xhb;
+  }
+  __syncthreads();
+  ring_ghosts(m, y0, [&](int i, int src) {
+    s_Mb[i] = s_Mb[src];
+    s_Xhb[i] = s_Xhb[src];
+    s_gphx[i] = s_gphx[src];
+    s_gphy[i] = s_gphy[src];
+    s_gchx[i] = s_gchx[src];
+    s_gchy[i] = s_gchy[src];
+  });
+  __syncthreads();
+  double src = 0.0;
+  if (t.valid) {
+    const Nbh k = make_nbh(t, m);
+    const Nbh2 k2 = make_nbh2((threadIdx.x / ADJ_TILE_X + 2) * ADJ_W2 + threadIdx.x % ADJ_TILE_X + 2, t.y, m);
+    const int idx = t.y * m.nx + t.x;
+    auto ph = [&](int dx, int dy) { return s_ph[k2.s(dx, dy)]; };
+    auto ch = [&](int dx, int dy) { return s_ch[k2.s(dx, dy)]; };
+    auto pb1 = [&](int dx, int dy) { return s_pb1[k2.s(dx, dy)]; };
+    auto cb1 = [&](int dx, int dy) { return s_cb1[k2.s(dx, dy)]; };
+    auto Xh = [&](int dx, int dy) { return s_Xh[k2.s(dx, dy)]; };
+    auto kD = [&](int dx, int dy) { return D * ch(dx, dy); };
+    // K1 at the node
+    const T Mb0 = s_Mb[k.l];
+    T phb = pb1(0, 0) + a * Mb0;
     // c^{n+1} = c^{n+1/2} + D lap9(c^{n+1/2}) + Div(D c^{n+1/2}, X^{n+1/2}) - gamma (c^{n+1/2} - c0) + A(n) count
-    // Div(k, X)(q) = sum_i W_i (k(q) + k(q + e_i)) (X(q + e_i) - X(q)) / 12, W = 4 on axis links, 1 on diagonals:
-    // node r enters as q (all links) and as q + e_i of its neighbour q = r - e_i.
-    const int EXs[8] = {1, 0, -1, 0, 1, -1, -1, 1}, EYs[8] = {0, 1, 0, -1, 1, 1, -1, -1};
-    T kb_ax = T(0), kb_dg = T(0), Xb_ax = T(0), Xb_dg = T(0);
-    const T cb0 = cb1(0, 0), Xh0 = Xh(0, 0), k0 = kD(0, 0);
-    for (int i = 0; i < 8; ++i) {
-      const int ex = EXs[i], ey = EYs[i];
-      const T cbm = cb1(-ex, -ey);
-      const T tk = cb0 * (Xh(ex, ey) - Xh0) + cbm * (Xh0 - Xh(-ex, -ey));
-      const T tX = cbm * (kD(-ex, -ey) + k0) - cb0 * (k0 + kD(ex, ey));
-      if (i < 4) {
-        kb_ax += tk;
-        Xb_ax += tX;
-      } else {
-        kb_dg += tk;
-        Xb_dg += tX;
-      }
-    }
-    const T kb = (T(4) * kb_ax + kb_dg) * cst<T>(1.0 / 12.0);
-    p.Xhb[idx] = (T(4) * Xb_ax + Xb_dg) * cst<T>(1.0 / 12.0);
-    p.chb[idx] = (T(1) - T(m.gamma)) * cb0 + D * L9<T>(cb1) + D * kb;
+    T kb, Xhb_unused;
+    link_adj<T>(cb1, Xh, kD, kb, Xhb_unused);
+    const T cb0 = cb1(0, 0);
+    T chb = (T(1) - T(m.gamma)) * cb0 + D * L9<T>(cb1) + D * kb;
     // d c^{n+1}(r) / d A0 = min(n, t*) count_n(r)
     if (m.ramp != 0.0 && ndrop > 0) {
       const int cnt = source_count_at((double)k.x, (double)k.y, drops, ndrop, m);
       src = (double)cb0 * m.ramp * (double)cnt;
     }
+    // K2: M = a phi^{1/2} + b (phi^n)^3 - B(c^{1/2}) lap9(phi^{1/2}) - B1 grad9 c^{1/2} . grad9 phi^{1/2};
+    // X^{1/2} = (B1/2) |grad9 phi^{1/2}|^2
+    const T B0 = T(m.B0), B1 = T(m.B1), b = T(m.b);
+    auto BM = [&](int dx, int dy) { return (B0 + B1 * ch(dx, dy)) * s_Mb[k.s(dx, dy)]; };
+    auto gchxM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gchx[q] * s_Mb[q]; };
+    auto gchyM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gchy[q] * s_Mb[q]; };
+    auto gphxX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphx[q] * s_Xhb[q]; };
+    auto gphyX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphy[q] * s_Xhb[q]; };
+    auto gphxM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphx[q] * s_Mb[q]; };
+    auto gphyM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphy[q] * s_Mb[q]; };
+    phb = ((phb - L9<T>(BM)) + B1 * (G9x<T>(gchxM) + G9y_T<T>(k, gchyM))) - B1 * (G9x<T>(gphxX) + G9y_T<T>(k, gphyX));
+    chb = (chb - B1 * L9<T>(ph) * Mb0) + B1 * (G9x<T>(gphxM) + G9y_T<T>(k, gphyM));
+    const T ph0 = p.phi[k.p(0, 0, p.pitch)];
+    p.phb[idx] = phb;
+    p.chb[idx] = chb;
+    p.pb[idx] = T(3) * b * (ph0 * ph0) * Mb0;
   }
   // deterministic per-block partial sum of the A0 contribution, added to the block's running total (steps
   // are taken one after another, so each block's total accumulates in a fixed order)
@@ -234,42 +360,6 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj1(AdjModel m, AdjFwd f, AdjP
     for (int w = 0; w < ADJ_THREADS / 64; ++w) s += red[w];
     part[xcd_block()] += s;
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(ADJ_THREADS) void k_adj2(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
-  __shared__ T s_Mb[ADJ_HN], s_ch[ADJ_HN], s_ph[ADJ_HN], s_Xhb[ADJ_HN];
-  __shared__ T s_gchx[ADJ_HN], s_gchy[ADJ_HN], s_gphx[ADJ_HN], s_gphy[ADJ_HN];
-  const Tile t = make_tile(m, p.pitch);
-  stage(s_Mb, t, [&](int o, int) { return p.Mb[o]; });
-  stage(s_ch, t, [&](int o, int) { return T(f.ch[o]); });
-  stage(s_ph, t, [&](int o, int) { return T(f.ph[o]); });
-  stage(s_Xhb, t, [&](int o, int) { return p.Xhb[o]; });
-  stage(s_gchx, t, [&](int o, int) { return p.gchx[o]; });
-  stage(s_gchy, t, [&](int o, int) { return p.gchy[o]; });
-  stage(s_gphx, t, [&](int o, int) { return p.gphx[o]; });
-  stage(s_gphy, t, [&](int o, int) { return p.gphy[o]; });
-  __syncthreads();
-  if (!t.valid) return;
-  const Nbh k = make_nbh(t, m);
-  const int idx = t.y * m.nx + t.x;
-  const T B0 = T(m.B0), B1 = T(m.B1), b = T(m.b);
-  auto ph = [&](int dx, int dy) { return s_ph[k.s(dx, dy)]; };
-  auto BM = [&](int dx, int dy) { const int q = k.s(dx, dy); return (B0 + B1 * s_ch[q]) * s_Mb[q]; };
-  auto gchxM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gchx[q] * s_Mb[q]; };
-  auto gchyM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gchy[q] * s_Mb[q]; };
-  auto gphxX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphx[q] * s_Xhb[q]; };
-  auto gphyX = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphy[q] * s_Xhb[q]; };
-  auto gphxM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphx[q] * s_Mb[q]; };
-  auto gphyM = [&](int dx, int dy) { const int q = k.s(dx, dy); return s_gphy[q] * s_Mb[q]; };
-  // M = a phi^{1/2} + b (phi^n)^3 - B(c^{1/2}) lap9(phi^{1/2}) - B1 grad9 c^{1/2} . grad9 phi^{1/2};
-  // X^{1/2} = (B1/2) |grad9 phi^{1/2}|^2
-  p.phb[idx] = ((p.phb[idx] - L9<T>(BM)) + B1 * (G9x<T>(gchxM) + G9y_T<T>(k, gchyM))) -
-               B1 * (G9x<T>(gphxX) + G9y_T<T>(k, gphyX));
-  const T Mb0 = s_Mb[k.l];
-  p.chb[idx] = (p.chb[idx] - B1 * L9<T>(ph) * Mb0) + B1 * (G9x<T>(gphxM) + G9y_T<T>(k, gphyM));
-  const T ph0 = p.phi[k.p(0, 0, p.pitch)];
-  p.pb[idx] = T(3) * b * (ph0 * ph0) * Mb0;
 }
 
 template <typename T>
@@ -366,26 +456,6 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjP
 // F_bar, phi and c on the tile with a two-node ring.  A ring node takes the values of the node it stands for (its
 // periodic image; with walls, a ring row beyond a plate takes the boundary row's, as a plane read at the mirrored
 // row gives).  Then K4's and K5's updates of phi_bar and c_bar at the tile, in that order.
-constexpr int ADJ_W2 = ADJ_TILE_X + 4, ADJ_N2 = ADJ_W2 * (ADJ_TILE_Y + 4);
-static_assert(ADJ_N2 <= 3 * ADJ_THREADS, "three staged values per thread");
-
-// Neighbourhood of a point in the frame with the two-node ring: index l in that frame, and the mirror signs.
-struct Nbh2 {
-  int l;
-  int sg[3];
-  __device__ int s(int dx, int dy) const { return l + dy * ADJ_W2 + dx; }
-  __device__ int odd(int dy) const { return sg[dy + 1]; }
-};
-
-__device__ __forceinline__ Nbh2 make_nbh2(int l, int y, const AdjModel& m) {
-  Nbh2 k;
-  k.l = l;
-  k.sg[0] = m.walls && y == 0 ? -1 : 1;
-  k.sg[1] = 1;
-  k.sg[2] = m.walls && y == m.ny - 1 ? -1 : 1;
-  return k;
-}
-
 template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj45(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
   __shared__ T s_Fxb[ADJ_N2], s_Fyb[ADJ_N2], s_phi[ADJ_N2], s_c[ADJ_N2];
@@ -400,31 +470,14 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj45(AdjModel m, AdjFwd f, Adj
   T* const s_mu = s_g[2];
   T* const s_X = s_g[3];
   const Tile t = make_tile(m, p.pitch);
-  const int nbx = (m.nx + ADJ_TILE_X - 1) / ADJ_TILE_X;
-  const int b = xcd_block(), by = b / nbx, bx = b - by * nbx;
-  const int x0 = bx * ADJ_TILE_X, y0 = by * ADJ_TILE_Y;
-  // the frame with the two-node ring: periodic images, or with walls the mirrored rows (clamped for lattices of
-  // fewer rows than the ring reaches; only ring nodes that are not computed read those)
-#pragma unroll
-  for (int jj = 0; jj < 3; ++jj) {
-    const int i = threadIdx.x + jj * ADJ_THREADS;
-    if (i < ADJ_N2) {
-      const int ly = i / ADJ_W2, lx = i - ly * ADJ_W2;
-      const int gx = (x0 + lx - 2 + 2 * m.nx) % m.nx;
-      int gy = y0 + ly - 2;
-      if (m.walls) {
-        gy = gy < 0 ? -1 - gy : gy >= m.ny ? 2 * m.ny - 1 - gy : gy;
-        gy = gy < 0 ? 0 : gy >= m.ny ? m.ny - 1 : gy;
-      } else {
-        gy = (gy + 2 * m.ny) % m.ny;
-      }
-      const int o = gy * m.nx + gx, q = gy * p.pitch + gx;
-      s_Fxb[i] = p.Fxb[o];
-      s_Fyb[i] = p.Fyb[o];
-      s_phi[i] = p.phi[q];
-      s_c[i] = p.c[q];
-    }
-  }
+  int x0, y0;
+  tile_origin(m, x0, y0);
+  stage2(m, p.pitch, x0, y0, [&](int i, int o, int q) {
+    s_Fxb[i] = p.Fxb[o];
+    s_Fyb[i] = p.Fyb[o];
+    s_phi[i] = p.phi[q];
+    s_c[i] = p.c[q];
+  });
   stage(s_mu, t, [&](int o, int) { return T(f.mu[o]); });
   stage(s_X, t, [&](int o, int) { return T(f.X[o]); });
   __syncthreads();
@@ -465,21 +518,15 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj45(AdjModel m, AdjFwd f, Adj
     s_gcy[i] = G9y<T>(cc);
   }
   __syncthreads();
-  if (m.walls) {
-    for (int i = threadIdx.x; i < ADJ_HN; i += ADJ_THREADS) {
-      const int ly = i / ADJ_HX, lx = i - ly * ADJ_HX;
-      const int gy = y0 + ly - 1;
-      if (gy >= 0 && gy < m.ny) continue;
-      const int src = ((gy < 0 ? 0 : m.ny - 1) - y0 + 1) * ADJ_HX + lx;
-      s_mub[i] = s_mub[src];
-      s_Xb[i] = s_Xb[src];
-      s_gpx[i] = s_gpx[src];
-      s_gpy[i] = s_gpy[src];
-      s_gcx[i] = s_gcx[src];
-      s_gcy[i] = s_gcy[src];
-    }
-    __syncthreads();
-  }
+  ring_ghosts(m, y0, [&](int i, int src) {
+    s_mub[i] = s_mub[src];
+    s_Xb[i] = s_Xb[src];
+    s_gpx[i] = s_gpx[src];
+    s_gpy[i] = s_gpy[src];
+    s_gcx[i] = s_gcx[src];
+    s_gcy[i] = s_gcy[src];
+  });
+  __syncthreads();
   if (!t.valid) return;
   // K5: mu = a phi + b phi^3 - B(c) lap9 phi - B1 grad9 phi . grad9 c;  X = (B1/2) |grad9 phi|^2 (Eqs. 3, 5)
   const T a = T(m.a), b3 = T(m.b), B0 = T(m.B0), B1 = T(m.B1);
@@ -551,8 +598,7 @@ template <typename T>
 hipError_t launch_adjoint_step(hipStream_t s, const AdjModel& m, const AdjFwd& f, const AdjPlanes<T>& p,
                                const DropDev* drops_n, int ndrop, double* part) {
   const int nb = adj_blocks(m.nx, m.ny);
-  hipLaunchKernelGGL((k_adj1<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p, drops_n, ndrop, part);
-  hipLaunchKernelGGL((k_adj2<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
+  hipLaunchKernelGGL((k_adj12<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p, drops_n, ndrop, part);
   hipLaunchKernelGGL((k_adj3<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
   hipLaunchKernelGGL((k_adj45<T>), dim3(nb), dim3(ADJ_THREADS), 0, s, m, f, p);
   return hipGetLastError();

@@ -1314,7 +1314,7 @@ struct AdjLayout {
   size_t off_cp = 0, off_seg = 0, off_final = 0, off_fwd = 0, off_adj = 0, off_part = 0, total = 0;
 };
 
-constexpr int ADJ_TMP_PLANES = 12;  // gradient planes and intermediate adjoints of one backward step
+constexpr int ADJ_TMP_PLANES = 4;  // intermediate adjoints of one backward step
 // The adjoint step reads the first ADJ_FWD_PLANES stage planes of the forward step (mu .. X^{n+1/2}), and the
 // recompute exports only those: the record of an interval holds ADJ_FWD_PLANES planes per step.
 constexpr int ADJ_FWD_PLANES = ADJ_EXPORT_PLANES;
@@ -1484,7 +1484,7 @@ int adj_backward(lbm_ctx* c, const AdjLayout& A, char* w, double* dA0, double* d
     p.fb = out;
     p.pb = out + 9 * M;
     p.cb = out + 10 * M;
-    T** t[] = {&p.gphx, &p.gphy, &p.gchx, &p.gchy, &p.Mb, &p.Xhb, &p.phb, &p.chb, &p.Fxb, &p.Fyb, &p.mub, &p.Xb};
+    T** t[] = {&p.phb, &p.chb, &p.Fxb, &p.Fyb};
     static_assert(sizeof(t) / sizeof(t[0]) == ADJ_TMP_PLANES, "temporary planes");
     for (int i = 0; i < ADJ_TMP_PLANES; ++i) *t[i] = tmp + (size_t)i * M;
     return p;
