@@ -452,10 +452,11 @@ __global__ __launch_bounds__(ADJ_THREADS) void k_adj3(AdjModel m, AdjFwd f, AdjP
 }
 
 // K4 and K5 in one launch.  The adjoint of the force (K4) gives mu_bar and X_bar, which the adjoint of mu_phi and
-// X (K5) reads at the 3 x 3 neighbourhood: they are computed on the tile with a one-node ring and kept in LDS, from
-// F_bar, phi and c on the tile with a two-node ring.  A ring node takes the values of the node it stands for (its
-// periodic image; with walls, a ring row beyond a plate takes the boundary row's, as a plane read at the mirrored
-// row gives).  Then K4's and K5's updates of phi_bar and c_bar at the tile, in that order.
+// X (K5) reads at the 3 x 3 neighbourhood, as it reads the gradients of phi^n, c^n: these are computed on the tile
+// with a one-node ring and kept in LDS, from F_bar, phi and c on the tile with a two-node ring.  A ring node takes
+// the values of the node it stands for (its periodic image; with walls, a ring row beyond a plate takes the
+// boundary row's, as a plane read at the mirrored row gives).  K4's update of phi_bar and c_bar at the tile comes
+// first, then K5's.
 template <typename T>
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj45(AdjModel m, AdjFwd f, AdjPlanes<T> p) {
   __shared__ T s_Fxb[ADJ_N2], s_Fyb[ADJ_N2], s_phi[ADJ_N2], s_c[ADJ_N2];
