@@ -15,7 +15,7 @@ membership, the upwind sides and the droplet masks fixed; a perturbation of 1e-6
   differences, on all three paths;
 * the same on a 70 x 37 lattice, periodic and between plates, whose sides are not multiples of the adjoint
   kernels' tiles;
-* FP32 adjoint against the FP64 one; the torch.autograd wrapper; the state is restored and a second
+* FP32 adjoint against the FP64 one, periodic and between plates; the torch.autograd wrapper; the state is restored and a second
   backward pass repeats the first bit for bit; the checkpoint interval and the kernel path leave the gradients
   unchanged bit for bit.
 """
@@ -213,6 +213,21 @@ def test_fp32_adjoint_tracks_fp64():
     s32.close()
     rel = float(np.linalg.norm(dc32 - dc64) / np.linalg.norm(dc64))
     print("fp32 vs fp64: J", J32, J64, "dA0", dA32, dA64, "dJ/dpsi relative L2", rel)
+    assert abs(J32 - J64) < 1e-3
+    assert abs(dA32 - dA64) <= 1e-2 * abs(dA64)
+    assert rel < 1e-2
+
+
+def test_fp32_adjoint_tracks_fp64_between_plates():
+    """The FP32 adjoint between plates (the mirror signs and the ring rows beyond a plate in FP32) against the FP64
+    one on the near-wall workload, with the bounds of the periodic FP32 check."""
+    w = _near_wall_workload()
+    s64, J64, dA64, dc64 = adjoint(w, 200, 50, precision=0)
+    s64.close()
+    s32, J32, dA32, dc32 = adjoint(w, 200, 50, precision=1)
+    s32.close()
+    rel = float(np.linalg.norm(dc32 - dc64) / np.linalg.norm(dc64))
+    print("walls, fp32 vs fp64: J", J32, J64, "dA0", dA32, dA64, "dJ/dpsi relative L2", rel)
     assert abs(J32 - J64) < 1e-3
     assert abs(dA32 - dA64) <= 1e-2 * abs(dA64)
     assert rel < 1e-2
