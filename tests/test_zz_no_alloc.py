@@ -21,26 +21,33 @@ def _lbm():
 
 def _stored_pops(f_pre, precision, n0=1.0):
     """The documented device layout of the populations: f*_i(r) = f_i(r + e_i) (periodic), FP64 as is, FP32 the
-    deviation f* - (float)(w_i n0) rounded to float."""
+    deviation f* - (float)(w_i n0) rounded to float, FP16 the half of (float)f* - (float)(w_i n0)."""
     fs = np.stack([np.roll(f_pre[i], (-EY[i], -EX[i]), axis=(0, 1)) for i in range(9)])
     if precision == 0:
         return np.ascontiguousarray(fs)
+    if precision == 2:
+        wn32 = np.float32(WT * n0)[:, None, None]
+        return np.ascontiguousarray((fs.astype(np.float32) - wn32).astype(np.float16))
     wn = np.float32(WT * n0).astype(np.float64)[:, None, None]
     return np.ascontiguousarray((fs - wn).astype(np.float32))
 
 
 def _pre_collision(stored, precision, n0=1.0):
-    fs = stored.astype(np.float64)
-    if precision != 0:
-        fs = fs + np.float32(WT * n0).astype(np.float64)[:, None, None]
+    if precision == 2:  # widened in float, as the library reads FP16 storage back
+        fs = (stored.astype(np.float32) + np.float32(WT * n0)[:, None, None]).astype(np.float64)
+    else:
+        fs = stored.astype(np.float64)
+        if precision != 0:
+            fs = fs + np.float32(WT * n0).astype(np.float64)[:, None, None]
     return np.stack([np.roll(fs[i], (EY[i], EX[i]), axis=(0, 1)) for i in range(9)])
 
 
 def _noalloc_run(torch, lbm, w, f_pre, drops, precision, nsteps):
     dt = torch.float64 if precision == 0 else torch.float32
+    ft = torch.float16 if precision == 2 else dt
     npdt = np.float64 if precision == 0 else np.float32
     dev = torch.device("cuda:0")
-    f = [torch.from_numpy(_stored_pops(f_pre, precision)).to(dev), torch.zeros((9, w.ny, w.nx), dtype=dt, device=dev)]
+    f = [torch.from_numpy(_stored_pops(f_pre, precision)).to(dev), torch.zeros((9, w.ny, w.nx), dtype=ft, device=dev)]
     phi = [torch.from_numpy(w.phi0.astype(npdt)).to(dev), torch.zeros((w.ny, w.nx), dtype=dt, device=dev)]
     c = [torch.from_numpy(w.c0.astype(npdt)).to(dev), torch.zeros((w.ny, w.nx), dtype=dt, device=dev)]
     table = (lbm.lbm_droplet * len(drops))(*[lbm.make_droplet(d) for d in drops])
@@ -60,7 +67,7 @@ def _noalloc_run(torch, lbm, w, f_pre, drops, precision, nsteps):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_noalloc_equals_lbm_step_on_two_calls_in_a_row(precision):
     import torch
     lbm = _lbm()
